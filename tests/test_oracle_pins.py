@@ -1,0 +1,341 @@
+"""Pins for the CPU oracle: it is checked against things other than itself.
+
+* brute-force enumeration of all simple paths (definitions of d, sigma, Eq.2,
+  Eq.3, DAG(s) via the last arcs of shortest paths, delta_s.);
+* a library routine (scipy's Dijkstra) for distances on mid-size graphs;
+* closed forms on paths, stars, cycles, complete graphs and grids;
+* the Eq.2/Eq.3 triple sum over (s, v, t), independent of Alg 1;
+* an edge-count invariant from a forward recurrence, independent of Alg 1;
+* a hand-derived worked example with incremental updates (tests/golden);
+* sigma overflow exactly where C(68,34) passes 2^64.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from brute import brute
+from paper_1311_2147_amd import workloads as W
+
+INF = oracle.INF
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _bc_close(got, want, tol=1e-10):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray([float(x) for x in want], dtype=np.float64)
+    assert got.shape == want.shape
+    err = np.abs(got - want) / np.maximum(np.abs(want), 1.0)
+    assert err.max(initial=0.0) <= tol, (got, want)
+
+
+# ---------------------------------------------------------------- brute force
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("directed", [True, False])
+def test_oracle_matches_brute_force(seed, directed):
+    n = 6 + seed % 3
+    g = W.random_small(n, 0.45 if directed else 0.5, 3, seed=1000 + seed, directed=directed)
+    if g.m == 0:
+        pytest.skip("empty draw")
+    ref = brute(g)
+    got = oracle.brandes(g)
+    for s in range(n):
+        for t in range(n):
+            want_d = ref["D"][s][t]
+            assert got["D"][s, t] == (INF if want_d is None else want_d), (s, t)
+            assert int(got["sigma"][s, t]) == ref["sigma"][s][t], (s, t)
+    _bc_close(got["bc"], ref["bc"])
+    for s in range(n):
+        one = oracle.source(g, s)
+        assert set(zip(one["dag_a"].tolist(), one["dag_b"].tolist())) == ref["dag"][s]
+        _bc_close(one["delta"], ref["delta"][s])
+
+
+def test_oracle_handles_unreachable_and_isolated():
+    # 0 -> 1 -> 2, vertex 3 isolated, 4 -> 2
+    g = W.Graph(5, True, np.array([0, 1, 4], np.int32), np.array([1, 2, 2], np.int32), np.array([1, 1, 1]))
+    ref = brute(g)
+    got = oracle.brandes(g)
+    assert got["D"][3, 0] == INF and int(got["sigma"][3, 0]) == 0
+    assert got["D"][3, 3] == 0 and int(got["sigma"][3, 3]) == 1
+    _bc_close(got["bc"], ref["bc"])
+
+
+# ------------------------------------------------------------ library routine
+
+
+@pytest.mark.parametrize("directed", [True, False])
+def test_distances_match_scipy_dijkstra(directed):
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+
+    n = 150
+    g = W.random_small(n, 0.04, 20, seed=77, directed=directed)
+    a, b, w = g.arcs()
+    mat = csr_matrix((w.astype(np.float64), (a, b)), shape=(n, n))
+    ref = shortest_path(mat, method="D", directed=True)
+    got = oracle.brandes(g)["D"]
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, got != INF)
+    assert np.array_equal(ref[fin].astype(np.int64), got[fin])
+
+
+# --------------------------------------------------------------- closed forms
+
+
+@pytest.mark.parametrize("n", [2, 5, 10, 17])
+def test_undirected_path(n):
+    got = oracle.brandes(W.path_graph(n, c=3))
+    i = np.arange(n)
+    _bc_close(got["bc"], 2 * i * (n - 1 - i))
+    assert np.array_equal(got["D"], 3 * np.abs(i[:, None] - i[None, :]))
+    assert np.all(got["sigma"] == 1)
+
+
+@pytest.mark.parametrize("n", [3, 8])
+def test_directed_path(n):
+    got = oracle.brandes(W.path_graph(n, directed=True))
+    i = np.arange(n)
+    _bc_close(got["bc"], i * (n - 1 - i))
+
+
+@pytest.mark.parametrize("n", [3, 6, 11])
+def test_star(n):
+    got = oracle.brandes(W.star_graph(n, c=2))
+    want = np.zeros(n)
+    want[0] = (n - 1) * (n - 2)
+    _bc_close(got["bc"], want)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 6])
+def test_odd_cycle(k):
+    n = 2 * k + 1
+    got = oracle.brandes(W.cycle_graph(n, c=5))
+    _bc_close(got["bc"], np.full(n, k * (k - 1)))
+    i = np.arange(n)
+    diff = np.abs(i[:, None] - i[None, :])
+    assert np.array_equal(got["D"], 5 * np.minimum(diff, n - diff))
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 8])
+def test_even_cycle(k):
+    n = 2 * k
+    got = oracle.brandes(W.cycle_graph(n))
+    _bc_close(got["bc"], np.full(n, (k - 1) ** 2))
+    # antipodal pairs have exactly two shortest paths, all others one
+    i = np.arange(n)
+    anti = (np.abs(i[:, None] - i[None, :]) == k)
+    assert np.all(got["sigma"][anti] == 2) and np.all(got["sigma"][~anti] == 1)
+
+
+@pytest.mark.parametrize("n", [3, 7, 12])
+def test_directed_cycle(n):
+    got = oracle.brandes(W.cycle_graph(n, directed=True))
+    _bc_close(got["bc"], np.full(n, (n - 1) * (n - 2) / 2))
+
+
+@pytest.mark.parametrize("n", [4, 9])
+def test_complete_equal_weights(n):
+    got = oracle.brandes(W.complete_graph_equal(n, c=4))
+    _bc_close(got["bc"], np.zeros(n))
+    assert np.all(got["sigma"] == 1)
+
+
+@pytest.mark.parametrize("r,c", [(3, 4), (6, 6), (10, 13)])
+def test_grid_path_counts_are_binomials(r, c):
+    got = oracle.brandes(W.grid_graph(r, c))
+    for i in range(r):
+        for j in range(c):
+            assert int(got["sigma"][0, i * c + j]) == math.comb(i + j, i)
+            assert got["D"][0, i * c + j] == i + j
+
+
+def test_sigma_overflow_at_35x35_grid_but_not_34x34():
+    g34 = W.grid_graph(34, 34)
+    s = oracle.source(g34, 0)
+    assert int(s["sigma"][34 * 34 - 1]) == math.comb(66, 33)
+    with pytest.raises(oracle.SigmaOverflow):
+        oracle.source(W.grid_graph(35, 35), 0)
+    with pytest.raises(oracle.SigmaOverflow):
+        oracle.brandes(W.grid_graph(35, 35), rows=False)
+
+
+# ------------------------------------------------ independent recomputations
+
+
+def _triple_sum_bc(D, S):
+    """Eq.2 + Eq.3 directly: sum over s != v != t of sigma_sv*sigma_vt/sigma_st
+    whenever d(s,v) + d(v,t) = d(s,t) (all finite)."""
+    n = D.shape[0]
+    fin = D != INF
+    Sf = S.astype(np.float64)
+    bc = np.zeros(n)
+    for v in range(n):
+        ok = fin[:, v][:, None] & fin[v, :][None, :] & fin
+        on = ok & (np.where(ok, D[:, v][:, None] + D[v, :][None, :], -1) == D)
+        on[v, :] = False
+        on[:, v] = False
+        np.fill_diagonal(on, False)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            contrib = np.where(on, Sf[:, v][:, None] * Sf[v, :][None, :] / Sf, 0.0)
+        bc[v] = contrib.sum()
+    return bc
+
+
+@pytest.mark.parametrize("directed,seed", [(True, 1), (False, 2), (True, 3)])
+def test_bc_matches_eq2_eq3_triple_sum(directed, seed):
+    g = W.random_small(60, 0.08, 4, seed=seed, directed=directed)
+    got = oracle.brandes(g)
+    _bc_close(got["bc"], _triple_sum_bc(got["D"], got["sigma"]))
+
+
+def test_bc_total_matches_edge_count_invariant():
+    """sum_v BC(v) = sum_{s != t, sigma_st > 0} (H_st/sigma_st - 1), where H_st is
+    the number of arcs summed over all shortest s-t paths, from the forward
+    recurrence H_st = sum_{a in P_s(t)} (H_sa + sigma_sa)."""
+    g = W.random_small(40, 0.1, 3, seed=9, directed=True)
+    got = oracle.brandes(g)
+    D, S = got["D"], got["sigma"].astype(object)
+    a_, b_, w_ = (x.tolist() for x in g.arcs())
+    total = Fraction(0)
+    n = g.n
+    for s in range(n):
+        order = sorted((t for t in range(n) if D[s, t] != INF), key=lambda t: D[s, t])
+        H = {s: 0}
+        for t in order:
+            if t == s:
+                continue
+            H[t] = sum(H[a] + int(S[s, a]) for a, b, w in zip(a_, b_, w_)
+                       if b == t and D[s, a] != INF and D[s, a] + w == D[s, t])
+            total += Fraction(H[t], int(S[s, t])) - 1
+    assert abs(float(total) - got["bc"].sum()) <= 1e-10 * max(1.0, float(total))
+
+
+def test_estar_is_arcs_with_weight_equal_distance():
+    """E* (arcs on some shortest path, the union of DAG(s)) equals the arcs whose
+    weight is their own distance."""
+    for directed, seed in [(True, 5), (False, 6)]:
+        g = W.random_small(40, 0.12, 6, seed=seed, directed=directed)
+        got = oracle.brandes(g)
+        es = oracle.estar_arcs(g)
+        a, b, w = g.arcs()
+        by_w = {(int(x), int(y), int(z)) for x, y, z in zip(a, b, w) if got["D"][x, y] == z}
+        assert es == by_w
+        union = set()
+        for s in range(g.n):
+            one = oracle.source(g, s)
+            union |= set(zip(one["dag_a"].tolist(), one["dag_b"].tolist()))
+        assert {(x, y) for x, y, _ in es} == union
+
+
+def test_result_independent_of_thread_count():
+    g = W.random_small(120, 0.05, 9, seed=4, directed=True)
+    a = oracle.brandes(g, threads=1)
+    b = oracle.brandes(g, threads=5)
+    assert np.array_equal(a["bc"], b["bc"])
+    assert np.array_equal(a["D"], b["D"]) and np.array_equal(a["sigma"], b["sigma"])
+
+
+def test_rows_match_full():
+    g = W.random_small(80, 0.06, 9, seed=12, directed=True)
+    full = oracle.brandes(g)
+    src = [0, 5, 79, 33]
+    r = oracle.rows(g, src, threads=3)
+    for i, s in enumerate(src):
+        assert np.array_equal(r["D"][i], full["D"][s])
+        assert np.array_equal(r["sigma"][i], full["sigma"][s])
+        one = oracle.source(g, s)
+        assert np.array_equal(r["delta"][i], one["delta"])
+
+
+# ---------------------------------------------------------------- validation
+
+
+@pytest.mark.parametrize("src,dst,w,code", [
+    ([0], [0], [1], -2),
+    ([0, 0], [1, 1], [1, 2], -4),
+    ([0], [1], [0], -3),
+    ([0], [7], [1], -1),
+])
+def test_oracle_rejects_bad_graphs(src, dst, w, code):
+    g = W.Graph(3, True, np.array(src, np.int32), np.array(dst, np.int32), np.array(w))
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.brandes(g)
+    assert e.value.code == code
+
+
+def test_undirected_duplicate_in_either_orientation_rejected():
+    g = W.Graph(3, False, np.array([0, 1], np.int32), np.array([1, 0], np.int32), np.array([1, 1]))
+    with pytest.raises(oracle.OracleError):
+        oracle.brandes(g)
+
+
+# ----------------------------------------------------- worked example (golden)
+
+
+def _parse(x):
+    if x == "I":
+        return INF
+    if isinstance(x, str):
+        return Fraction(x)
+    return x
+
+
+def test_golden_diamond_sequence():
+    with open(os.path.join(GOLDEN, "diamond_updates.json")) as f:
+        gold = json.load(f)
+    e = np.asarray(gold["edges"], dtype=np.int64)
+    g = W.Graph(gold["n"], gold["directed"], e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2])
+    for step in gold["steps"]:
+        if step["update"] is not None:
+            u = step["update"]
+            up = (W.Update("edge", u=u["u"], v=u["v"], w=u["w"]) if u["kind"] == "edge"
+                  else W.Update("vertex", v=u["v"], edges=[tuple(x) for x in u["edges"]]))
+            g = W.apply_update(g, up)
+        got = oracle.brandes(g)
+        _bc_close(got["bc"], [_parse(x) for x in step["bc"]])
+        if "D" in step:
+            assert got["D"].tolist() == [[_parse(x) for x in row] for row in step["D"]]
+            assert got["sigma"].astype(np.int64).tolist() == step["sigma"]
+        ref = brute(g)
+        _bc_close(got["bc"], ref["bc"])
+
+
+# ------------------------------------------------------ incremental special cases
+
+
+def test_nonimproving_weight_changes_nothing_but_the_weight():
+    """w' > d(u,v): by Lemma 2 case 1 every pair keeps d and sigma, so BC is unchanged."""
+    g = W.random_small(30, 0.15, 5, seed=21, directed=True)
+    base = oracle.brandes(g)
+    # find an arc whose weight exceeds its distance and lower it a little, staying above
+    a, b, w = g.src, g.dst, g.w
+    for i in range(g.m):
+        if w[i] > base["D"][a[i], b[i]] + 1:
+            g2 = g.copy()
+            g2.w[i] = base["D"][a[i], b[i]] + 1
+            after = oracle.brandes(g2)
+            assert np.array_equal(after["D"], base["D"]) and np.array_equal(after["sigma"], base["sigma"])
+            _bc_close(after["bc"], base["bc"])
+            return
+    pytest.skip("no non-shortest arc in this draw")
+
+
+@pytest.mark.parametrize("k", [3, 4, 7])
+def test_closing_a_path_into_a_cycle(k):
+    """Inserting {0, n-1} into the unit path P_n moves BC from the path closed
+    form to the cycle closed form."""
+    for n in (2 * k, 2 * k + 1):
+        p = W.path_graph(n)
+        _bc_close(oracle.brandes(p)["bc"], 2 * np.arange(n) * (n - 1 - np.arange(n)))
+        c = W.apply_update(p, W.Update("edge", u=0, v=n - 1, w=1))
+        want = (k - 1) ** 2 if n == 2 * k else k * (k - 1)
+        _bc_close(oracle.brandes(c)["bc"], np.full(n, want))

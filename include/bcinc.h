@@ -1,0 +1,194 @@
+/*
+ * bcinc -- incremental betweenness centrality on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libbcinc.so.  Every call takes plain host or device pointers and
+ * sizes; no framework types cross this boundary.  The method is the
+ * incremental update of Nasre, Pontecorvi and Ramachandran, "Betweenness
+ * Centrality -- Incremental and Faster" (arXiv:1311.2147):
+ *
+ *   - an incremental edge update lowers the weight of an existing arc or
+ *     inserts a missing one (Section 1, problem statement);
+ *   - a vertex update does that on any subset of the arcs into and out of
+ *     one vertex v (Section 4);
+ *   - after each update the library holds, for every pair (s,t), the distance
+ *     d(s,t) and the shortest-path count sigma_st (Lemma 2 for edges, Lemma 4
+ *     for vertex updates, In then Out on the reverse graph), the SSSP DAG of
+ *     every source implicitly as the predicate of Eq.1 over E* (the arcs on
+ *     some shortest path, Section 1), and BC(v) of Eq.3 updated by the
+ *     difference of the Brandes dependencies (Eq.4, Alg 1) of every affected
+ *     source (Alg 3).
+ *
+ * Conventions shared by every call:
+ *   - Vertices are 0..n-1.  Weights are positive integers below 2^31-1.
+ *   - Directed graphs take arcs (a,b).  Undirected graphs take each edge once
+ *     and are handled as their directed double G_D (Section 3, undirected
+ *     graphs), so BC counts ordered pairs (twice the unordered convention).
+ *   - Unreachable pairs have distance INT64_MAX and sigma 0 at this boundary;
+ *     they contribute nothing to BC.
+ *   - Device state per graph is D (int32, n x n, row-major) and sigma (uint64,
+ *     n x n): 12 bytes per pair.  A finite distance that would reach 2^31-1
+ *     raises BC_ERR_DIST_OVERFLOW; a path count above 2^64-1 raises
+ *     BC_ERR_SIGMA_OVERFLOW.  Both are sticky: the graph answers with that
+ *     error until bc_recompute or bc_free_graph.
+ *   - Calls on one context come from one host thread.  Work is ordered on the
+ *     context's stream; device-side errors surface at the next synchronising
+ *     call (bc_sync, bc_scores, bc_get_*, bc_wait).
+ *   - A call that fails validation leaves every state unchanged.
+ */
+#ifndef BCINC_H
+#define BCINC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bc_status;
+
+enum {
+    BC_OK = 0,
+    BC_ERR_INVALID_ARG = -1,     /* null pointer, n <= 0, id out of range, ... */
+    BC_ERR_SELF_LOOP = -2,       /* arc (a,a) */
+    BC_ERR_BAD_WEIGHT = -3,      /* w <= 0 or w >= 2^31-1 */
+    BC_ERR_DUPLICATE_EDGE = -4,  /* repeated arc at load or inside one vertex update */
+    BC_ERR_NOT_INCIDENT = -5,    /* vertex-update edge not touching v */
+    BC_ERR_NOT_INCREMENTAL = -6, /* new weight >= current weight (Lemma 2 needs a strict decrease) */
+    BC_ERR_ADMISSION = -7,       /* state would exceed the context's memory budget */
+    BC_ERR_CAPACITY = -8,        /* arena, arc or E* capacity exceeded */
+    BC_ERR_SIGMA_OVERFLOW = -9,  /* sticky: a path count passed 2^64-1 */
+    BC_ERR_DIST_OVERFLOW = -10,  /* sticky: a finite distance reached 2^31-1 */
+    BC_ERR_HIP = -11,            /* HIP runtime error; text in bc_last_error */
+    BC_ERR_NO_DEVICE = -12,      /* no usable gfx950 device */
+    BC_ERR_ESTAR_CAPACITY = -13  /* sticky: E* outgrew its capacity */
+};
+
+typedef struct bc_ctx bc_ctx;
+typedef int32_t bc_graph_id;
+
+typedef struct {
+    int32_t device;         /* HIP device ordinal */
+    int32_t flags;          /* reserved, 0 */
+    void *stream;           /* hipStream_t to order all work on; NULL: the library makes one */
+    void *scratch;          /* device buffer for per-workgroup work areas (caller owns it) */
+    uint64_t scratch_bytes; /* its size; see bc_scratch_bytes */
+    uint64_t memory_budget; /* admission limit for the sum of graph arenas, 0 = none */
+    int32_t slots;          /* persistent workgroups of the per-source kernel, 0 = one per CU */
+    int32_t block;          /* threads per workgroup of the per-source kernel, 0 = 1024 */
+} bc_config;
+
+typedef struct {
+    int32_t a, b; /* arc (a,b); for a vertex update one of them is v */
+    int64_t w;    /* new weight */
+} bc_edge;
+
+/* Sizes (bytes) the caller allocates in device memory. */
+uint64_t bc_graph_bytes(int32_t n, int64_t arc_capacity, int64_t estar_capacity);
+uint64_t bc_scratch_bytes(int32_t n_max, int32_t slots);
+
+/* Creates a context on cfg->device.  The scratch buffer must stay alive and
+ * unused by the caller until bc_destroy.  Returns BC_ERR_NO_DEVICE when the
+ * device is missing or is not gfx950. */
+bc_status bc_create(bc_ctx **out, const bc_config *cfg);
+bc_status bc_destroy(bc_ctx *ctx);
+
+/* Loads a graph and computes its initial state with a static Brandes pass on
+ * the GPU (the paper assumes BC and every DAG are available before the first
+ * update: Section 1, and Alg 7 of the appendix).
+ *   src, dst, w: host arrays of m arcs (edges when undirected), copied in;
+ *     the caller keeps ownership.
+ *   arc_capacity: most arcs (of G_D) the graph may ever hold, >= its arc count.
+ *   estar_capacity: most arcs E* may hold (0 = arc_capacity).
+ *   arena: caller-allocated device memory of bc_graph_bytes(...) bytes or
+ *     more, 256-byte aligned, owned by the caller, untouched by it until
+ *     bc_free_graph.
+ * Validation: ids in range, no self-loops (BC_ERR_SELF_LOOP), no repeated
+ * arcs (BC_ERR_DUPLICATE_EDGE), weights in [1, 2^31-2] (BC_ERR_BAD_WEIGHT),
+ * arena size (BC_ERR_CAPACITY), budget (BC_ERR_ADMISSION).  Asynchronous
+ * after validation. */
+bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                        const int64_t *w, int32_t directed, int64_t arc_capacity, int64_t estar_capacity,
+                        void *arena, uint64_t arena_bytes, bc_graph_id *out);
+bc_status bc_free_graph(bc_ctx *ctx, bc_graph_id g);
+
+/* Incremental edge update (Section 3, Alg 3 with Lemma 2 and Alg 2): arc
+ * (u,v) of a directed graph, or edge {u,v} of an undirected one (two arc
+ * updates, Section 3 undirected paragraph), gets weight w.  w must be below
+ * the current weight, or the arc must be new (BC_ERR_NOT_INCREMENTAL
+ * otherwise).  Stream-ordered; returns after enqueueing. */
+bc_status bc_update_edge(bc_ctx *ctx, bc_graph_id g, int32_t u, int32_t v, int64_t w);
+
+/* Incremental vertex update (Section 4, steps (A)-(D), Alg 4 and Lemma 4):
+ * k edges e[0..k) each with e[i].a == v or e[i].b == v.  Directed: (x,v) is
+ * an in-arc (set E_i), (v,x) an out-arc (set E_o).  Undirected: {v,x} is both.
+ * Each must lower the current weight or be new; no arc may repeat.  Sets with
+ * more than 64 arcs per direction are applied as consecutive vertex updates
+ * at v, which reach the same state. */
+bc_status bc_update_vertex(bc_ctx *ctx, bc_graph_id g, int32_t v, int32_t k, const bc_edge *e);
+
+/* Batched and served updates.  A request names a graph and either one edge
+ * update or one vertex update.  bc_submit validates every request (none is
+ * applied if one fails; *bad_index gets its index), then enqueues them as
+ * steps: step k holds the k-th request of every graph, and all graphs of a
+ * step are processed together by the same kernel launches (replayed from a
+ * captured HIP graph).  Requests on one graph keep their order.  *ticket
+ * identifies the submission for bc_poll/bc_wait. */
+typedef struct {
+    bc_graph_id graph;
+    int32_t kind;          /* 0 = edge (u, v, w), 1 = vertex (v, k, edges) */
+    int32_t u, v;
+    int64_t w;
+    int32_t k;
+    const bc_edge *edges;  /* host pointer, k entries, read during bc_submit only */
+} bc_request;
+
+bc_status bc_submit(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *ticket, int32_t *bad_index);
+/* *done = 1 once every step of the ticket has finished on the device. */
+bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, int32_t *done);
+bc_status bc_wait(bc_ctx *ctx, uint64_t ticket);
+
+/* Waits for all work of the context; returns the first sticky error of any
+ * graph, or BC_OK. */
+bc_status bc_sync(bc_ctx *ctx);
+
+/* BC(v) for all v (Eq.3 over ordered pairs) into host memory out[0..n).
+ * Synchronises. */
+bc_status bc_scores(bc_ctx *ctx, bc_graph_id g, double *out);
+
+/* Full static recomputation on the GPU from the current arc set (the Brandes
+ * baseline, Alg 7, and the recovery path after a sticky error). */
+bc_status bc_recompute(bc_ctx *ctx, bc_graph_id g);
+
+/* Introspection (tests).  All synchronise and write host memory.
+ * bc_get_rows: rows s0..s0+cnt-1 of d (int64, INT64_MAX unreachable) and
+ *   sigma (uint64); either pointer may be NULL.
+ * bc_get_dag: arcs (a[i], b[i]) of DAG(s), the predicate of Eq.1 over E*;
+ *   cap entries at most, *cnt gets the full count.
+ * bc_get_estar: E* arcs (a, b, w); same capacity rule.
+ * bc_get_delta: the dependency row delta_s.(.) of Eq.4 computed by the GPU's
+ *   level-ordered accumulation (0 at s itself and at unreachable vertices).
+ * bc_state_hash: 128-bit hash of D and sigma (order-fixed, bit-exact).
+ * bc_get_stats: counters of the last update (see bc_update_stats). */
+bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id g, int32_t s0, int32_t cnt, int64_t *D, uint64_t *sigma);
+bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *a, int32_t *b, int64_t cap, int64_t *cnt);
+bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id g, int32_t *a, int32_t *b, int64_t *w, int64_t cap, int64_t *cnt);
+bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id g, int32_t s, double *out);
+bc_status bc_state_hash(bc_ctx *ctx, bc_graph_id g, uint64_t out[2]);
+
+typedef struct {
+    int64_t affected_sources; /* |A| of the last update (sum over its phases) */
+    int64_t changed_pairs;    /* pairs (s,t) whose d or sigma changed */
+    int64_t estar_arcs;       /* |E*| after the update */
+    int64_t max_levels;       /* deepest DAG level count seen by the per-source kernel */
+    int64_t updates_applied;  /* updates since load */
+} bc_update_stats;
+bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id g, bc_update_stats *out);
+
+const char *bc_status_string(bc_status s);
+const char *bc_last_error(bc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCINC_H */

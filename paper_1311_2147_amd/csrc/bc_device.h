@@ -1,0 +1,118 @@
+// Device-side data structures of libbcinc (shared by its kernels and its host
+// code; nothing here is shared with anything outside the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcinc {
+
+// Unreachable marker of the int32 distance matrix.  Finite distances stay
+// strictly below it; a finite result that would reach it is an overflow.
+constexpr int32_t INF32 = 0x7fffffff;
+
+// Arcs per direction carried inline by one update job (E_i and E_o of
+// Section 4).  Larger vertex updates are split on the host into consecutive
+// vertex updates at the same vertex.
+constexpr int KMAX = 64;
+
+// Most vertices whose distance row fits in LDS (4 bytes each) next to the
+// per-workgroup bookkeeping: 36864 * 4 = 144 KiB of the 160 KiB of gfx950.
+constexpr int32_t LDS_ROW_MAX = 36864;
+
+// E* rebuild modes (see the k_es_* kernels).
+enum { ES_MERGE = 0, ES_FILTER = 1, ES_BUILD = 2 };
+
+// Dependency-pass modes (see dag_pass).
+enum { MODE_OLD = 0, MODE_NEW = 1, MODE_STATIC = 2, MODE_ROW = 3 };
+
+// Sticky status bits of a graph.
+enum : int32_t { ST_SIGMA_OVF = 1, ST_DIST_OVF = 2, ST_ESTAR_CAP = 4 };
+
+// Control words of one graph, resident in device memory.
+struct GraphCtl {
+    int32_t status;     // sticky ST_* bits
+    int32_t a_count;    // |A| of the update in flight (written by the scan)
+    int32_t work_next;  // next item of the persistent per-source kernel
+    int32_t max_levels; // deepest Kahn level count seen (statistic)
+    int32_t es_m;       // arcs in the current E* (buffer X)
+    int32_t es_m_tmp;   // arcs in the merged E* (buffer Y)
+    int32_t pad0, pad1;
+    unsigned long long changed_pairs;  // statistic of the last update
+    unsigned long long affected_last;  // |A| of the last update
+    unsigned long long updates;        // updates applied since load
+};
+
+// Per-source scalars of the update in flight (Alg 4 output).
+//   dv = d'(s,v), sv = sigma'_sv, hv = sigma-hat'_sv (new paths through E_i);
+//   flag bit 0: d'(s,v) == d(s,v) ("same"), bit 1: s is affected.
+struct SrcScal {
+    int32_t dv;
+    int32_t flags;
+    uint64_t sv;
+    uint64_t hv;
+};
+
+// Device pointers and sizes of one graph.  A copy rides in every job.
+struct GraphPtrs {
+    int32_t n;
+    int32_t directed;
+    int64_t es_cap;  // capacity of each E* buffer (arcs)
+    int32_t *D;      // n x n distances, INF32 = unreachable
+    uint64_t *S;     // n x n path counts
+    double *bc_hi, *bc_lo;  // BC as an unevaluated sum hi + lo
+    double *bc_delta;       // per-update difference, folded into (hi, lo) at commit
+    // E* as CSR by tail; X holds the current set, Y the merged set of an update.
+    int32_t *x_ptr, *x_src, *x_dst, *x_w;
+    int32_t *y_ptr, *y_src, *y_dst, *y_w;
+    int32_t *es_cnt;  // n + 1 counts / offsets for rebuilding
+    SrcScal *scal;    // n
+    int32_t *alist;   // n, affected sources
+    int32_t *rv_D;    // snapshot of row v before the update (n)
+    uint64_t *rv_S;
+    int32_t *rvv_D;   // row v'' after the Out phase (n)
+    uint64_t *rvv_S, *rvv_H;
+    GraphCtl *ctl;
+    // Full arc set as CSR by tail (static recompute and E* build).
+    int32_t *arc_ptr, *arc_dst, *arc_w;
+    int64_t arc_m;
+};
+
+// One update on one graph: centre vertex v, in-arcs E_i = {(in_tail[j], v)}
+// and out-arcs E_o = {(v, out_head[j])} with their new weights.  An arc
+// update (u, v) is the vertex form at v with E_i = {(u, v)} and E_o empty.
+// The merged arc list u_* (tail-sorted) is E_i and E_o together, the arcs
+// that enter E* candidates.
+struct UpdateJob {
+    GraphPtrs g;
+    int32_t v;
+    int32_t n_in, n_out;
+    int32_t n_u;
+    const int32_t *row_v_D;   // row v to read during the update: live row, or the snapshot
+    const uint64_t *row_v_S;  // when the Out phase rewrites row v
+    int32_t in_tail[KMAX], in_w[KMAX];
+    int32_t out_head[KMAX], out_w[KMAX];
+    int32_t u_tail[2 * KMAX], u_head[2 * KMAX], u_w[2 * KMAX];
+};
+
+// Per-workgroup scratch of the per-source kernels.
+struct SlotLayout {
+    size_t indeg, order, lvl, coef, dold, queue2, total;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+__host__ __device__ inline SlotLayout slot_layout(int32_t n) {
+    SlotLayout L;
+    size_t off = 0;
+    L.indeg = off;  off += align256(sizeof(int32_t) * (size_t)n);
+    L.order = off;  off += align256(sizeof(int32_t) * (size_t)n);
+    L.lvl = off;    off += align256(sizeof(int32_t) * ((size_t)n + 1));
+    L.coef = off;   off += align256(sizeof(double) * (size_t)n);
+    L.dold = off;   off += align256(sizeof(double) * (size_t)n);
+    L.queue2 = off; off += align256(sizeof(int32_t) * (size_t)n);
+    L.total = off;
+    return L;
+}
+
+}  // namespace bcinc

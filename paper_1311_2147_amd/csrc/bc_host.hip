@@ -1,0 +1,1017 @@
+// Host side of libbcinc: the C ABI declared in include/bcinc.h.
+//
+// Responsibilities: validation of every request against a host mirror of the
+// arcs (so a rejected call leaves all state unchanged), carving each graph's
+// caller-provided device arena, staging update jobs, launching the kernel
+// sequence (directly for single updates, replayed from a captured HIP graph
+// for batched steps) and introspection copies.  All arithmetic of the method
+// runs in the kernels of bc_kernels.hip.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bcinc.h"
+#include "bc_device.h"
+
+// The kernels live in bc_kernels.hip, compiled in the same translation unit
+// (see bcinc.hip).
+
+using namespace bcinc;
+
+namespace {
+
+constexpr int RING = 4;            // job staging slots in flight
+constexpr int JCAP = 256;          // jobs per staging slot
+constexpr size_t MISC_BYTES = 4096;
+constexpr int DEFAULT_SLOTS = 256; // one persistent workgroup per CU of an MI355X
+constexpr int DEFAULT_BLOCK = 512;
+constexpr int64_t W_MAX = (int64_t)INF32 - 1;
+
+size_t ring_slot_bytes() { return align256(256 + sizeof(UpdateJob) * JCAP); }
+size_t ring_bytes() { return RING * ring_slot_bytes(); }
+
+struct Mirror {
+    // Arcs of G (G_D when undirected) as a CSR by tail, heads sorted, plus an
+    // overlay of arcs inserted since the last rebuild.
+    int32_t n = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> dst;
+    std::vector<int32_t> w;
+    std::unordered_map<uint64_t, int32_t> extra;
+    int64_t arcs = 0;
+
+    uint64_t key(int32_t a, int32_t b) const { return (uint64_t)a * (uint64_t)n + (uint64_t)b; }
+
+    // current weight of (a,b), or -1 when absent
+    int64_t find(int32_t a, int32_t b) const {
+        auto first = dst.begin() + ptr[a], last = dst.begin() + ptr[a + 1];
+        auto it = std::lower_bound(first, last, b);
+        if (it != last && *it == b) return w[it - dst.begin()];
+        auto e = extra.find(key(a, b));
+        return e == extra.end() ? -1 : e->second;
+    }
+
+    void set(int32_t a, int32_t b, int32_t wt) {
+        auto first = dst.begin() + ptr[a], last = dst.begin() + ptr[a + 1];
+        auto it = std::lower_bound(first, last, b);
+        if (it != last && *it == b) {
+            w[it - dst.begin()] = wt;
+            return;
+        }
+        auto e = extra.find(key(a, b));
+        if (e == extra.end()) {
+            extra.emplace(key(a, b), wt);
+            ++arcs;
+        } else {
+            e->second = wt;
+        }
+    }
+
+    // Folds the overlay into the CSR.
+    void compact() {
+        if (extra.empty()) return;
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> add(n);
+        for (auto &kv : extra) add[kv.first / n].push_back({(int32_t)(kv.first % n), kv.second});
+        std::vector<int64_t> np(n + 1, 0);
+        std::vector<int32_t> nd, nw;
+        nd.reserve(arcs);
+        nw.reserve(arcs);
+        for (int32_t a = 0; a < n; ++a) {
+            std::vector<std::pair<int32_t, int32_t>> row;
+            for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) row.push_back({dst[e], w[e]});
+            row.insert(row.end(), add[a].begin(), add[a].end());
+            std::sort(row.begin(), row.end());
+            for (auto &p : row) {
+                nd.push_back(p.first);
+                nw.push_back(p.second);
+            }
+            np[a + 1] = (int64_t)nd.size();
+        }
+        ptr.swap(np);
+        dst.swap(nd);
+        w.swap(nw);
+        extra.clear();
+    }
+};
+
+struct GraphRec {
+    bool live = false;
+    int32_t n = 0;
+    int32_t directed = 1;
+    int64_t arc_cap = 0, es_cap = 0;
+    char *arena = nullptr;
+    uint64_t arena_bytes = 0;
+    GraphPtrs P{};
+    Mirror mirror;
+    uint64_t updates = 0;
+};
+
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct bc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *scratch = nullptr;
+    uint64_t scratch_bytes = 0;
+    uint64_t budget = 0;
+    uint64_t in_use = 0;
+    int slots = DEFAULT_SLOTS;
+    int block = DEFAULT_BLOCK;
+    int cu_count = 256;
+    std::vector<GraphRec *> graphs;
+    std::string last_error;
+    // staging
+    UpdateJob *h_jobs[RING] = {};
+    int32_t *h_njobs[RING] = {};
+    hipEvent_t ring_ev[RING] = {};
+    bool ring_used[RING] = {};
+    int ring_next = 0;
+    std::map<std::tuple<int, int, size_t, int, int>, StepGraph> graph_cache;
+    // tickets
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, hipEvent_t> tickets;
+    std::vector<hipEvent_t> spare_events;
+};
+
+namespace {
+
+bc_status hip_fail(bc_ctx *ctx, hipError_t e, const char *what) {
+    if (ctx) {
+        char buf[512];
+        snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+        ctx->last_error = buf;
+    }
+    return BC_ERR_HIP;
+}
+
+#define HIPCHK(call)                                           \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+bc_status fail(bc_ctx *ctx, bc_status s, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return s;
+}
+
+char *ring_dev(bc_ctx *ctx, int r) { return ctx->scratch + (size_t)r * ring_slot_bytes(); }
+UpdateJob *ring_jobs_dev(bc_ctx *ctx, int r) { return (UpdateJob *)(ring_dev(ctx, r) + 256); }
+int32_t *ring_njobs_dev(bc_ctx *ctx, int r) { return (int32_t *)ring_dev(ctx, r); }
+char *misc_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes(); }
+char *slots_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes() + MISC_BYTES; }
+
+int usable_slots(bc_ctx *ctx, int32_t n_max, size_t *slot_bytes) {
+    const size_t sb = slot_layout(n_max).total;
+    *slot_bytes = sb;
+    const uint64_t fixed = ring_bytes() + MISC_BYTES;
+    if (ctx->scratch_bytes <= fixed) return 0;
+    const uint64_t avail = (ctx->scratch_bytes - fixed) / sb;
+    return (int)std::min<uint64_t>((uint64_t)ctx->slots, avail);
+}
+
+int lds_cap_for(int32_t n_max) { return std::min<int32_t>(n_max, LDS_ROW_MAX); }
+
+// Arena layout of one graph (every piece 256-byte aligned).
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    }
+};
+
+GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *total) {
+    Carve c;
+    const size_t nn = (size_t)n * (size_t)n;
+    size_t oD = c.take(4 * nn), oS = c.take(8 * nn);
+    size_t ohi = c.take(8 * (size_t)n), olo = c.take(8 * (size_t)n), odl = c.take(8 * (size_t)n);
+    size_t oxp = c.take(4 * ((size_t)n + 1)), oxs = c.take(4 * (size_t)es_cap), oxd = c.take(4 * (size_t)es_cap),
+           oxw = c.take(4 * (size_t)es_cap);
+    size_t oyp = c.take(4 * ((size_t)n + 1)), oys = c.take(4 * (size_t)es_cap), oyd = c.take(4 * (size_t)es_cap),
+           oyw = c.take(4 * (size_t)es_cap);
+    size_t ocnt = c.take(4 * ((size_t)n + 1));
+    size_t osc = c.take(sizeof(SrcScal) * (size_t)n), oal = c.take(4 * (size_t)n);
+    size_t orvd = c.take(4 * (size_t)n), orvs = c.take(8 * (size_t)n);
+    size_t orvvd = c.take(4 * (size_t)n), orvvs = c.take(8 * (size_t)n), orvvh = c.take(8 * (size_t)n);
+    size_t octl = c.take(sizeof(GraphCtl));
+    size_t oap = c.take(4 * ((size_t)n + 1)), oad = c.take(4 * (size_t)arc_cap), oaw = c.take(4 * (size_t)arc_cap);
+    *total = c.off;
+    GraphPtrs P{};
+    if (!base) return P;
+    P.n = n;
+    P.es_cap = es_cap;
+    P.D = (int32_t *)(base + oD);
+    P.S = (uint64_t *)(base + oS);
+    P.bc_hi = (double *)(base + ohi);
+    P.bc_lo = (double *)(base + olo);
+    P.bc_delta = (double *)(base + odl);
+    P.x_ptr = (int32_t *)(base + oxp);
+    P.x_src = (int32_t *)(base + oxs);
+    P.x_dst = (int32_t *)(base + oxd);
+    P.x_w = (int32_t *)(base + oxw);
+    P.y_ptr = (int32_t *)(base + oyp);
+    P.y_src = (int32_t *)(base + oys);
+    P.y_dst = (int32_t *)(base + oyd);
+    P.y_w = (int32_t *)(base + oyw);
+    P.es_cnt = (int32_t *)(base + ocnt);
+    P.scal = (SrcScal *)(base + osc);
+    P.alist = (int32_t *)(base + oal);
+    P.rv_D = (int32_t *)(base + orvd);
+    P.rv_S = (uint64_t *)(base + orvs);
+    P.rvv_D = (int32_t *)(base + orvvd);
+    P.rvv_S = (uint64_t *)(base + orvvs);
+    P.rvv_H = (uint64_t *)(base + orvvh);
+    P.ctl = (GraphCtl *)(base + octl);
+    P.arc_ptr = (int32_t *)(base + oap);
+    P.arc_dst = (int32_t *)(base + oad);
+    P.arc_w = (int32_t *)(base + oaw);
+    return P;
+}
+
+GraphRec *get_graph(bc_ctx *ctx, bc_graph_id g) {
+    if (!ctx || g < 0 || g >= (int)ctx->graphs.size()) return nullptr;
+    GraphRec *r = ctx->graphs[g];
+    return (r && r->live) ? r : nullptr;
+}
+
+// Acquire a staging slot (waits until its previous use has finished).
+bc_status ring_acquire(bc_ctx *ctx, int *slot) {
+    int r = ctx->ring_next;
+    ctx->ring_next = (r + 1) % RING;
+    if (ctx->ring_used[r]) HIPCHK(hipEventSynchronize(ctx->ring_ev[r]));
+    ctx->ring_used[r] = false;
+    *slot = r;
+    return BC_OK;
+}
+
+bc_status ring_stage(bc_ctx *ctx, int r, const std::vector<UpdateJob> &jobs) {
+    const size_t nj = jobs.size();
+    if (nj > (size_t)JCAP) return fail(ctx, BC_ERR_CAPACITY, "too many jobs in one step");
+    *ctx->h_njobs[r] = (int32_t)nj;
+    if (nj) memcpy(ctx->h_jobs[r], jobs.data(), sizeof(UpdateJob) * nj);
+    HIPCHK(hipMemcpyAsync(ring_njobs_dev(ctx, r), ctx->h_njobs[r], sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    if (nj)
+        HIPCHK(hipMemcpyAsync(ring_jobs_dev(ctx, r), ctx->h_jobs[r], sizeof(UpdateJob) * nj, hipMemcpyHostToDevice,
+                              ctx->stream));
+    return BC_OK;
+}
+
+bc_status ring_release(bc_ctx *ctx, int r) {
+    HIPCHK(hipEventRecord(ctx->ring_ev[r], ctx->stream));
+    ctx->ring_used[r] = true;
+    return BC_OK;
+}
+
+struct LaunchShape {
+    int32_t n_max;
+    int njobs;
+    int slots;
+    size_t slot_bytes;
+    int lds_cap;
+};
+
+// The update kernel sequence for the jobs staged in ring slot r.
+bc_status launch_update_sequence(bc_ctx *ctx, int r, const LaunchShape &L) {
+    const UpdateJob *jobs = ring_jobs_dev(ctx, r);
+    const int32_t *nj = ring_njobs_dev(ctx, r);
+    hipStream_t st = ctx->stream;
+    const int g_elem = (int)std::min<int64_t>(((int64_t)L.n_max + 255) / 256, 2048);
+    const int g_wave = (int)std::min<int64_t>(((int64_t)L.n_max * 64 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_scan, dim3(g_elem), dim3(256), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_rowv, dim3(g_elem), dim3(256), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_es_count<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_es_scan<ES_MERGE>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), (size_t)L.lds_cap * 4, st, jobs, nj, slots_dev(ctx),
+                       L.slot_bytes, L.lds_cap);
+    hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_es_scatter<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+    hipLaunchKernelGGL(k_commit, dim3(g_elem), dim3(256), 0, st, jobs, nj, 0);
+    HIPCHK(hipGetLastError());
+    return BC_OK;
+}
+
+bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape *L) {
+    L->n_max = 1;
+    for (auto &j : jobs) L->n_max = std::max(L->n_max, j.g.n);
+    L->njobs = (int)jobs.size();
+    L->slots = usable_slots(ctx, L->n_max, &L->slot_bytes);
+    if (L->slots < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for one work slot at this n");
+    L->lds_cap = lds_cap_for(L->n_max);
+    return BC_OK;
+}
+
+bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_graph) {
+    LaunchShape L;
+    bc_status st = shape_for(ctx, jobs, &L);
+    if (st) return st;
+    int r;
+    if ((st = ring_acquire(ctx, &r))) return st;
+    if ((st = ring_stage(ctx, r, jobs))) return st;
+    if (!use_graph) {
+        if ((st = launch_update_sequence(ctx, r, L))) return st;
+    } else {
+        auto key = std::make_tuple(r, L.njobs, L.slot_bytes, L.slots, L.lds_cap);
+        auto it = ctx->graph_cache.find(key);
+        if (it == ctx->graph_cache.end()) {
+            StepGraph sg;
+            HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            bc_status cst = launch_update_sequence(ctx, r, L);
+            hipError_t ce = hipStreamEndCapture(ctx->stream, &sg.graph);
+            if (cst) return cst;
+            if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
+            HIPCHK(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+            it = ctx->graph_cache.emplace(key, sg).first;
+        }
+        HIPCHK(hipGraphLaunch(it->second.exec, ctx->stream));
+    }
+    return ring_release(ctx, r);
+}
+
+UpdateJob job_template(const GraphRec *g) {
+    UpdateJob j;
+    memset(&j, 0, sizeof j);
+    j.g = g->P;
+    return j;
+}
+
+// Splits one validated update into jobs of at most KMAX arcs per direction.
+// Each job is itself an incremental vertex update at v, so applying them in
+// order reaches the same state.
+void build_jobs(const GraphRec *g, int32_t v, const std::vector<std::pair<int32_t, int32_t>> &ein,
+                const std::vector<std::pair<int32_t, int32_t>> &eout, std::vector<UpdateJob> &out) {
+    size_t i = 0, o = 0;
+    do {
+        UpdateJob j = job_template(g);
+        j.v = v;
+        while (i < ein.size() && j.n_in < KMAX) {
+            j.in_tail[j.n_in] = ein[i].first;
+            j.in_w[j.n_in] = ein[i].second;
+            j.u_tail[j.n_u] = ein[i].first;
+            j.u_head[j.n_u] = v;
+            j.u_w[j.n_u] = ein[i].second;
+            ++j.n_in, ++j.n_u, ++i;
+        }
+        while (o < eout.size() && j.n_out < KMAX) {
+            j.out_head[j.n_out] = eout[o].first;
+            j.out_w[j.n_out] = eout[o].second;
+            j.u_tail[j.n_u] = v;
+            j.u_head[j.n_u] = eout[o].first;
+            j.u_w[j.n_u] = eout[o].second;
+            ++j.n_out, ++j.n_u, ++o;
+        }
+        if (j.n_out > 0) {
+            j.row_v_D = g->P.rv_D;
+            j.row_v_S = g->P.rv_S;
+        } else {
+            j.row_v_D = g->P.D + (size_t)v * g->n;
+            j.row_v_S = g->P.S + (size_t)v * g->n;
+        }
+        out.push_back(j);
+    } while (i < ein.size() || o < eout.size());
+}
+
+// Validates one request against the mirror plus the pending changes of
+// earlier requests in the same call; on success appends its jobs and its
+// arc changes.
+struct Pending {
+    std::map<std::pair<int32_t, int32_t>, int32_t> arcs;  // (a,b) -> new weight
+    int64_t inserted = 0;
+};
+
+int64_t current_weight(const GraphRec *g, const Pending &p, int32_t a, int32_t b) {
+    auto it = p.arcs.find({a, b});
+    if (it != p.arcs.end()) return it->second;
+    return g->mirror.find(a, b);
+}
+
+bc_status check_edge_arg(bc_ctx *ctx, const GraphRec *g, int32_t a, int32_t b, int64_t w) {
+    if (a < 0 || b < 0 || a >= g->n || b >= g->n) return fail(ctx, BC_ERR_INVALID_ARG, "vertex id out of range");
+    if (a == b) return fail(ctx, BC_ERR_SELF_LOOP, "self-loop");
+    if (w <= 0 || w > W_MAX) return fail(ctx, BC_ERR_BAD_WEIGHT, "weight out of range");
+    return BC_OK;
+}
+
+bc_status validate_vertex(bc_ctx *ctx, GraphRec *g, int32_t v, int32_t k, const bc_edge *e, Pending &p,
+                          std::vector<UpdateJob> &jobs) {
+    if (v < 0 || v >= g->n) return fail(ctx, BC_ERR_INVALID_ARG, "vertex id out of range");
+    if (k < 0 || (k > 0 && !e)) return fail(ctx, BC_ERR_INVALID_ARG, "bad edge list");
+    std::vector<std::pair<int32_t, int32_t>> ein, eout;
+    std::vector<std::pair<std::pair<int32_t, int32_t>, int32_t>> changes;
+    std::map<std::pair<int32_t, int32_t>, int> seen;
+    for (int32_t i = 0; i < k; ++i) {
+        const int32_t a = e[i].a, b = e[i].b;
+        bc_status st = check_edge_arg(ctx, g, a, b, e[i].w);
+        if (st) return st;
+        if (a != v && b != v) return fail(ctx, BC_ERR_NOT_INCIDENT, "edge does not touch the updated vertex");
+        const int32_t x = (a == v) ? b : a;
+        const std::pair<int32_t, int32_t> key = g->directed ? std::make_pair(a, b) : std::make_pair(std::min(a, b), std::max(a, b));
+        if (seen.count(key)) return fail(ctx, BC_ERR_DUPLICATE_EDGE, "edge repeated in one vertex update");
+        seen[key] = 1;
+        const int32_t w = (int32_t)e[i].w;
+        if (g->directed) {
+            const int64_t cw = current_weight(g, p, a, b);
+            if (cw >= 0 && w >= cw) return fail(ctx, BC_ERR_NOT_INCREMENTAL, "new weight is not below the current one");
+            if (b == v) ein.push_back({a, w});
+            else eout.push_back({b, w});
+            changes.push_back({{a, b}, w});
+        } else {
+            const int64_t cw = current_weight(g, p, x, v);
+            if (cw >= 0 && w >= cw) return fail(ctx, BC_ERR_NOT_INCREMENTAL, "new weight is not below the current one");
+            ein.push_back({x, w});
+            eout.push_back({x, w});
+            changes.push_back({{x, v}, w});
+            changes.push_back({{v, x}, w});
+        }
+    }
+    int64_t ins = 0;
+    for (auto &c : changes)
+        if (current_weight(g, p, c.first.first, c.first.second) < 0) ++ins;
+    if (g->mirror.arcs + p.inserted + ins > g->arc_cap) return fail(ctx, BC_ERR_CAPACITY, "arc capacity exceeded");
+    for (auto &c : changes) p.arcs[c.first] = c.second;
+    p.inserted += ins;
+    if (k > 0) build_jobs(g, v, ein, eout, jobs);
+    return BC_OK;
+}
+
+// For a directed arc (u,v): the vertex form at v with E_i = {(u,v)}.  For an
+// undirected edge {u,v}: the vertex form at u with E_i = {(v,u)} and
+// E_o = {(u,v)}, equivalent to the two arc updates of G_D in sequence.
+bc_status validate_edge(bc_ctx *ctx, GraphRec *g, int32_t u, int32_t v, int64_t w, Pending &p,
+                        std::vector<UpdateJob> &jobs) {
+    bc_status st = check_edge_arg(ctx, g, u, v, w);
+    if (st) return st;
+    bc_edge e{u, v, w};
+    return validate_vertex(ctx, g, g->directed ? v : u, 1, &e, p, jobs);
+}
+
+void apply_pending(GraphRec *g, const Pending &p) {
+    for (auto &kv : p.arcs) g->mirror.set(kv.first.first, kv.first.second, kv.second);
+}
+
+bc_status read_status(bc_ctx *ctx, GraphRec *g, int32_t *status) {
+    HIPCHK(hipMemcpyAsync(status, &g->P.ctl->status, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BC_OK;
+}
+
+bc_status sticky_to_status(int32_t st) {
+    if (st & ST_SIGMA_OVF) return BC_ERR_SIGMA_OVERFLOW;
+    if (st & ST_DIST_OVF) return BC_ERR_DIST_OVERFLOW;
+    if (st & ST_ESTAR_CAP) return BC_ERR_ESTAR_CAPACITY;
+    return BC_OK;
+}
+
+// Static pass on the GPU from the mirror's arcs: distances, E*, counts,
+// dependencies and BC (Alg 7 with the DAG taken from E*, Alg 6 steps 2-8).
+bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
+    g->mirror.compact();
+    const int32_t n = g->n;
+    std::vector<int32_t> hp(n + 1), hd(g->mirror.dst), hw(g->mirror.w);
+    for (int32_t i = 0; i <= n; ++i) hp[i] = (int32_t)g->mirror.ptr[i];
+    const int64_t m = (int64_t)hd.size();
+    if (m > g->arc_cap) return fail(ctx, BC_ERR_CAPACITY, "arc capacity exceeded");
+    g->P.arc_m = m;
+    HIPCHK(hipMemcpyAsync(g->P.arc_ptr, hp.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, ctx->stream));
+    if (m) {
+        HIPCHK(hipMemcpyAsync(g->P.arc_dst, hd.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->P.arc_w, hw.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIPCHK(hipMemsetAsync(g->P.ctl, 0, sizeof(GraphCtl), ctx->stream));
+    HIPCHK(hipMemsetAsync(g->P.bc_delta, 0, 8 * (size_t)n, ctx->stream));
+    std::vector<UpdateJob> jobs(1, job_template(g));
+    LaunchShape L;
+    bc_status st = shape_for(ctx, jobs, &L);
+    if (st) return st;
+    int r;
+    if ((st = ring_acquire(ctx, &r))) return st;
+    if ((st = ring_stage(ctx, r, jobs))) return st;
+    const UpdateJob *dj = ring_jobs_dev(ctx, r);
+    const int32_t *nj = ring_njobs_dev(ctx, r);
+    const int slots = std::min<int>(L.slots, n);
+    const int g_wave = (int)std::min<int64_t>(((int64_t)n * 64 + 255) / 256, 4096);
+    hipStream_t s = ctx->stream;
+    hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
+    hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, slots_dev(ctx), L.slot_bytes,
+                       L.lds_cap);
+    hipLaunchKernelGGL(k_es_count<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
+    hipLaunchKernelGGL(k_es_scan<ES_BUILD>, dim3(1), dim3(1024), 0, s, dj, nj);
+    hipLaunchKernelGGL(k_es_scatter<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
+    hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
+    hipLaunchKernelGGL(k_static, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, slots_dev(ctx), L.slot_bytes,
+                       L.lds_cap);
+    hipLaunchKernelGGL(k_commit, dim3((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048), dim3(256), 0, s, dj, nj, 1);
+    HIPCHK(hipGetLastError());
+    st = ring_release(ctx, r);
+    if (st) return st;
+    // the host vectors above are read by the copies: finish before they go
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int32_t status = 0;
+    if ((st = read_status(ctx, g, &status))) return st;
+    if (status) return fail(ctx, sticky_to_status(status), "static pass failed");
+    return BC_OK;
+}
+
+bc_status set_lds_limits(bc_ctx *ctx) {
+    const int bytes = LDS_ROW_MAX * 4;
+    HIPCHK(hipFuncSetAttribute((const void *)k_source, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    HIPCHK(hipFuncSetAttribute((const void *)k_sssp, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    HIPCHK(hipFuncSetAttribute((const void *)k_static, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    HIPCHK(hipFuncSetAttribute((const void *)k_delta_row, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    return BC_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI ====
+
+extern "C" {
+
+uint64_t bc_graph_bytes(int32_t n, int64_t arc_capacity, int64_t estar_capacity) {
+    if (n <= 0 || arc_capacity < 0) return 0;
+    if (estar_capacity <= 0) estar_capacity = arc_capacity;
+    size_t total = 0;
+    carve(nullptr, n, std::max<int64_t>(arc_capacity, 1), std::max<int64_t>(estar_capacity, 1), &total);
+    return total;
+}
+
+uint64_t bc_scratch_bytes(int32_t n_max, int32_t slots) {
+    if (n_max <= 0) return 0;
+    if (slots <= 0) slots = DEFAULT_SLOTS;
+    return ring_bytes() + MISC_BYTES + (uint64_t)slots * slot_layout(n_max).total;
+}
+
+const char *bc_status_string(bc_status s) {
+    switch (s) {
+        case BC_OK: return "ok";
+        case BC_ERR_INVALID_ARG: return "invalid argument";
+        case BC_ERR_SELF_LOOP: return "self-loop";
+        case BC_ERR_BAD_WEIGHT: return "weight out of range";
+        case BC_ERR_DUPLICATE_EDGE: return "duplicate edge";
+        case BC_ERR_NOT_INCIDENT: return "edge not incident to the vertex";
+        case BC_ERR_NOT_INCREMENTAL: return "update is not incremental";
+        case BC_ERR_ADMISSION: return "memory budget exceeded";
+        case BC_ERR_CAPACITY: return "capacity exceeded";
+        case BC_ERR_SIGMA_OVERFLOW: return "path count overflow";
+        case BC_ERR_DIST_OVERFLOW: return "distance overflow";
+        case BC_ERR_HIP: return "HIP runtime error";
+        case BC_ERR_NO_DEVICE: return "no gfx950 device";
+        case BC_ERR_ESTAR_CAPACITY: return "E* capacity exceeded";
+        default: return "unknown status";
+    }
+}
+
+const char *bc_last_error(bc_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
+    if (!out || !cfg) return BC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    hipError_t de = hipGetDeviceCount(&count);
+    if (de != hipSuccess || cfg->device < 0 || cfg->device >= count) {
+        fprintf(stderr, "bcinc: bc_create: device %d unavailable (%d devices, %s)\n", cfg->device, count,
+                hipGetErrorString(de));
+        return BC_ERR_NO_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    de = hipGetDeviceProperties(&prop, cfg->device);
+    if (de != hipSuccess) {
+        fprintf(stderr, "bcinc: bc_create: hipGetDeviceProperties: %s\n", hipGetErrorString(de));
+        return BC_ERR_NO_DEVICE;
+    }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        fprintf(stderr, "bcinc: bc_create: device %d is %s, not gfx950\n", cfg->device, prop.gcnArchName);
+        return BC_ERR_NO_DEVICE;
+    }
+    if (!cfg->scratch || cfg->scratch_bytes < ring_bytes() + MISC_BYTES) return BC_ERR_INVALID_ARG;
+    if (((uintptr_t)cfg->scratch & 255) != 0) return BC_ERR_INVALID_ARG;
+    bc_ctx *ctx = new bc_ctx();
+    ctx->device = cfg->device;
+    ctx->cu_count = prop.multiProcessorCount;
+    ctx->scratch = (char *)cfg->scratch;
+    ctx->scratch_bytes = cfg->scratch_bytes;
+    ctx->budget = cfg->memory_budget;
+    ctx->slots = cfg->slots > 0 ? cfg->slots : DEFAULT_SLOTS;
+    ctx->block = cfg->block > 0 ? cfg->block : DEFAULT_BLOCK;
+    if (ctx->block % 64 != 0 || ctx->block > 1024) {
+        delete ctx;
+        return BC_ERR_INVALID_ARG;
+    }
+    auto bail = [&](hipError_t e, const char *what) {
+        bc_status st = hip_fail(ctx, e, what);
+        fprintf(stderr, "bcinc: %s\n", ctx->last_error.c_str());
+        delete ctx;
+        return st;
+    };
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) return bail(e, "hipSetDevice");
+    if (cfg->stream) {
+        ctx->stream = (hipStream_t)cfg->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(e, "hipStreamCreate");
+        ctx->own_stream = true;
+    }
+    for (int r = 0; r < RING; ++r) {
+        e = hipHostMalloc((void **)&ctx->h_jobs[r], sizeof(UpdateJob) * JCAP, hipHostMallocDefault);
+        if (e != hipSuccess) return bail(e, "hipHostMalloc");
+        e = hipHostMalloc((void **)&ctx->h_njobs[r], 256, hipHostMallocDefault);
+        if (e != hipSuccess) return bail(e, "hipHostMalloc");
+        e = hipEventCreateWithFlags(&ctx->ring_ev[r], hipEventDisableTiming);
+        if (e != hipSuccess) return bail(e, "hipEventCreate");
+    }
+    if (set_lds_limits(ctx) != BC_OK) {
+        fprintf(stderr, "bcinc: %s\n", ctx->last_error.c_str());
+        delete ctx;
+        return BC_ERR_HIP;
+    }
+    e = hipMemsetAsync(ctx->scratch, 0, ctx->scratch_bytes, ctx->stream);
+    if (e != hipSuccess) return bail(e, "hipMemsetAsync");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return bail(e, "hipStreamSynchronize");
+    *out = ctx;
+    return BC_OK;
+}
+
+bc_status bc_destroy(bc_ctx *ctx) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->graph_cache) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    for (auto &kv : ctx->tickets) (void)hipEventDestroy(kv.second);
+    for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
+    for (int r = 0; r < RING; ++r) {
+        if (ctx->h_jobs[r]) (void)hipHostFree(ctx->h_jobs[r]);
+        if (ctx->h_njobs[r]) (void)hipHostFree(ctx->h_njobs[r]);
+        if (ctx->ring_ev[r]) (void)hipEventDestroy(ctx->ring_ev[r]);
+    }
+    for (auto *g : ctx->graphs) delete g;
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return BC_OK;
+}
+
+bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int64_t *w,
+                        int32_t directed, int64_t arc_capacity, int64_t estar_capacity, void *arena,
+                        uint64_t arena_bytes, bc_graph_id *out) {
+    if (!ctx || !out || n <= 0 || m < 0 || (m > 0 && (!src || !dst || !w)) || !arena)
+        return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_load_graph");
+    if (((uintptr_t)arena & 255) != 0) return fail(ctx, BC_ERR_INVALID_ARG, "arena not 256-byte aligned");
+    const int64_t arcs = directed ? m : 2 * m;
+    if (arc_capacity < arcs) return fail(ctx, BC_ERR_CAPACITY, "arc capacity below the arc count");
+    if (arc_capacity >= (int64_t)INT32_MAX) return fail(ctx, BC_ERR_CAPACITY, "arc capacity above 2^31-1");
+    if (estar_capacity <= 0) estar_capacity = arc_capacity;
+    estar_capacity = std::min(estar_capacity, arc_capacity);
+    const uint64_t need = bc_graph_bytes(n, arc_capacity, estar_capacity);
+    if (arena_bytes < need) return fail(ctx, BC_ERR_CAPACITY, "arena smaller than bc_graph_bytes");
+    if (ctx->budget && ctx->in_use + arena_bytes > ctx->budget)
+        return fail(ctx, BC_ERR_ADMISSION, "graph state would exceed the memory budget");
+    size_t sb;
+    if (usable_slots(ctx, n, &sb) < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for this n");
+    // host mirror (validates ids, loops, weights, duplicates)
+    GraphRec *g = new GraphRec();
+    g->n = n;
+    g->directed = directed ? 1 : 0;
+    g->arc_cap = arc_capacity;
+    g->es_cap = estar_capacity;
+    g->arena = (char *)arena;
+    g->arena_bytes = arena_bytes;
+    Mirror &mr = g->mirror;
+    mr.n = n;
+    std::vector<std::pair<uint64_t, int32_t>> keyed;
+    keyed.reserve(arcs);
+    for (int64_t i = 0; i < m; ++i) {
+        const int32_t a = src[i], b = dst[i];
+        if (a < 0 || b < 0 || a >= n || b >= n) {
+            delete g;
+            return fail(ctx, BC_ERR_INVALID_ARG, "vertex id out of range");
+        }
+        if (a == b) {
+            delete g;
+            return fail(ctx, BC_ERR_SELF_LOOP, "self-loop");
+        }
+        if (w[i] <= 0 || w[i] > W_MAX) {
+            delete g;
+            return fail(ctx, BC_ERR_BAD_WEIGHT, "weight out of range");
+        }
+        keyed.push_back({(uint64_t)a * n + b, (int32_t)w[i]});
+        if (!directed) keyed.push_back({(uint64_t)b * n + a, (int32_t)w[i]});
+    }
+    std::sort(keyed.begin(), keyed.end());
+    for (size_t i = 1; i < keyed.size(); ++i)
+        if (keyed[i].first == keyed[i - 1].first) {
+            delete g;
+            return fail(ctx, BC_ERR_DUPLICATE_EDGE, "duplicate edge");
+        }
+    mr.ptr.assign(n + 1, 0);
+    mr.dst.resize(keyed.size());
+    mr.w.resize(keyed.size());
+    for (size_t i = 0; i < keyed.size(); ++i) {
+        const int32_t a = (int32_t)(keyed[i].first / n);
+        mr.dst[i] = (int32_t)(keyed[i].first % n);
+        mr.w[i] = keyed[i].second;
+        mr.ptr[a + 1]++;
+    }
+    for (int32_t a = 0; a < n; ++a) mr.ptr[a + 1] += mr.ptr[a];
+    mr.arcs = (int64_t)keyed.size();
+    size_t total = 0;
+    g->P = carve((char *)arena, n, arc_capacity, estar_capacity, &total);
+    g->P.directed = g->directed;
+    g->live = true;
+    ctx->graphs.push_back(g);
+    ctx->in_use += arena_bytes;
+    *out = (bc_graph_id)(ctx->graphs.size() - 1);
+    bc_status st = static_pass(ctx, g);
+    if (st) {
+        g->live = false;
+        ctx->in_use -= arena_bytes;
+        return st;
+    }
+    return BC_OK;
+}
+
+bc_status bc_free_graph(bc_ctx *ctx, bc_graph_id gid) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    g->live = false;
+    ctx->in_use -= g->arena_bytes;
+    g->mirror = Mirror();
+    return BC_OK;
+}
+
+bc_status bc_update_edge(bc_ctx *ctx, bc_graph_id gid, int32_t u, int32_t v, int64_t w) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    Pending p;
+    std::vector<UpdateJob> jobs;
+    bc_status st = validate_edge(ctx, g, u, v, w, p, jobs);
+    if (st) return st;
+    apply_pending(g, p);
+    for (auto &j : jobs) {
+        std::vector<UpdateJob> one(1, j);
+        if ((st = run_step(ctx, one, false))) return st;
+    }
+    g->updates += 1;
+    return BC_OK;
+}
+
+bc_status bc_update_vertex(bc_ctx *ctx, bc_graph_id gid, int32_t v, int32_t k, const bc_edge *e) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    Pending p;
+    std::vector<UpdateJob> jobs;
+    bc_status st = validate_vertex(ctx, g, v, k, e, p, jobs);
+    if (st) return st;
+    apply_pending(g, p);
+    for (auto &j : jobs) {
+        std::vector<UpdateJob> one(1, j);
+        if ((st = run_step(ctx, one, false))) return st;
+    }
+    g->updates += 1;
+    return BC_OK;
+}
+
+bc_status bc_submit(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *ticket, int32_t *bad_index) {
+    if (!ctx || cnt < 0 || (cnt > 0 && !reqs) || !ticket) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_submit");
+    if (bad_index) *bad_index = -1;
+    std::map<int32_t, Pending> pend;
+    std::map<int32_t, std::vector<UpdateJob>> per_graph;
+    std::vector<int32_t> order;
+    for (int32_t i = 0; i < cnt; ++i) {
+        const bc_request &r = reqs[i];
+        GraphRec *g = get_graph(ctx, r.graph);
+        bc_status st;
+        if (!g) st = fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+        else if (r.kind == 0) st = validate_edge(ctx, g, r.u, r.v, r.w, pend[r.graph], per_graph[r.graph]);
+        else if (r.kind == 1) st = validate_vertex(ctx, g, r.v, r.k, r.edges, pend[r.graph], per_graph[r.graph]);
+        else st = fail(ctx, BC_ERR_INVALID_ARG, "bad request kind");
+        if (st) {
+            if (bad_index) *bad_index = i;
+            return st;
+        }
+        if (std::find(order.begin(), order.end(), r.graph) == order.end()) order.push_back(r.graph);
+    }
+    for (auto &kv : pend) apply_pending(ctx->graphs[kv.first], kv.second);
+    for (int32_t i = 0; i < cnt; ++i) ctx->graphs[reqs[i].graph]->updates += 1;
+    size_t steps = 0;
+    for (auto &kv : per_graph) steps = std::max(steps, kv.second.size());
+    for (size_t k = 0; k < steps; ++k) {
+        std::vector<UpdateJob> step;
+        for (int32_t gid : order) {
+            auto &v = per_graph[gid];
+            if (k < v.size()) step.push_back(v[k]);
+        }
+        for (size_t off = 0; off < step.size(); off += JCAP) {
+            std::vector<UpdateJob> part(step.begin() + off, step.begin() + std::min(step.size(), off + JCAP));
+            bc_status st = run_step(ctx, part, true);
+            if (st) return st;
+        }
+    }
+    hipEvent_t ev;
+    if (!ctx->spare_events.empty()) {
+        ev = ctx->spare_events.back();
+        ctx->spare_events.pop_back();
+    } else {
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(ev, ctx->stream));
+    *ticket = ctx->next_ticket++;
+    ctx->tickets[*ticket] = ev;
+    return BC_OK;
+}
+
+bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, int32_t *done) {
+    if (!ctx || !done) return BC_ERR_INVALID_ARG;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) {
+        *done = (ticket > 0 && ticket < ctx->next_ticket) ? 1 : 0;
+        return *done ? BC_OK : fail(ctx, BC_ERR_INVALID_ARG, "unknown ticket");
+    }
+    hipError_t e = hipEventQuery(it->second);
+    if (e == hipErrorNotReady) {
+        *done = 0;
+        return BC_OK;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventQuery");
+    *done = 1;
+    ctx->spare_events.push_back(it->second);
+    ctx->tickets.erase(it);
+    return BC_OK;
+}
+
+bc_status bc_wait(bc_ctx *ctx, uint64_t ticket) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return (ticket > 0 && ticket < ctx->next_ticket) ? BC_OK : fail(ctx, BC_ERR_INVALID_ARG, "unknown ticket");
+    HIPCHK(hipEventSynchronize(it->second));
+    ctx->spare_events.push_back(it->second);
+    ctx->tickets.erase(it);
+    return BC_OK;
+}
+
+bc_status bc_sync(bc_ctx *ctx) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (auto *g : ctx->graphs) {
+        if (!g || !g->live) continue;
+        int32_t st = 0;
+        bc_status s = read_status(ctx, g, &st);
+        if (s) return s;
+        if (st) return sticky_to_status(st);
+    }
+    return BC_OK;
+}
+
+bc_status bc_scores(bc_ctx *ctx, bc_graph_id gid, double *out) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || !out) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph or null output");
+    std::vector<double> hi(g->n), lo(g->n);
+    HIPCHK(hipMemcpyAsync(hi.data(), g->P.bc_hi, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(lo.data(), g->P.bc_lo, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
+    int32_t st = 0;
+    bc_status s = read_status(ctx, g, &st);
+    if (s) return s;
+    if (st) return sticky_to_status(st);
+    for (int32_t i = 0; i < g->n; ++i) out[i] = hi[i] + lo[i];
+    return BC_OK;
+}
+
+bc_status bc_recompute(bc_ctx *ctx, bc_graph_id gid) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    return static_pass(ctx, g);
+}
+
+bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id gid, int32_t s0, int32_t cnt, int64_t *D, uint64_t *sigma) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || s0 < 0 || cnt < 0 || s0 + (int64_t)cnt > g->n) return fail(ctx, BC_ERR_INVALID_ARG, "bad row range");
+    const size_t cells = (size_t)cnt * g->n;
+    std::vector<int32_t> d32(D ? cells : 0);
+    if (D) HIPCHK(hipMemcpyAsync(d32.data(), g->P.D + (size_t)s0 * g->n, 4 * cells, hipMemcpyDeviceToHost, ctx->stream));
+    if (sigma) HIPCHK(hipMemcpyAsync(sigma, g->P.S + (size_t)s0 * g->n, 8 * cells, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (D)
+        for (size_t i = 0; i < cells; ++i) D[i] = d32[i] == INF32 ? INT64_MAX : (int64_t)d32[i];
+    return BC_OK;
+}
+
+bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id gid, int32_t *a, int32_t *b, int64_t *w, int64_t cap, int64_t *cnt) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || !cnt || cap < 0) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    int32_t m = 0;
+    HIPCHK(hipMemcpyAsync(&m, &g->P.ctl->es_m, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *cnt = m;
+    const size_t k = (size_t)std::min<int64_t>(cap, m);
+    std::vector<int32_t> ww(k);
+    if (k) {
+        if (a) HIPCHK(hipMemcpyAsync(a, g->P.x_src, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (b) HIPCHK(hipMemcpyAsync(b, g->P.x_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (w) HIPCHK(hipMemcpyAsync(ww.data(), g->P.x_w, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (w)
+            for (size_t i = 0; i < k; ++i) w[i] = ww[i];
+    }
+    return BC_OK;
+}
+
+bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id gid, int32_t s, int32_t *a, int32_t *b, int64_t cap, int64_t *cnt) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || s < 0 || s >= g->n || !cnt || cap < 0) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    std::vector<UpdateJob> jobs(1, job_template(g));
+    int r;
+    bc_status st;
+    if ((st = ring_acquire(ctx, &r))) return st;
+    if ((st = ring_stage(ctx, r, jobs))) return st;
+    unsigned long long *dcnt = (unsigned long long *)misc_dev(ctx);
+    HIPCHK(hipMemsetAsync(dcnt, 0, 8, ctx->stream));
+    // DAG(s) is a subset of E*, so the spare E* buffer Y holds it
+    hipLaunchKernelGGL(k_dag_arcs, dim3(1024), dim3(256), 0, ctx->stream, ring_jobs_dev(ctx, r), s, g->P.y_src,
+                       g->P.y_dst, g->es_cap, dcnt);
+    HIPCHK(hipGetLastError());
+    if ((st = ring_release(ctx, r))) return st;
+    unsigned long long c = 0;
+    HIPCHK(hipMemcpyAsync(&c, dcnt, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *cnt = (int64_t)c;
+    const size_t k = (size_t)std::min<int64_t>(cap, (int64_t)c);
+    if (k) {
+        if (a) HIPCHK(hipMemcpyAsync(a, g->P.y_src, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (b) HIPCHK(hipMemcpyAsync(b, g->P.y_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return BC_OK;
+}
+
+bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || s < 0 || s >= g->n || !out) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    size_t sb;
+    if (usable_slots(ctx, g->n, &sb) < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small");
+    std::vector<UpdateJob> jobs(1, job_template(g));
+    int r;
+    bc_status st;
+    if ((st = ring_acquire(ctx, &r))) return st;
+    if ((st = ring_stage(ctx, r, jobs))) return st;
+    const int lds = lds_cap_for(g->n);
+    hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), (size_t)lds * 4, ctx->stream, ring_jobs_dev(ctx, r), s,
+                       slots_dev(ctx), lds);
+    HIPCHK(hipGetLastError());
+    if ((st = ring_release(ctx, r))) return st;
+    const SlotLayout L = slot_layout(g->n);
+    HIPCHK(hipMemcpyAsync(out, slots_dev(ctx) + L.dold, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BC_OK;
+}
+
+bc_status bc_state_hash(bc_ctx *ctx, bc_graph_id gid, uint64_t out[2]) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || !out) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    std::vector<UpdateJob> jobs(1, job_template(g));
+    int r;
+    bc_status st;
+    if ((st = ring_acquire(ctx, &r))) return st;
+    if ((st = ring_stage(ctx, r, jobs))) return st;
+    unsigned long long *dh = (unsigned long long *)misc_dev(ctx) + 2;
+    HIPCHK(hipMemsetAsync(dh, 0, 16, ctx->stream));
+    hipLaunchKernelGGL(k_hash, dim3(1024), dim3(256), 0, ctx->stream, ring_jobs_dev(ctx, r), dh);
+    HIPCHK(hipGetLastError());
+    if ((st = ring_release(ctx, r))) return st;
+    HIPCHK(hipMemcpyAsync(out, dh, 16, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BC_OK;
+}
+
+bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id gid, bc_update_stats *out) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || !out) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    GraphCtl c;
+    HIPCHK(hipMemcpyAsync(&c, g->P.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    out->affected_sources = (int64_t)c.affected_last;
+    out->changed_pairs = (int64_t)c.changed_pairs;
+    out->estar_arcs = c.es_m;
+    out->max_levels = c.max_levels;
+    out->updates_applied = (int64_t)g->updates;
+    return BC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+"""CPU-side checks of the boundary: the library loads and exports every entry
+point the header declares; size queries are pure host arithmetic."""
+from __future__ import annotations
+
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bcinc.h")
+LIB = os.path.join(ROOT, "paper_1311_2147_amd", "libbcinc.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(bc_[a-z_]+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib_built():
+    if not os.path.exists(LIB):
+        from paper_1311_2147_amd import build
+
+        build.build()
+    return LIB
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("bc_load_graph", "bc_update_edge", "bc_update_vertex", "bc_scores", "bc_submit", "bc_recompute",
+                     "bc_get_rows", "bc_get_dag"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib_built):
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_built], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (bc_[a-z_]+)\b", out))
+    missing = declared_functions() - exported
+    assert not missing, f"declared but not exported: {sorted(missing)}"
+
+
+def test_binding_loads_and_covers_the_header(lib_built):
+    from paper_1311_2147_amd import bcinc
+
+    assert set(bcinc.EXPORTED) == declared_functions()
+
+
+def test_size_queries(lib_built):
+    from paper_1311_2147_amd import bcinc
+
+    n = 1000
+    b = bcinc.bc_graph_bytes(n, 8000, 0)
+    assert b >= 12 * n * n  # D (int32) + sigma (uint64) dominate
+    assert b < 12 * n * n + 8000 * 64 + n * 400
+    assert bcinc.bc_graph_bytes(0, 10, 0) == 0
+    s1 = bcinc.bc_scratch_bytes(n, 10)
+    s2 = bcinc.bc_scratch_bytes(n, 20)
+    assert s2 > s1 > 0
+
+
+def test_status_strings(lib_built):
+    from paper_1311_2147_amd import bcinc
+
+    for code in bcinc.STATUS_NAMES:
+        assert bcinc._lib.bc_status_string(code)
+
+
+def test_create_without_device_fails_cleanly(lib_built):
+    import ctypes
+
+    import torch
+
+    from paper_1311_2147_amd import bcinc
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = bcinc.bc_config(0, 0, None, None, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    rc = bcinc._lib.bc_create(ctypes.byref(h), ctypes.byref(cfg))
+    assert rc in (-12, -1)

@@ -21,10 +21,14 @@ constexpr int KMAX = 64;
 constexpr int32_t LDS_ROW_MAX = 36864;
 
 // E* rebuild modes (see the k_es_* kernels).
-enum { ES_MERGE = 0, ES_FILTER = 1, ES_BUILD = 2 };
+//   ES_BUILD   all arcs (CSR by tail)  -> X  (arcs with w == d)
+//   ES_BUILD_C all arcs (CSR by head)  -> XC (arcs with w == d)
+//   ES_MERGE   XC plus the updated arcs -> YC
+//   ES_FILTER  YC                       -> XC (arcs with w == d after the update)
+enum { ES_BUILD = 0, ES_BUILD_C = 1, ES_MERGE = 2, ES_FILTER = 3 };
 
-// Dependency-pass modes (see dag_pass).
-enum { MODE_OLD = 0, MODE_NEW = 1, MODE_STATIC = 2, MODE_ROW = 3 };
+// Flags of the restricted dependency pass.
+enum : int32_t { F_VIS = 1, F_B = 2 };
 
 // Sticky status bits of a graph.
 enum : int32_t { ST_SIGMA_OVF = 1, ST_DIST_OVF = 2, ST_ESTAR_CAP = 4 };
@@ -35,9 +39,10 @@ struct GraphCtl {
     int32_t a_count;    // |A| of the update in flight (written by the scan)
     int32_t work_next;  // next item of the persistent per-source kernel
     int32_t max_levels; // deepest Kahn level count seen (statistic)
-    int32_t es_m;       // arcs in the current E* (buffer X)
-    int32_t es_m_tmp;   // arcs in the merged E* (buffer Y)
-    int32_t pad0, pad1;
+    int32_t es_m;       // arcs in X (E* by tail, built by the static pass)
+    int32_t esc_m;      // arcs in XC (E* by head, kept current)
+    int32_t esc_m_tmp;  // arcs in YC (E* by head plus the updated arcs)
+    int32_t pad0;
     unsigned long long changed_pairs;  // statistic of the last update
     unsigned long long affected_last;  // |A| of the last update
     unsigned long long updates;        // updates applied since load
@@ -62,9 +67,11 @@ struct GraphPtrs {
     uint64_t *S;     // n x n path counts
     double *bc_hi, *bc_lo;  // BC as an unevaluated sum hi + lo
     double *bc_delta;       // per-update difference, folded into (hi, lo) at commit
-    // E* as CSR by tail; X holds the current set, Y the merged set of an update.
+    // E* three ways: X by tail (static pass), XC by head (current), YC by
+    // head with the updated arcs merged in (during an update).
     int32_t *x_ptr, *x_src, *x_dst, *x_w;
-    int32_t *y_ptr, *y_src, *y_dst, *y_w;
+    int32_t *xc_ptr, *xc_src, *xc_dst, *xc_w;
+    int32_t *yc_ptr, *yc_src, *yc_dst, *yc_w;
     int32_t *es_cnt;  // n + 1 counts / offsets for rebuilding
     SrcScal *scal;    // n
     int32_t *alist;   // n, affected sources
@@ -73,8 +80,9 @@ struct GraphPtrs {
     int32_t *rvv_D;   // row v'' after the Out phase (n)
     uint64_t *rvv_S, *rvv_H;
     GraphCtl *ctl;
-    // Full arc set as CSR by tail (static recompute and E* build).
+    // Full arc set by tail and by head (static recompute and E* build).
     int32_t *arc_ptr, *arc_dst, *arc_w;
+    int32_t *arcin_ptr, *arcin_src, *arcin_w;
     int64_t arc_m;
 };
 
@@ -95,24 +103,50 @@ struct UpdateJob {
     int32_t u_tail[2 * KMAX], u_head[2 * KMAX], u_w[2 * KMAX];
 };
 
-// Per-workgroup scratch of the per-source kernels.
-struct SlotLayout {
-    size_t indeg, order, lvl, coef, dold, queue2, total;
-};
-
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-__host__ __device__ inline SlotLayout slot_layout(int32_t n) {
-    SlotLayout L;
+// Per-workgroup scratch of the static pass (Kahn levels over a whole DAG).
+struct StaticLayout {
+    size_t indeg, order, lvl, coef, queue2, total;
+};
+
+__host__ __device__ inline StaticLayout static_layout(int32_t n) {
+    StaticLayout L;
     size_t off = 0;
     L.indeg = off;  off += align256(sizeof(int32_t) * (size_t)n);
     L.order = off;  off += align256(sizeof(int32_t) * (size_t)n);
     L.lvl = off;    off += align256(sizeof(int32_t) * ((size_t)n + 1));
     L.coef = off;   off += align256(sizeof(double) * (size_t)n);
-    L.dold = off;   off += align256(sizeof(double) * (size_t)n);
     L.queue2 = off; off += align256(sizeof(int32_t) * (size_t)n);
     L.total = off;
     return L;
+}
+
+// Per-workgroup scratch of the update pass.  flags / outdeg / acc are kept
+// all-zero between sources (each pass clears exactly the entries it used).
+struct UpdateLayout {
+    size_t flags, outdeg, acc, sub, q1, q2, bl_t, bl_d, bl_s, total;
+};
+
+__host__ __device__ inline UpdateLayout update_layout(int32_t n) {
+    UpdateLayout L;
+    size_t off = 0;
+    L.flags = off;  off += align256(sizeof(int32_t) * (size_t)n);
+    L.outdeg = off; off += align256(sizeof(int32_t) * (size_t)n);
+    L.acc = off;    off += align256(sizeof(double) * (size_t)n);
+    L.sub = off;    off += align256(sizeof(int32_t) * (size_t)n);
+    L.q1 = off;     off += align256(sizeof(int32_t) * (size_t)n);
+    L.q2 = off;     off += align256(sizeof(int32_t) * (size_t)n);
+    L.bl_t = off;   off += align256(sizeof(int32_t) * (size_t)n);
+    L.bl_d = off;   off += align256(sizeof(int32_t) * (size_t)n);
+    L.bl_s = off;   off += align256(sizeof(uint64_t) * (size_t)n);
+    L.total = off;
+    return L;
+}
+
+__host__ __device__ inline size_t slot_bytes_for(int32_t n) {
+    const size_t a = static_layout(n).total, b = update_layout(n).total;
+    return a > b ? a : b;
 }
 
 }  // namespace bcinc

@@ -129,6 +129,7 @@ struct bc_ctx {
     int slots = DEFAULT_SLOTS;
     int block = DEFAULT_BLOCK;
     int cu_count = 256;
+    int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
     std::vector<GraphRec *> graphs;
     std::string last_error;
     // staging
@@ -173,7 +174,7 @@ char *misc_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes(); }
 char *slots_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes() + MISC_BYTES; }
 
 int usable_slots(bc_ctx *ctx, int32_t n_max, size_t *slot_bytes) {
-    const size_t sb = slot_layout(n_max).total;
+    const size_t sb = slot_bytes_for(n_max);
     *slot_bytes = sb;
     const uint64_t fixed = ring_bytes() + MISC_BYTES;
     if (ctx->scratch_bytes <= fixed) return 0;
@@ -200,6 +201,8 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     size_t ohi = c.take(8 * (size_t)n), olo = c.take(8 * (size_t)n), odl = c.take(8 * (size_t)n);
     size_t oxp = c.take(4 * ((size_t)n + 1)), oxs = c.take(4 * (size_t)es_cap), oxd = c.take(4 * (size_t)es_cap),
            oxw = c.take(4 * (size_t)es_cap);
+    size_t oxcp = c.take(4 * ((size_t)n + 1)), oxcs = c.take(4 * (size_t)es_cap), oxcd = c.take(4 * (size_t)es_cap),
+           oxcw = c.take(4 * (size_t)es_cap);
     size_t oyp = c.take(4 * ((size_t)n + 1)), oys = c.take(4 * (size_t)es_cap), oyd = c.take(4 * (size_t)es_cap),
            oyw = c.take(4 * (size_t)es_cap);
     size_t ocnt = c.take(4 * ((size_t)n + 1));
@@ -208,6 +211,7 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     size_t orvvd = c.take(4 * (size_t)n), orvvs = c.take(8 * (size_t)n), orvvh = c.take(8 * (size_t)n);
     size_t octl = c.take(sizeof(GraphCtl));
     size_t oap = c.take(4 * ((size_t)n + 1)), oad = c.take(4 * (size_t)arc_cap), oaw = c.take(4 * (size_t)arc_cap);
+    size_t oip = c.take(4 * ((size_t)n + 1)), ois = c.take(4 * (size_t)arc_cap), oiw = c.take(4 * (size_t)arc_cap);
     *total = c.off;
     GraphPtrs P{};
     if (!base) return P;
@@ -222,10 +226,14 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     P.x_src = (int32_t *)(base + oxs);
     P.x_dst = (int32_t *)(base + oxd);
     P.x_w = (int32_t *)(base + oxw);
-    P.y_ptr = (int32_t *)(base + oyp);
-    P.y_src = (int32_t *)(base + oys);
-    P.y_dst = (int32_t *)(base + oyd);
-    P.y_w = (int32_t *)(base + oyw);
+    P.xc_ptr = (int32_t *)(base + oxcp);
+    P.xc_src = (int32_t *)(base + oxcs);
+    P.xc_dst = (int32_t *)(base + oxcd);
+    P.xc_w = (int32_t *)(base + oxcw);
+    P.yc_ptr = (int32_t *)(base + oyp);
+    P.yc_src = (int32_t *)(base + oys);
+    P.yc_dst = (int32_t *)(base + oyd);
+    P.yc_w = (int32_t *)(base + oyw);
     P.es_cnt = (int32_t *)(base + ocnt);
     P.scal = (SrcScal *)(base + osc);
     P.alist = (int32_t *)(base + oal);
@@ -238,6 +246,9 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     P.arc_ptr = (int32_t *)(base + oap);
     P.arc_dst = (int32_t *)(base + oad);
     P.arc_w = (int32_t *)(base + oaw);
+    P.arcin_ptr = (int32_t *)(base + oip);
+    P.arcin_src = (int32_t *)(base + ois);
+    P.arcin_w = (int32_t *)(base + oiw);
     return P;
 }
 
@@ -281,6 +292,7 @@ struct LaunchShape {
     int slots;
     size_t slot_bytes;
     int lds_cap;
+    int32_t n_layout;
 };
 
 // The update kernel sequence for the jobs staged in ring slot r.
@@ -297,7 +309,7 @@ bc_status launch_update_sequence(bc_ctx *ctx, int r, const LaunchShape &L) {
     hipLaunchKernelGGL(k_es_scan<ES_MERGE>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), (size_t)L.lds_cap * 4, st, jobs, nj, slots_dev(ctx),
-                       L.slot_bytes, L.lds_cap);
+                       L.slot_bytes, L.lds_cap, L.n_layout);
     hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_es_scatter<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
@@ -310,7 +322,8 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     L->n_max = 1;
     for (auto &j : jobs) L->n_max = std::max(L->n_max, j.g.n);
     L->njobs = (int)jobs.size();
-    L->slots = usable_slots(ctx, L->n_max, &L->slot_bytes);
+    L->n_layout = ctx->n_layout;
+    L->slots = usable_slots(ctx, ctx->n_layout, &L->slot_bytes);
     if (L->slots < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for one work slot at this n");
     L->lds_cap = lds_cap_for(L->n_max);
     return BC_OK;
@@ -487,10 +500,26 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
     const int64_t m = (int64_t)hd.size();
     if (m > g->arc_cap) return fail(ctx, BC_ERR_CAPACITY, "arc capacity exceeded");
     g->P.arc_m = m;
+    // the same arcs grouped by head (counting sort; tails stay ascending)
+    std::vector<int32_t> ip(n + 1, 0), is((size_t)m), iw((size_t)m);
+    for (int64_t e = 0; e < m; ++e) ip[hd[e] + 1]++;
+    for (int32_t i = 0; i < n; ++i) ip[i + 1] += ip[i];
+    {
+        std::vector<int32_t> fill(ip.begin(), ip.end() - 1);
+        for (int32_t a = 0; a < n; ++a)
+            for (int32_t e = hp[a]; e < hp[a + 1]; ++e) {
+                const int32_t q = fill[hd[e]]++;
+                is[q] = a;
+                iw[q] = hw[e];
+            }
+    }
     HIPCHK(hipMemcpyAsync(g->P.arc_ptr, hp.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(g->P.arcin_ptr, ip.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, ctx->stream));
     if (m) {
         HIPCHK(hipMemcpyAsync(g->P.arc_dst, hd.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(g->P.arc_w, hw.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->P.arcin_src, is.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->P.arcin_w, iw.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
     }
     HIPCHK(hipMemsetAsync(g->P.ctl, 0, sizeof(GraphCtl), ctx->stream));
     HIPCHK(hipMemsetAsync(g->P.bc_delta, 0, 8 * (size_t)n, ctx->stream));
@@ -504,19 +533,26 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
     const UpdateJob *dj = ring_jobs_dev(ctx, r);
     const int32_t *nj = ring_njobs_dev(ctx, r);
     const int slots = std::min<int>(L.slots, n);
+    // slots may still hold another layout's lists (n_layout can just have grown)
+    HIPCHK(hipMemsetAsync(slots_dev(ctx), 0, (size_t)L.slots * L.slot_bytes, ctx->stream));
     const int g_wave = (int)std::min<int64_t>(((int64_t)n * 64 + 255) / 256, 4096);
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
     hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, slots_dev(ctx), L.slot_bytes,
-                       L.lds_cap);
+                       L.lds_cap, L.n_layout);
     hipLaunchKernelGGL(k_es_count<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
     hipLaunchKernelGGL(k_es_scan<ES_BUILD>, dim3(1), dim3(1024), 0, s, dj, nj);
     hipLaunchKernelGGL(k_es_scatter<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
+    hipLaunchKernelGGL(k_es_count<ES_BUILD_C>, dim3(g_wave), dim3(256), 0, s, dj, nj);
+    hipLaunchKernelGGL(k_es_scan<ES_BUILD_C>, dim3(1), dim3(1024), 0, s, dj, nj);
+    hipLaunchKernelGGL(k_es_scatter<ES_BUILD_C>, dim3(g_wave), dim3(256), 0, s, dj, nj);
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
     hipLaunchKernelGGL(k_static, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, slots_dev(ctx), L.slot_bytes,
-                       L.lds_cap);
+                       L.lds_cap, L.n_layout);
     hipLaunchKernelGGL(k_commit, dim3((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048), dim3(256), 0, s, dj, nj, 1);
     HIPCHK(hipGetLastError());
+    // the update kernels expect their per-workgroup flags and sums at zero
+    HIPCHK(hipMemsetAsync(slots_dev(ctx), 0, (size_t)L.slots * L.slot_bytes, s));
     st = ring_release(ctx, r);
     if (st) return st;
     // the host vectors above are read by the copies: finish before they go
@@ -553,7 +589,7 @@ uint64_t bc_graph_bytes(int32_t n, int64_t arc_capacity, int64_t estar_capacity)
 uint64_t bc_scratch_bytes(int32_t n_max, int32_t slots) {
     if (n_max <= 0) return 0;
     if (slots <= 0) slots = DEFAULT_SLOTS;
-    return ring_bytes() + MISC_BYTES + (uint64_t)slots * slot_layout(n_max).total;
+    return ring_bytes() + MISC_BYTES + (uint64_t)slots * slot_bytes_for(n_max);
 }
 
 const char *bc_status_string(bc_status s) {
@@ -684,7 +720,8 @@ bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
     if (ctx->budget && ctx->in_use + arena_bytes > ctx->budget)
         return fail(ctx, BC_ERR_ADMISSION, "graph state would exceed the memory budget");
     size_t sb;
-    if (usable_slots(ctx, n, &sb) < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for this n");
+    if (usable_slots(ctx, std::max(n, ctx->n_layout), &sb) < 1)
+        return fail(ctx, BC_ERR_CAPACITY, "scratch too small for this n");
     // host mirror (validates ids, loops, weights, duplicates)
     GraphRec *g = new GraphRec();
     g->n = n;
@@ -735,6 +772,7 @@ bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
     g->P = carve((char *)arena, n, arc_capacity, estar_capacity, &total);
     g->P.directed = g->directed;
     g->live = true;
+    ctx->n_layout = std::max(ctx->n_layout, n);  // the static pass below re-zeroes every slot
     ctx->graphs.push_back(g);
     ctx->in_use += arena_bytes;
     *out = (bc_graph_id)(ctx->graphs.size() - 1);
@@ -917,15 +955,15 @@ bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id gid, int32_t *a, int32_t *b, int
     GraphRec *g = get_graph(ctx, gid);
     if (!g || !cnt || cap < 0) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
     int32_t m = 0;
-    HIPCHK(hipMemcpyAsync(&m, &g->P.ctl->es_m, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(&m, &g->P.ctl->esc_m, 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     *cnt = m;
     const size_t k = (size_t)std::min<int64_t>(cap, m);
     std::vector<int32_t> ww(k);
     if (k) {
-        if (a) HIPCHK(hipMemcpyAsync(a, g->P.x_src, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
-        if (b) HIPCHK(hipMemcpyAsync(b, g->P.x_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
-        if (w) HIPCHK(hipMemcpyAsync(ww.data(), g->P.x_w, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (a) HIPCHK(hipMemcpyAsync(a, g->P.xc_src, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (b) HIPCHK(hipMemcpyAsync(b, g->P.xc_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (w) HIPCHK(hipMemcpyAsync(ww.data(), g->P.xc_w, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
         if (w)
             for (size_t i = 0; i < k; ++i) w[i] = ww[i];
@@ -943,9 +981,9 @@ bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id gid, int32_t s, int32_t *a, int32_
     if ((st = ring_stage(ctx, r, jobs))) return st;
     unsigned long long *dcnt = (unsigned long long *)misc_dev(ctx);
     HIPCHK(hipMemsetAsync(dcnt, 0, 8, ctx->stream));
-    // DAG(s) is a subset of E*, so the spare E* buffer Y holds it
-    hipLaunchKernelGGL(k_dag_arcs, dim3(1024), dim3(256), 0, ctx->stream, ring_jobs_dev(ctx, r), s, g->P.y_src,
-                       g->P.y_dst, g->es_cap, dcnt);
+    // DAG(s) is a subset of E*, so the spare E* buffer YC holds it
+    hipLaunchKernelGGL(k_dag_arcs, dim3(1024), dim3(256), 0, ctx->stream, ring_jobs_dev(ctx, r), s, g->P.yc_src,
+                       g->P.yc_dst, g->es_cap, dcnt);
     HIPCHK(hipGetLastError());
     if ((st = ring_release(ctx, r))) return st;
     unsigned long long c = 0;
@@ -954,8 +992,8 @@ bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id gid, int32_t s, int32_t *a, int32_
     *cnt = (int64_t)c;
     const size_t k = (size_t)std::min<int64_t>(cap, (int64_t)c);
     if (k) {
-        if (a) HIPCHK(hipMemcpyAsync(a, g->P.y_src, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
-        if (b) HIPCHK(hipMemcpyAsync(b, g->P.y_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (a) HIPCHK(hipMemcpyAsync(a, g->P.yc_src, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        if (b) HIPCHK(hipMemcpyAsync(b, g->P.yc_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     return BC_OK;
@@ -965,19 +1003,20 @@ bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g || s < 0 || s >= g->n || !out) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
     size_t sb;
-    if (usable_slots(ctx, g->n, &sb) < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small");
+    if (usable_slots(ctx, ctx->n_layout, &sb) < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small");
     std::vector<UpdateJob> jobs(1, job_template(g));
     int r;
     bc_status st;
     if ((st = ring_acquire(ctx, &r))) return st;
     if ((st = ring_stage(ctx, r, jobs))) return st;
     const int lds = lds_cap_for(g->n);
+    // the row lands in slot 0's B-list value area, unused by this pass
+    double *row = (double *)(slots_dev(ctx) + update_layout(ctx->n_layout).bl_s);
     hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), (size_t)lds * 4, ctx->stream, ring_jobs_dev(ctx, r), s,
-                       slots_dev(ctx), lds);
+                       slots_dev(ctx), lds, ctx->n_layout, row);
     HIPCHK(hipGetLastError());
     if ((st = ring_release(ctx, r))) return st;
-    const SlotLayout L = slot_layout(g->n);
-    HIPCHK(hipMemcpyAsync(out, slots_dev(ctx) + L.dold, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out, row, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return BC_OK;
 }
@@ -1008,7 +1047,7 @@ bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id gid, bc_update_stats *out) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     out->affected_sources = (int64_t)c.affected_last;
     out->changed_pairs = (int64_t)c.changed_pairs;
-    out->estar_arcs = c.es_m;
+    out->estar_arcs = c.esc_m;
     out->max_levels = c.max_levels;
     out->updates_applied = (int64_t)g->updates;
     return BC_OK;

@@ -3,14 +3,14 @@
 // Update pipeline for a batch of jobs (one update on each of several graphs):
 //   k_scan        affected sources A and Alg 4 scalars (Eq.6, Eq.7)
 //   k_rowv        row v'' of the Out phase (Alg 4 on the reverse graph)
-//   k_es_*        E* candidates: merge the updated arcs into E* (buffer Y)
-//   k_source      per affected source: old DAG dependencies, row update by
-//                 Lemma 2 / Lemma 4, new DAG dependencies, BC difference
-//   k_es_*        E*' = arcs of Y whose weight equals their new distance
+//   k_es_*        E* (by head) plus the updated arcs (buffer YC)
+//   k_source      per affected source: changed targets by Lemma 2 / Lemma 4,
+//                 old and new partial dependencies over them, BC difference
+//   k_es_*        E*' = arcs of YC whose weight equals their new distance
 //   k_commit      BC += difference (compensated), reset counters
 // Static pass (initial state and full recompute, Alg 7):
 //   k_sssp        distances of every source (frontier Bellman-Ford in LDS)
-//   k_es_*        E* = arcs with w(a,b) = d(a,b)
+//   k_es_*        E* = arcs with w(a,b) = d(a,b), by tail (X) and by head (XC)
 //   k_static      per source: path counts in DAG order, dependencies, BC
 #include "bc_device.h"
 
@@ -224,43 +224,52 @@ __global__ void __launch_bounds__(256) k_rowv(const UpdateJob *__restrict__ jobs
 
 // ------------------------------------------------------------ E* rebuild ---
 //
-// E* is a CSR by tail.  Three modes share one wave-per-tail compaction:
-//   ES_MERGE:  Y = X plus the updated arcs (appended to their tails' segments)
-//   ES_FILTER: X = arcs of Y with w == d(a,b) (after the update)
-//   ES_BUILD:  X = arcs of the full arc set with w == d(a,b) (static pass)
-// Arcs whose weight exceeds their distance lie on no shortest path, so they
-// can be dropped; distances only decrease under incremental updates, so E*'
-// is contained in E* plus the updated arcs.
+// E* is kept as segments of arcs keyed by tail (X, built by the static pass
+// for its forward Kahn order) or by head (XC, kept current; the update walks
+// DAG predecessors).  One wave-per-segment compaction serves every mode; see
+// the ES_* enum.  An arc whose weight exceeds its distance lies on no
+// shortest path and is dropped; distances only decrease under incremental
+// updates, so E*' is contained in E* plus the updated arcs (Section 1
+// definition of E*; Alg 6 steps 2-4 use the same test w(u,v) = d(u,v)).
 
 struct EsView {
-    const int32_t *ptr, *dst, *w;
+    const int32_t *ptr, *other, *w;  // input segments; other = the non-key endpoint
+    bool by_head;                    // key endpoint: head (true) or tail (false)
+    bool keep_all, merge;
     int32_t *optr, *osrc, *odst, *ow;
-    int32_t m_limit;  // capacity of the output
-    int32_t *m_out;   // where the total goes
+    int32_t m_limit;
+    int32_t *m_out;
 };
 
 __device__ __forceinline__ EsView es_view(const UpdateJob &J, int mode) {
     EsView e;
-    if (mode == ES_MERGE) {
-        e.ptr = J.g.x_ptr; e.dst = J.g.x_dst; e.w = J.g.x_w;
-        e.optr = J.g.y_ptr; e.osrc = J.g.y_src; e.odst = J.g.y_dst; e.ow = J.g.y_w;
-        e.m_out = &J.g.ctl->es_m_tmp;
-    } else if (mode == ES_FILTER) {
-        e.ptr = J.g.y_ptr; e.dst = J.g.y_dst; e.w = J.g.y_w;
-        e.optr = J.g.x_ptr; e.osrc = J.g.x_src; e.odst = J.g.x_dst; e.ow = J.g.x_w;
-        e.m_out = &J.g.ctl->es_m;
-    } else {
-        e.ptr = J.g.arc_ptr; e.dst = J.g.arc_dst; e.w = J.g.arc_w;
-        e.optr = J.g.x_ptr; e.osrc = J.g.x_src; e.odst = J.g.x_dst; e.ow = J.g.x_w;
-        e.m_out = &J.g.ctl->es_m;
-    }
+    e.keep_all = false;
+    e.merge = false;
     e.m_limit = (int32_t)J.g.es_cap;
+    if (mode == ES_BUILD) {
+        e.ptr = J.g.arc_ptr; e.other = J.g.arc_dst; e.w = J.g.arc_w; e.by_head = false;
+        e.optr = J.g.x_ptr; e.osrc = J.g.x_src; e.odst = J.g.x_dst; e.ow = J.g.x_w;
+        e.m_out = &J.g.ctl->es_m;
+    } else if (mode == ES_BUILD_C) {
+        e.ptr = J.g.arcin_ptr; e.other = J.g.arcin_src; e.w = J.g.arcin_w; e.by_head = true;
+        e.optr = J.g.xc_ptr; e.osrc = J.g.xc_src; e.odst = J.g.xc_dst; e.ow = J.g.xc_w;
+        e.m_out = &J.g.ctl->esc_m;
+    } else if (mode == ES_MERGE) {
+        e.ptr = J.g.xc_ptr; e.other = J.g.xc_src; e.w = J.g.xc_w; e.by_head = true;
+        e.optr = J.g.yc_ptr; e.osrc = J.g.yc_src; e.odst = J.g.yc_dst; e.ow = J.g.yc_w;
+        e.m_out = &J.g.ctl->esc_m_tmp;
+        e.keep_all = true;
+        e.merge = true;
+    } else {
+        e.ptr = J.g.yc_ptr; e.other = J.g.yc_src; e.w = J.g.yc_w; e.by_head = true;
+        e.optr = J.g.xc_ptr; e.osrc = J.g.xc_src; e.odst = J.g.xc_dst; e.ow = J.g.xc_w;
+        e.m_out = &J.g.ctl->esc_m;
+    }
     return e;
 }
 
-__device__ __forceinline__ bool es_keep(const UpdateJob &J, int mode, int32_t a, int32_t b, int32_t w) {
-    if (mode == ES_MERGE) return true;
-    return J.g.D[(size_t)a * J.g.n + b] == w;
+__device__ __forceinline__ bool es_keep(const UpdateJob &J, const EsView &e, int32_t a, int32_t b, int32_t w) {
+    return e.keep_all || J.g.D[(size_t)a * J.g.n + b] == w;
 }
 
 template <int MODE>
@@ -271,39 +280,43 @@ __global__ void __launch_bounds__(256) k_es_count(const UpdateJob *__restrict__ 
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (MODE != ES_BUILD && job_dead(J)) continue;
+        if (MODE >= ES_MERGE && job_dead(J)) continue;
         const EsView e = es_view(J, MODE);
         const int32_t n = J.g.n;
-        for (int64_t a = wave; a < n; a += nwaves) {
-            const int32_t p0 = e.ptr[a], p1 = e.ptr[a + 1];
+        for (int64_t key = wave; key < n; key += nwaves) {
+            const int32_t p0 = e.ptr[key], p1 = e.ptr[key + 1];
             int32_t cnt = 0;
             for (int32_t base = p0; base < p1; base += 64) {
                 const int32_t i = base + lane;
                 bool keep = false;
-                if (i < p1) keep = es_keep(J, MODE, (int32_t)a, e.dst[i], e.w[i]);
+                if (i < p1) {
+                    const int32_t o = e.other[i];
+                    keep = e.by_head ? es_keep(J, e, o, (int32_t)key, e.w[i]) : es_keep(J, e, (int32_t)key, o, e.w[i]);
+                }
                 cnt += (int32_t)__popcll(__ballot(keep));
             }
-            if (MODE == ES_MERGE) {
+            if (e.merge) {
                 for (int32_t base = 0; base < J.n_u; base += 64) {
                     const int32_t k = base + lane;
-                    cnt += (int32_t)__popcll(__ballot(k < J.n_u && J.u_tail[k] == a));
+                    cnt += (int32_t)__popcll(__ballot(k < J.n_u && J.u_head[k] == key));
                 }
             }
-            if (lane == 0) J.g.es_cnt[a] = cnt;
+            if (lane == 0) J.g.es_cnt[key] = cnt;
         }
     }
 }
 
-// One workgroup per job: exclusive scan of the per-tail counts into the
-// output row pointers; the total goes to the control block.  A total above
-// the capacity sets the sticky E* capacity error and the scatter is skipped.
+// One workgroup per job: exclusive scan of the per-segment counts into the
+// output segment pointers; the total goes to the control block.  A total
+// above the capacity sets the sticky E* capacity error and the scatter is
+// skipped.
 template <int MODE>
 __global__ void __launch_bounds__(1024) k_es_scan(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
     __shared__ int32_t sh[40];
     const int j = blockIdx.x;
     if (j >= *njobs_p) return;
     const UpdateJob &J = jobs[j];
-    if (MODE != ES_BUILD && job_dead(J)) return;
+    if (MODE >= ES_MERGE && job_dead(J)) return;
     const EsView e = es_view(J, MODE);
     const int32_t n = J.g.n;
     const int32_t per = (n + blockDim.x - 1) / blockDim.x;
@@ -335,40 +348,42 @@ __global__ void __launch_bounds__(256) k_es_scatter(const UpdateJob *__restrict_
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (MODE == ES_FILTER && job_dead(J)) continue;
+        if (MODE >= ES_MERGE && job_dead(J)) continue;
         const EsView e = es_view(J, MODE);
         const int32_t n = J.g.n;
         if (e.optr[n] > e.m_limit) continue;
-        for (int64_t a = wave; a < n; a += nwaves) {
-            const int32_t p0 = e.ptr[a], p1 = e.ptr[a + 1];
-            int32_t out = e.optr[a];
+        for (int64_t key = wave; key < n; key += nwaves) {
+            const int32_t p0 = e.ptr[key], p1 = e.ptr[key + 1];
+            int32_t out = e.optr[key];
             for (int32_t base = p0; base < p1; base += 64) {
                 const int32_t i = base + lane;
                 bool keep = false;
-                int32_t b = 0, w = 0;
+                int32_t a = 0, b = 0, w = 0;
                 if (i < p1) {
-                    b = e.dst[i];
+                    const int32_t o = e.other[i];
+                    a = e.by_head ? o : (int32_t)key;
+                    b = e.by_head ? (int32_t)key : o;
                     w = e.w[i];
-                    keep = es_keep(J, MODE, (int32_t)a, b, w);
+                    keep = es_keep(J, e, a, b, w);
                 }
                 const uint64_t mask = __ballot(keep);
                 if (keep) {
                     const int32_t o = out + (int32_t)popc_below(mask, lane);
-                    e.osrc[o] = (int32_t)a;
+                    e.osrc[o] = a;
                     e.odst[o] = b;
                     e.ow[o] = w;
                 }
                 out += (int32_t)__popcll(mask);
             }
-            if (MODE == ES_MERGE) {
+            if (e.merge) {
                 for (int32_t base = 0; base < J.n_u; base += 64) {
                     const int32_t k = base + lane;
-                    const bool hit = (k < J.n_u) && (J.u_tail[k] == a);
+                    const bool hit = (k < J.n_u) && (J.u_head[k] == key);
                     const uint64_t mask = __ballot(hit);
                     if (hit) {
                         const int32_t o = out + (int32_t)popc_below(mask, lane);
-                        e.osrc[o] = (int32_t)a;
-                        e.odst[o] = J.u_head[k];
+                        e.osrc[o] = J.u_tail[k];
+                        e.odst[o] = (int32_t)key;
                         e.ow[o] = J.u_w[k];
                     }
                     out += (int32_t)__popcll(mask);
@@ -379,57 +394,71 @@ __global__ void __launch_bounds__(256) k_es_scatter(const UpdateJob *__restrict_
 }
 
 // ------------------------------------------------------------ DAG passes ---
-//
-// One workgroup handles one source s.  DAG(s) is never stored: an arc (a,b)
-// of E* is in DAG(s) iff d(s,a) is finite and d(s,a) + w(a,b) = d(s,b)
-// (Eq.1; Lemma 3 shows the paper's Update-DAG builds exactly this set).
-//   1. in-degrees over the E* arcs (arc-parallel, atomics),
-//   2. Kahn rounds from s: a vertex whose last DAG predecessor is consumed
-//      joins the next frontier, so the frontiers in order form a topological
-//      order with level offsets (any reverse topological order serves the
-//      accumulation, Section 2.1),
-//   3. levels in reverse: each vertex pulls Eq.4 over its successors,
-//      delta(a) = sigma_sa * sum_b (1 + delta(b)) / sigma_sb, summed in the
-//      fixed CSR order, so a recomputation is bit-identical.
-// MODE_OLD keeps delta in dold; MODE_NEW adds delta' - delta to bc_delta;
-// MODE_STATIC also counts paths (sigma_sb = sum of sigma_sa over DAG
-// predecessors, pushed in Kahn order) and adds delta to bc_delta;
-// MODE_ROW writes delta to dold only (introspection).
 
 struct BlockShared {
     int32_t head, tail, next, nlev;
     int32_t item;
-    int32_t flags;
+    int32_t nb;
     int32_t scan[40];
     unsigned long long counter;
 };
 
-struct Slot {
+struct SSlot {
     int32_t *indeg, *order, *lvl, *queue2;
-    double *coef, *dold;
+    double *coef;
 };
 
-__device__ __forceinline__ Slot slot_at(char *base, int32_t n) {
-    const SlotLayout L = slot_layout(n);
-    Slot s;
+__device__ __forceinline__ SSlot sslot_at(char *base, int32_t n) {
+    const StaticLayout L = static_layout(n);
+    SSlot s;
     s.indeg = (int32_t *)(base + L.indeg);
     s.order = (int32_t *)(base + L.order);
     s.lvl = (int32_t *)(base + L.lvl);
     s.queue2 = (int32_t *)(base + L.queue2);
     s.coef = (double *)(base + L.coef);
-    s.dold = (double *)(base + L.dold);
     return s;
 }
 
-template <int MODE>
-__device__ void dag_pass(const int32_t s, const int32_t n, const int32_t *Drow, uint64_t *Srow, const int32_t *ptr,
-                         const int32_t *src, const int32_t *dst, const int32_t *wt, const int32_t m, const Slot &sl,
-                         double *bc_delta, GraphCtl *ctl, BlockShared &sh) {
+struct USlot {
+    int32_t *flags, *outdeg, *sub, *q1, *q2, *bl_t, *bl_d;
+    double *acc;
+    uint64_t *bl_s;
+};
+
+__device__ __forceinline__ USlot uslot_at(char *base, int32_t n) {
+    const UpdateLayout L = update_layout(n);
+    USlot u;
+    u.flags = (int32_t *)(base + L.flags);
+    u.outdeg = (int32_t *)(base + L.outdeg);
+    u.acc = (double *)(base + L.acc);
+    u.sub = (int32_t *)(base + L.sub);
+    u.q1 = (int32_t *)(base + L.q1);
+    u.q2 = (int32_t *)(base + L.q2);
+    u.bl_t = (int32_t *)(base + L.bl_t);
+    u.bl_d = (int32_t *)(base + L.bl_d);
+    u.bl_s = (uint64_t *)(base + L.bl_s);
+    return u;
+}
+
+// Whole-DAG pass of the static computation for one source (one workgroup).
+// An arc (a,b) of E* is in DAG(s) iff d(s,a) is finite and
+// d(s,a) + w(a,b) = d(s,b) (Eq.1).
+//   1. in-degrees over the E* arcs (arc-parallel, atomics),
+//   2. Kahn rounds from s: a vertex whose last DAG predecessor is consumed
+//      joins the next frontier, so the frontiers in order form a topological
+//      order with level offsets (any topological order serves, Section 2.1);
+//      path counts are pushed along the way, sigma_sb = sum of sigma_sa over
+//      the DAG predecessors a (Alg 6, step 7),
+//   3. levels in reverse: each vertex pulls Eq.4 over its successors,
+//      delta(a) = sigma_sa * sum_b (1 + delta(b)) / sigma_sb, and BC(a) gets
+//      delta(a) for a != s (Alg 1).
+__device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t *Drow, uint64_t *Srow,
+                                const int32_t *ptr, const int32_t *src, const int32_t *dst, const int32_t *wt,
+                                const int32_t m, const SSlot &sl, double *bc_delta, GraphCtl *ctl, BlockShared &sh) {
     const int tid = threadIdx.x, bs = blockDim.x;
     for (int32_t i = tid; i < n; i += bs) {
         sl.indeg[i] = 0;
-        if (MODE == MODE_OLD || MODE == MODE_ROW) sl.dold[i] = 0.0;
-        if (MODE == MODE_STATIC) Srow[i] = (i == s) ? 1ull : 0ull;
+        Srow[i] = (i == s) ? 1ull : 0ull;
     }
     __syncthreads();
     for (int32_t i = tid; i < m; i += bs) {
@@ -456,16 +485,14 @@ __device__ void dag_pass(const int32_t s, const int32_t n, const int32_t *Drow, 
         for (int32_t idx = lo + tid; idx < hi; idx += bs) {
             const int32_t a = sl.order[idx];
             const int32_t da = Drow[a];
-            const uint64_t sa = (MODE == MODE_STATIC) ? Srow[a] : 0ull;
+            const uint64_t sa = Srow[a];
             const int32_t e1 = ptr[a + 1];
             for (int32_t e = ptr[a]; e < e1; ++e) {
                 const int32_t b = dst[e];
                 const int32_t db = Drow[b];
                 if (db != INF32 && (int64_t)da + wt[e] == (int64_t)db) {
-                    if (MODE == MODE_STATIC) {
-                        const uint64_t old = atomicAdd((unsigned long long *)&Srow[b], (unsigned long long)sa);
-                        if (old + sa < old) ovf = true;
-                    }
+                    const uint64_t old = atomicAdd((unsigned long long *)&Srow[b], (unsigned long long)sa);
+                    if (old + sa < old) ovf = true;
                     if (atomicSub(&sl.indeg[b], 1) == 1) {
                         const int32_t pos = atomicAdd(&sh.next, 1);
                         sl.order[pos] = b;
@@ -481,7 +508,7 @@ __device__ void dag_pass(const int32_t s, const int32_t n, const int32_t *Drow, 
         }
         __syncthreads();
     }
-    if (MODE == MODE_STATIC && ovf) atomicOr(&ctl->status, ST_SIGMA_OVF);
+    if (ovf) atomicOr(&ctl->status, ST_SIGMA_OVF);
     const int32_t nlev = sh.nlev;
     if (tid == 0) {
         sl.lvl[nlev] = sh.tail;
@@ -503,136 +530,245 @@ __device__ void dag_pass(const int32_t s, const int32_t n, const int32_t *Drow, 
             const double sa = (double)Srow[a];
             const double dl = sa * acc;
             sl.coef[a] = (1.0 + dl) / sa;
-            if (a == s) continue;
-            if (MODE == MODE_OLD || MODE == MODE_ROW) {
-                sl.dold[a] = dl;
-            } else if (MODE == MODE_NEW) {
-                const double diff = dl - sl.dold[a];
-                if (diff != 0.0) atomicAdd(&bc_delta[a], diff);
-            } else {
-                if (dl != 0.0) atomicAdd(&bc_delta[a], dl);
-            }
+            if (a != s && dl != 0.0) atomicAdd(&bc_delta[a], dl);
         }
         __syncthreads();
     }
 }
 
-// Row update of one affected source (the all-pairs step of Alg 3 restricted
-// to row s).  In phase: Lemma 4 with the old row v.  Out phase (if E_o is not
-// empty): Lemma 4 on G'_R, D = d'(s,v) + d''(v,t), with row v''.  sigma is
-// read only where a distance test says the pair may change, and only changed
-// elements are written.
-__device__ void row_update(const UpdateJob &J, const int32_t s, int32_t *Drow_lds, const bool lds, BlockShared &sh) {
+// Partial dependency of source s over a target set B (one workgroup):
+//   delta_B(x) = sum_{t in B} delta_st(x)
+//              = sum_{w : x in P_s(w)} sigma_sx / sigma_sw * ([w in B] + delta_B(w)),
+// Eq.4 with the indicator of B in place of 1.  It is non-zero only on the
+// ancestors of B in DAG(s), so only that sub-DAG is visited:
+//   1. backward BFS from B over DAG predecessor arcs (E* by head, Eq.1),
+//      counting each sub-DAG vertex's successors inside the sub-DAG,
+//   2. Kahn from the sub-DAG's sinks (a reverse topological order, which
+//      serves the accumulation, Section 2.1): each vertex pushes its term to
+//      its predecessors once all its successors have pushed to it.
+// Targets whose d(s,t) and sigma_st do not change keep the same set of
+// shortest paths, so delta_st is unchanged for them and the BC difference of
+// source s is delta'_B - delta_B with B the changed targets (Alg 3 re-runs
+// the whole accumulation; both give the same BC).
+// OUT_ROW: delta_B goes to out[x] (introspection); otherwise
+// bc_delta[x] += sign * delta_B(x) for x != s.
+template <bool OUT_ROW>
+__device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t *Drow, const uint64_t *Srow,
+                                const int32_t *cptr, const int32_t *csrc, const int32_t *cw, const int32_t *Bt,
+                                const int32_t nB, const USlot &u, const double sign, double *out,
+                                BlockShared &sh) {
     const int tid = threadIdx.x, bs = blockDim.x;
-    const int32_t n = J.g.n;
-    int32_t *Dg = J.g.D + (size_t)s * n;
-    uint64_t *Sg = J.g.S + (size_t)s * n;
-    const int32_t *Drow = lds ? Drow_lds : Dg;
-    const SrcScal sc = J.g.scal[s];
-    const bool same = (sc.flags & 1) != 0;
-    const bool has_out = J.n_out > 0;
-    const int32_t *rvD = J.row_v_D;
-    const uint64_t *rvS = J.row_v_S;
-    bool ovf_s = false, ovf_d = false;
-    uint32_t changed = 0;
-    for (int32_t t = tid; t < n; t += bs) {
-        const int32_t d0 = Drow[t];
-        int32_t d = d0;
-        uint64_t sg = 0;
-        bool sg_known = false;
-        int64_t c;
-        if (in_rule(d0, sc.dv, rvD[t], c)) {
-            if (c >= INF32) {
-                ovf_d = true;
-            } else if (c < d0) {
-                d = (int32_t)c;
-                sg = mul_chk(sc.sv, rvS[t], ovf_s);
+    if (tid == 0) sh.next = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < nB; i += bs) {
+        const int32_t t = Bt[i];
+        if (t == s || Drow[t] == INF32) continue;
+        u.flags[t] = F_VIS | F_B;
+        u.sub[atomicAdd(&sh.next, 1)] = t;
+    }
+    __syncthreads();
+    int32_t lo = 0, hi = sh.next;
+    __syncthreads();
+    while (lo < hi) {
+        for (int32_t idx = lo + tid; idx < hi; idx += bs) {
+            const int32_t x = u.sub[idx];
+            const int32_t dx = Drow[x];
+            const int32_t e1 = cptr[x + 1];
+            for (int32_t e = cptr[x]; e < e1; ++e) {
+                const int32_t a = csrc[e];
+                const int32_t da = Drow[a];
+                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)dx) {
+                    atomicAdd(&u.outdeg[a], 1);
+                    if ((atomicOr(&u.flags[a], F_VIS) & F_VIS) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
+                }
+            }
+        }
+        __syncthreads();
+        lo = hi;
+        hi = sh.next;
+        __syncthreads();
+    }
+    const int32_t nsub = hi;
+    if (tid == 0) sh.tail = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < nsub; i += bs) {
+        const int32_t x = u.sub[i];
+        if (u.outdeg[x] == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
+    }
+    __syncthreads();
+    int32_t qn = sh.tail;
+    int32_t *qa = u.q1, *qb = u.q2;
+    __syncthreads();
+    while (qn > 0) {
+        if (tid == 0) sh.tail = 0;
+        __syncthreads();
+        for (int32_t idx = tid; idx < qn; idx += bs) {
+            const int32_t x = qa[idx];
+            const double ax = u.acc[x];
+            if (x != s && ax != 0.0) {
+                if (OUT_ROW) out[x] = ax;
+                else atomicAdd(&out[x], sign * ax);
+            }
+            const double val = ((u.flags[x] & F_B) ? 1.0 : 0.0) + ax;
+            const double sx = (double)Srow[x];
+            const int32_t dx = Drow[x];
+            const int32_t e1 = cptr[x + 1];
+            for (int32_t e = cptr[x]; e < e1; ++e) {
+                const int32_t a = csrc[e];
+                const int32_t da = Drow[a];
+                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)dx) {
+                    atomicAdd(&u.acc[a], (double)Srow[a] / sx * val);
+                    if (atomicSub(&u.outdeg[a], 1) == 1) qb[atomicAdd(&sh.tail, 1)] = a;
+                }
+            }
+        }
+        __syncthreads();
+        qn = sh.tail;
+        int32_t *tmp = qa;
+        qa = qb;
+        qb = tmp;
+        __syncthreads();
+    }
+    for (int32_t i = tid; i < nsub; i += bs) {
+        const int32_t x = u.sub[i];
+        u.flags[x] = 0;
+        u.outdeg[x] = 0;
+        u.acc[x] = 0.0;
+    }
+    __syncthreads();
+}
+
+// New (d, sigma) of pair (s,t) by Lemma 4 In phase, then (if E_o is not
+// empty) Lemma 4 on G'_R with D = d'(s,v) + d''(v,t) and row v''.  sigma is
+// read only where a distance test says the pair may change.  Returns true if
+// the pair changes.
+__device__ __forceinline__ bool pair_update(const UpdateJob &J, const SrcScal &sc, const bool same, const bool has_out,
+                                            const int32_t t, const int32_t d0, const uint64_t *Sg, int32_t &d_out,
+                                            uint64_t &s_out, bool &ovf_s, bool &ovf_d) {
+    int32_t d = d0;
+    uint64_t sg = 0;
+    bool sg_known = false;
+    int64_t c;
+    const int32_t rvd = J.row_v_D[t];
+    if (in_rule(d0, sc.dv, rvd, c)) {
+        if (c >= INF32) {
+            ovf_d = true;
+        } else if (c < d0) {
+            d = (int32_t)c;
+            sg = mul_chk(sc.sv, J.row_v_S[t], ovf_s);
+            sg_known = true;
+        } else {
+            const uint64_t add = mul_chk(same ? sc.hv : sc.sv, J.row_v_S[t], ovf_s);
+            if (add != 0) {
+                sg = add_chk(Sg[t], add, ovf_s);
                 sg_known = true;
-            } else {
-                const uint64_t add = mul_chk(same ? sc.hv : sc.sv, rvS[t], ovf_s);
-                if (add != 0) {
-                    sg = add_chk(Sg[t], add, ovf_s);
-                    sg_known = true;
-                }
             }
-        }
-        if (has_out) {
-            const int32_t dvv = J.g.rvv_D[t];
-            int64_t c2;
-            if (in_rule(d, sc.dv, dvv, c2)) {
-                if (c2 >= INF32) {
-                    ovf_d = true;
-                } else if (c2 < d) {
-                    d = (int32_t)c2;
-                    sg = mul_chk(sc.sv, J.g.rvv_S[t], ovf_s);
-                    sg_known = true;
-                } else {
-                    const uint64_t mult = (dvv == rvD[t]) ? J.g.rvv_H[t] : J.g.rvv_S[t];
-                    const uint64_t add = mul_chk(sc.sv, mult, ovf_s);
-                    if (add != 0) {
-                        sg = add_chk(sg_known ? sg : Sg[t], add, ovf_s);
-                        sg_known = true;
-                    }
-                }
-            }
-        }
-        if (sg_known) {
-            Sg[t] = sg;
-            if (d != d0) {
-                Dg[t] = d;
-                if (lds) Drow_lds[t] = d;
-            }
-            ++changed;
         }
     }
-    if (ovf_s) atomicOr(&J.g.ctl->status, ST_SIGMA_OVF);
-    if (ovf_d) atomicOr(&J.g.ctl->status, ST_DIST_OVF);
-    if (changed) atomicAdd(&sh.counter, (unsigned long long)changed);
+    if (has_out) {
+        const int32_t dvv = J.g.rvv_D[t];
+        int64_t c2;
+        if (in_rule(d, sc.dv, dvv, c2)) {
+            if (c2 >= INF32) {
+                ovf_d = true;
+            } else if (c2 < d) {
+                d = (int32_t)c2;
+                sg = mul_chk(sc.sv, J.g.rvv_S[t], ovf_s);
+                sg_known = true;
+            } else {
+                const uint64_t mult = (dvv == rvd) ? J.g.rvv_H[t] : J.g.rvv_S[t];
+                const uint64_t add = mul_chk(sc.sv, mult, ovf_s);
+                if (add != 0) {
+                    sg = add_chk(sg_known ? sg : Sg[t], add, ovf_s);
+                    sg_known = true;
+                }
+            }
+        }
+    }
+    d_out = d;
+    s_out = sg;
+    return sg_known;
 }
 
 // Persistent per-source kernel: workgroups pull (job, affected source)
 // items from a device counter until every job's list is empty.  Each item:
-// old dependencies on E* (buffer X) from the old row, row update, new
-// dependencies on the merged E* (buffer Y) from the new row, BC difference.
+//   1. scan row s (staged in LDS) and list the changed targets B_s with their
+//      new (d, sigma) (the all-pairs step of Alg 3, restricted to row s),
+//   2. old partial dependency over B_s (E* by head, old row), sign -1,
+//   3. write the changed pairs (only those) to D and sigma,
+//   4. new partial dependency over B_s (merged E*, new row), sign +1.
+// Every workgroup's slot is laid out for the context-wide n_layout (the largest
+// graph), so the zero-kept arrays sit at the same place for every job.
 __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
-                                                 char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap) {
+                                                 char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
+                                                 int32_t n_layout) {
     extern __shared__ int32_t lds_row[];
     __shared__ BlockShared sh;
     const int njobs = *njobs_p;
+    const int tid = threadIdx.x, bs = blockDim.x;
     char *slot_base = scratch + (size_t)blockIdx.x * slot_bytes;
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
         const int32_t n = J.g.n;
         const bool lds = n <= lds_cap;
-        const Slot sl = slot_at(slot_base, n);
+        const USlot u = uslot_at(slot_base, n_layout);
         GraphCtl *ctl = J.g.ctl;
         if (job_dead(J)) continue;
         const int32_t count = *(volatile int32_t *)&ctl->a_count;
-        if (threadIdx.x == 0) sh.counter = 0;
+        const bool has_out = J.n_out > 0;
+        if (tid == 0) sh.counter = 0;
+        bool ovf_s = false, ovf_d = false;
         for (;;) {
             __syncthreads();
-            if (threadIdx.x == 0) sh.item = atomicAdd(&ctl->work_next, 1);
+            if (tid == 0) {
+                sh.item = atomicAdd(&ctl->work_next, 1);
+                sh.nb = 0;
+            }
             __syncthreads();
             const int32_t item = sh.item;
             if (item >= count) break;
             const int32_t s = J.g.alist[item];
             int32_t *Dg = J.g.D + (size_t)s * n;
             uint64_t *Sg = J.g.S + (size_t)s * n;
-            const int32_t *Drow = Dg;
+            const SrcScal sc = J.g.scal[s];
+            const bool same = (sc.flags & 1) != 0;
+            int32_t *Drow = Dg;
             if (lds) {
-                for (int32_t t = threadIdx.x; t < n; t += blockDim.x) lds_row[t] = Dg[t];
-                __syncthreads();
+                for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
                 Drow = lds_row;
             }
-            dag_pass<MODE_OLD>(s, n, Drow, Sg, J.g.x_ptr, J.g.x_src, J.g.x_dst, J.g.x_w, ctl->es_m, sl, J.g.bc_delta,
-                               ctl, sh);
-            row_update(J, s, lds_row, lds, sh);
             __syncthreads();
-            dag_pass<MODE_NEW>(s, n, Drow, Sg, J.g.y_ptr, J.g.y_src, J.g.y_dst, J.g.y_w, ctl->es_m_tmp, sl,
-                               J.g.bc_delta, ctl, sh);
+            for (int32_t t = tid; t < n; t += bs) {
+                int32_t d;
+                uint64_t sg;
+                if (pair_update(J, sc, same, has_out, t, Drow[t], Sg, d, sg, ovf_s, ovf_d)) {
+                    const int32_t pos = atomicAdd(&sh.nb, 1);
+                    u.bl_t[pos] = t;
+                    u.bl_d[pos] = d;
+                    u.bl_s[pos] = sg;
+                }
+            }
+            __syncthreads();
+            const int32_t nb = sh.nb;
+            if (nb == 0) continue;
+            restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, u.bl_t, nb, u, -1.0, J.g.bc_delta,
+                                   sh);
+            for (int32_t i = tid; i < nb; i += bs) {
+                const int32_t t = u.bl_t[i];
+                const int32_t d = u.bl_d[i];
+                Sg[t] = u.bl_s[i];
+                Dg[t] = d;
+                if (lds) lds_row[t] = d;
+            }
+            __syncthreads();
+            restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, u.bl_t, nb, u, 1.0, J.g.bc_delta,
+                                   sh);
+            if (tid == 0) sh.counter += (unsigned long long)nb;
         }
+        if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
+        if (ovf_d) atomicOr(&ctl->status, ST_DIST_OVF);
         __syncthreads();
-        if (threadIdx.x == 0 && sh.counter) atomicAdd(&ctl->changed_pairs, sh.counter);
+        if (tid == 0 && sh.counter) atomicAdd(&ctl->changed_pairs, sh.counter);
     }
 }
 
@@ -690,13 +826,13 @@ __global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__res
 // (atomicMin relaxations; a vertex improved in a round is queued once for
 // the next round).  Positive weights make it converge to d(s,.).
 __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ jobs, char *__restrict__ scratch,
-                                               size_t slot_bytes, int32_t lds_cap) {
+                                               size_t slot_bytes, int32_t lds_cap, int32_t n_layout) {
     extern __shared__ int32_t lds_row[];
     __shared__ BlockShared sh;
     const UpdateJob &J = jobs[0];
     const int32_t n = J.g.n;
     const bool lds = n <= lds_cap;
-    const Slot sl = slot_at(scratch + (size_t)blockIdx.x * slot_bytes, n);
+    const SSlot sl = sslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
     GraphCtl *ctl = J.g.ctl;
     const int tid = threadIdx.x, bs = blockDim.x;
     bool ovf = false;
@@ -763,13 +899,13 @@ __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ job
 // order (sigma_sb = sum over DAG predecessors a of sigma_sa, Alg 6 step 7),
 // then the dependency pull, BC += delta (Alg 1 line 5).
 __global__ void __launch_bounds__(1024) k_static(const UpdateJob *__restrict__ jobs, char *__restrict__ scratch,
-                                                 size_t slot_bytes, int32_t lds_cap) {
+                                                 size_t slot_bytes, int32_t lds_cap, int32_t n_layout) {
     extern __shared__ int32_t lds_row[];
     __shared__ BlockShared sh;
     const UpdateJob &J = jobs[0];
     const int32_t n = J.g.n;
     const bool lds = n <= lds_cap;
-    const Slot sl = slot_at(scratch + (size_t)blockIdx.x * slot_bytes, n);
+    const SSlot sl = sslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
     GraphCtl *ctl = J.g.ctl;
     if (job_dead(J)) return;
     for (;;) {
@@ -785,8 +921,8 @@ __global__ void __launch_bounds__(1024) k_static(const UpdateJob *__restrict__ j
             __syncthreads();
             Drow = lds_row;
         }
-        dag_pass<MODE_STATIC>(s, n, Drow, J.g.S + (size_t)s * n, J.g.x_ptr, J.g.x_src, J.g.x_dst, J.g.x_w,
-                              ctl->es_m, sl, J.g.bc_delta, ctl, sh);
+        static_dag_pass(s, n, Drow, J.g.S + (size_t)s * n, J.g.x_ptr, J.g.x_src, J.g.x_dst, J.g.x_w, ctl->es_m, sl,
+                        J.g.bc_delta, ctl, sh);
     }
 }
 
@@ -797,25 +933,31 @@ __global__ void k_reset_work(GraphCtl *ctl) {
 
 // ------------------------------------------------------------ introspection
 
-// Dependency row of one source by the same level-ordered accumulation.
+// Dependency row of one source, delta_s.(x) = sum over all reachable t of
+// delta_st(x), by the same restricted pass with B = every reachable t != s.
+// Writes the row to out_row (n values, 0 at s and at unreachable x).
 __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict__ jobs, int32_t s, char *__restrict__ scratch,
-                                                    int32_t lds_cap) {
+                                                    int32_t lds_cap, int32_t n_layout, double *out_row) {
     extern __shared__ int32_t lds_row[];
     __shared__ BlockShared sh;
     const UpdateJob &J = jobs[0];
     const int32_t n = J.g.n;
     const bool lds = n <= lds_cap;
-    const Slot sl = slot_at(scratch, n);
+    const USlot u = uslot_at(scratch, n_layout);
     if (job_dead(J)) return;
-    int32_t *Dg = J.g.D + (size_t)s * n;
+    const int32_t *Dg = J.g.D + (size_t)s * n;
     const int32_t *Drow = Dg;
-    if (lds) {
-        for (int32_t t = threadIdx.x; t < n; t += blockDim.x) lds_row[t] = Dg[t];
-        __syncthreads();
-        Drow = lds_row;
+    if (threadIdx.x == 0) sh.nb = 0;
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < n; t += blockDim.x) {
+        out_row[t] = 0.0;
+        if (lds) lds_row[t] = Dg[t];
+        if (t != s && Dg[t] != INF32) u.bl_t[atomicAdd(&sh.nb, 1)] = t;
     }
-    dag_pass<MODE_ROW>(s, n, Drow, J.g.S + (size_t)s * n, J.g.x_ptr, J.g.x_src, J.g.x_dst, J.g.x_w, J.g.ctl->es_m, sl,
-                       nullptr, J.g.ctl, sh);
+    if (lds) Drow = lds_row;
+    __syncthreads();
+    restricted_pass<true>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, u.bl_t, sh.nb, u, 1.0,
+                          out_row, sh);
 }
 
 // Arcs of DAG(s): the predicate of Eq.1 over E*.
@@ -823,12 +965,12 @@ __global__ void k_dag_arcs(const UpdateJob *__restrict__ jobs, int32_t s, int32_
                            unsigned long long *cnt) {
     const UpdateJob &J = jobs[0];
     if (job_dead(J)) return;
-    const int32_t n = J.g.n, m = J.g.ctl->es_m;
+    const int32_t n = J.g.n, m = J.g.ctl->esc_m;
     const int32_t *Drow = J.g.D + (size_t)s * n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = J.g.x_src[i], b = J.g.x_dst[i];
+        const int32_t a = J.g.xc_src[i], b = J.g.xc_dst[i];
         const int32_t da = Drow[a], db = Drow[b];
-        if (da != INF32 && db != INF32 && (int64_t)da + J.g.x_w[i] == (int64_t)db) {
+        if (da != INF32 && db != INF32 && (int64_t)da + J.g.xc_w[i] == (int64_t)db) {
             const unsigned long long k = atomicAdd(cnt, 1ull);
             if ((int64_t)k < cap) {
                 out_a[k] = a;

@@ -28,8 +28,8 @@ namespace {
 constexpr int RING = 4;            // job staging slots in flight
 constexpr int JCAP = 256;          // jobs per staging slot
 constexpr size_t MISC_BYTES = 4096;
-constexpr int DEFAULT_SLOTS = 256; // one persistent workgroup per CU of an MI355X
-constexpr int DEFAULT_BLOCK = 512;
+constexpr int DEFAULT_SLOTS = 2048; // 8 persistent single-wave workgroups per CU of an MI355X
+constexpr int DEFAULT_BLOCK = 64;   // one wave per affected source
 constexpr int64_t W_MAX = (int64_t)INF32 - 1;
 
 size_t ring_slot_bytes() { return align256(256 + sizeof(UpdateJob) * JCAP); }
@@ -130,6 +130,7 @@ struct bc_ctx {
     int block = DEFAULT_BLOCK;
     int cu_count = 256;
     int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
+    int32_t src_lds_max = 8192;  // per-source kernel stages rows up to this n in LDS
     std::vector<GraphRec *> graphs;
     std::string last_error;
     // staging
@@ -183,6 +184,9 @@ int usable_slots(bc_ctx *ctx, int32_t n_max, size_t *slot_bytes) {
 }
 
 int lds_cap_for(int32_t n_max) { return std::min<int32_t>(n_max, LDS_ROW_MAX); }
+
+// Dynamic LDS of k_source / k_delta_row: staged row plus 20 bytes per thread.
+size_t source_lds_bytes(int lds_cap, int block) { return align256((size_t)lds_cap * 4) + 20 * (size_t)block; }
 
 // Arena layout of one graph (every piece 256-byte aligned).
 struct Carve {
@@ -291,7 +295,8 @@ struct LaunchShape {
     int njobs;
     int slots;
     size_t slot_bytes;
-    int lds_cap;
+    int lds_cap;      // static pass: rows up to this size are staged in LDS
+    int src_lds_cap;  // per-source kernel: rows up to this size are staged in LDS
     int32_t n_layout;
 };
 
@@ -308,8 +313,8 @@ bc_status launch_update_sequence(bc_ctx *ctx, int r, const LaunchShape &L) {
     hipLaunchKernelGGL(k_es_count<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_es_scan<ES_MERGE>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), (size_t)L.lds_cap * 4, st, jobs, nj, slots_dev(ctx),
-                       L.slot_bytes, L.lds_cap, L.n_layout);
+    hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), source_lds_bytes(L.src_lds_cap, ctx->block), st, jobs,
+                       nj, slots_dev(ctx), L.slot_bytes, L.src_lds_cap, L.n_layout);
     hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
     hipLaunchKernelGGL(k_es_scatter<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
@@ -326,6 +331,7 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     L->slots = usable_slots(ctx, ctx->n_layout, &L->slot_bytes);
     if (L->slots < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for one work slot at this n");
     L->lds_cap = lds_cap_for(L->n_max);
+    L->src_lds_cap = std::min<int32_t>(L->n_max, ctx->src_lds_max);
     return BC_OK;
 }
 
@@ -563,13 +569,21 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
     return BC_OK;
 }
 
-bc_status set_lds_limits(bc_ctx *ctx) {
-    const int bytes = LDS_ROW_MAX * 4;
-    HIPCHK(hipFuncSetAttribute((const void *)k_source, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-    HIPCHK(hipFuncSetAttribute((const void *)k_sssp, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-    HIPCHK(hipFuncSetAttribute((const void *)k_static, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-    HIPCHK(hipFuncSetAttribute((const void *)k_delta_row, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+bc_status set_lds_limit(bc_ctx *ctx, const void *fn) {
+    hipFuncAttributes attr;
+    HIPCHK(hipFuncGetAttributes(&attr, fn));
+    // all of a gfx950 workgroup's 160 KiB of LDS, less what the kernel declares statically
+    const int bytes = 160 * 1024 - (int)attr.sharedSizeBytes;
+    HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return BC_OK;
+}
+
+bc_status set_lds_limits(bc_ctx *ctx) {
+    bc_status st;
+    if ((st = set_lds_limit(ctx, (const void *)k_source))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_sssp))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_static))) return st;
+    return set_lds_limit(ctx, (const void *)k_delta_row);
 }
 
 }  // namespace
@@ -1009,11 +1023,11 @@ bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
     bc_status st;
     if ((st = ring_acquire(ctx, &r))) return st;
     if ((st = ring_stage(ctx, r, jobs))) return st;
-    const int lds = lds_cap_for(g->n);
+    const int lds = std::min<int32_t>(g->n, 32768);  // row plus 20 KiB of expansion arrays fit in 160 KiB
     // the row lands in slot 0's B-list value area, unused by this pass
     double *row = (double *)(slots_dev(ctx) + update_layout(ctx->n_layout).bl_s);
-    hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), (size_t)lds * 4, ctx->stream, ring_jobs_dev(ctx, r), s,
-                       slots_dev(ctx), lds, ctx->n_layout, row);
+    hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), source_lds_bytes(lds, 1024), ctx->stream,
+                       ring_jobs_dev(ctx, r), s, slots_dev(ctx), lds, ctx->n_layout, row);
     HIPCHK(hipGetLastError());
     if ((st = ring_release(ctx, r))) return st;
     HIPCHK(hipMemcpyAsync(out, row, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));

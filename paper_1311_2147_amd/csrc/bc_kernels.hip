@@ -536,6 +536,36 @@ __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t 
     }
 }
 
+// Arc-parallel expansion helpers: the in-arcs of a list of vertices are
+// flattened with a block-wide scan of their in-degrees, so every lane takes
+// one arc and all predecessor loads of a level are in flight together.
+struct ExpandShared {
+    int32_t *off, *vtx, *beg;
+    double *val;
+};
+
+// Dynamic LDS of the per-source kernels: the staged row (4 * lds_cap bytes)
+// followed by the expansion arrays (20 bytes per thread).
+__device__ __forceinline__ ExpandShared expand_at(char *dyn, int32_t lds_cap) {
+    ExpandShared es;
+    char *p = dyn + align256((size_t)lds_cap * 4);
+    es.val = (double *)p;
+    es.off = (int32_t *)(p + 8 * blockDim.x);
+    es.vtx = es.off + blockDim.x;
+    es.beg = es.vtx + blockDim.x;
+    return es;
+}
+
+__device__ __forceinline__ int32_t find_owner(const ExpandShared &es, int32_t nv, int32_t j) {
+    int32_t lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (es.off[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Partial dependency of source s over a target set B (one workgroup):
 //   delta_B(x) = sum_{t in B} delta_st(x)
 //              = sum_{w : x in P_s(w)} sigma_sx / sigma_sw * ([w in B] + delta_B(w)),
@@ -551,12 +581,13 @@ __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t 
 // source s is delta'_B - delta_B with B the changed targets (Alg 3 re-runs
 // the whole accumulation; both give the same BC).
 // OUT_ROW: delta_B goes to out[x] (introspection); otherwise
-// bc_delta[x] += sign * delta_B(x) for x != s.
+// out[x] += sign * delta_B(x) for x != s (out = the BC difference).
 template <bool OUT_ROW>
-__device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t *Drow, const uint64_t *Srow,
-                                const int32_t *cptr, const int32_t *csrc, const int32_t *cw, const int32_t *Bt,
-                                const int32_t nB, const USlot &u, const double sign, double *out,
-                                BlockShared &sh) {
+__device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Srow,
+                                const int32_t *__restrict__ cptr, const int32_t *__restrict__ csrc,
+                                const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
+                                const USlot &u, const double sign, double *out, BlockShared &sh,
+                                const ExpandShared &es) {
     const int tid = threadIdx.x, bs = blockDim.x;
     if (tid == 0) sh.next = 0;
     __syncthreads();
@@ -569,26 +600,42 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
     __syncthreads();
     int32_t lo = 0, hi = sh.next;
     __syncthreads();
+    // 1. backward BFS, one level per round, arc-parallel within a round
     while (lo < hi) {
-        for (int32_t idx = lo + tid; idx < hi; idx += bs) {
-            const int32_t x = u.sub[idx];
-            const int32_t dx = Drow[x];
-            const int32_t e1 = cptr[x + 1];
-            for (int32_t e = cptr[x]; e < e1; ++e) {
+        for (int32_t c = lo; c < hi; c += bs) {
+            const int32_t idx = c + tid;
+            int32_t x = 0, b0 = 0, deg = 0;
+            if (idx < hi) {
+                x = u.sub[idx];
+                b0 = cptr[x];
+                deg = cptr[x + 1] - b0;
+            }
+            int32_t total;
+            const int32_t off = block_excl_scan(deg, sh.scan, total);
+            es.off[tid] = off;
+            es.vtx[tid] = x;
+            es.beg[tid] = b0;
+            __syncthreads();
+            const int32_t nv = min(bs, hi - c);
+            for (int32_t j = tid; j < total; j += bs) {
+                const int32_t i = find_owner(es, nv, j);
+                const int32_t xv = es.vtx[i];
+                const int32_t e = es.beg[i] + (j - es.off[i]);
                 const int32_t a = csrc[e];
                 const int32_t da = Drow[a];
-                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)dx) {
+                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)Drow[xv]) {
                     atomicAdd(&u.outdeg[a], 1);
                     if ((atomicOr(&u.flags[a], F_VIS) & F_VIS) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
         lo = hi;
         hi = sh.next;
         __syncthreads();
     }
     const int32_t nsub = hi;
+    // 2. Kahn from the sinks of the sub-DAG
     if (tid == 0) sh.tail = 0;
     __syncthreads();
     for (int32_t i = tid; i < nsub; i += bs) {
@@ -601,28 +648,43 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
     __syncthreads();
     while (qn > 0) {
         if (tid == 0) sh.tail = 0;
-        __syncthreads();
-        for (int32_t idx = tid; idx < qn; idx += bs) {
-            const int32_t x = qa[idx];
-            const double ax = u.acc[x];
-            if (x != s && ax != 0.0) {
-                if (OUT_ROW) out[x] = ax;
-                else atomicAdd(&out[x], sign * ax);
+        for (int32_t c = 0; c < qn; c += bs) {
+            const int32_t idx = c + tid;
+            int32_t x = 0, b0 = 0, deg = 0;
+            double coef = 0.0;
+            if (idx < qn) {
+                x = qa[idx];
+                const double ax = u.acc[x];
+                if (x != s && ax != 0.0) {
+                    if (OUT_ROW) out[x] = ax;
+                    else atomicAdd(&out[x], sign * ax);
+                }
+                // each predecessor a receives sigma_sa * coef
+                coef = (((u.flags[x] & F_B) ? 1.0 : 0.0) + ax) / (double)Srow[x];
+                b0 = cptr[x];
+                deg = cptr[x + 1] - b0;
             }
-            const double val = ((u.flags[x] & F_B) ? 1.0 : 0.0) + ax;
-            const double sx = (double)Srow[x];
-            const int32_t dx = Drow[x];
-            const int32_t e1 = cptr[x + 1];
-            for (int32_t e = cptr[x]; e < e1; ++e) {
+            int32_t total;
+            const int32_t off = block_excl_scan(deg, sh.scan, total);
+            es.off[tid] = off;
+            es.vtx[tid] = x;
+            es.beg[tid] = b0;
+            es.val[tid] = coef;
+            __syncthreads();
+            const int32_t nv = min(bs, qn - c);
+            for (int32_t j = tid; j < total; j += bs) {
+                const int32_t i = find_owner(es, nv, j);
+                const int32_t xv = es.vtx[i];
+                const int32_t e = es.beg[i] + (j - es.off[i]);
                 const int32_t a = csrc[e];
                 const int32_t da = Drow[a];
-                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)dx) {
-                    atomicAdd(&u.acc[a], (double)Srow[a] / sx * val);
+                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)Drow[xv]) {
+                    atomicAdd(&u.acc[a], (double)Srow[a] * es.val[i]);
                     if (atomicSub(&u.outdeg[a], 1) == 1) qb[atomicAdd(&sh.tail, 1)] = a;
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
         qn = sh.tail;
         int32_t *tmp = qa;
         qa = qb;
@@ -638,45 +700,54 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
     __syncthreads();
 }
 
-// New (d, sigma) of pair (s,t) by Lemma 4 In phase, then (if E_o is not
-// empty) Lemma 4 on G'_R with D = d'(s,v) + d''(v,t) and row v''.  sigma is
-// read only where a distance test says the pair may change.  Returns true if
-// the pair changes.
-__device__ __forceinline__ bool pair_update(const UpdateJob &J, const SrcScal &sc, const bool same, const bool has_out,
-                                            const int32_t t, const int32_t d0, const uint64_t *Sg, int32_t &d_out,
-                                            uint64_t &s_out, bool &ovf_s, bool &ovf_d) {
+// Row-v data an update reads for every pair (s,t) of an affected row.
+struct RowV {
+    const int32_t *rvD;   // d(v,t)  (= d'(v,t))
+    const uint64_t *rvS;  // sigma_vt
+    const int32_t *rvvD;  // d''(v,t)           (Out phase only)
+    const uint64_t *rvvS; // sigma''_vt
+    const uint64_t *rvvH; // sigma-hat''_vt
+    bool has_out;
+};
+
+// New (d, sigma) of pair (s,t) by Lemma 4 In phase (D = d'(s,v) + d(v,t)),
+// then, if E_o is not empty, Lemma 4 on G'_R (D = d'(s,v) + d''(v,t)).  sigma
+// is read only where a distance test says the pair may change.  Returns true
+// if the pair changes.
+__device__ __forceinline__ bool pair_update(const RowV &R, const SrcScal &sc, const bool same, const int32_t t,
+                                            const int32_t d0, const int32_t rvd, const int32_t dvv,
+                                            const uint64_t *Sg, int32_t &d_out, uint64_t &s_out, bool &ovf_s,
+                                            bool &ovf_d) {
     int32_t d = d0;
     uint64_t sg = 0;
     bool sg_known = false;
     int64_t c;
-    const int32_t rvd = J.row_v_D[t];
     if (in_rule(d0, sc.dv, rvd, c)) {
         if (c >= INF32) {
             ovf_d = true;
         } else if (c < d0) {
             d = (int32_t)c;
-            sg = mul_chk(sc.sv, J.row_v_S[t], ovf_s);
+            sg = mul_chk(sc.sv, R.rvS[t], ovf_s);
             sg_known = true;
         } else {
-            const uint64_t add = mul_chk(same ? sc.hv : sc.sv, J.row_v_S[t], ovf_s);
+            const uint64_t add = mul_chk(same ? sc.hv : sc.sv, R.rvS[t], ovf_s);
             if (add != 0) {
                 sg = add_chk(Sg[t], add, ovf_s);
                 sg_known = true;
             }
         }
     }
-    if (has_out) {
-        const int32_t dvv = J.g.rvv_D[t];
+    if (R.has_out) {
         int64_t c2;
         if (in_rule(d, sc.dv, dvv, c2)) {
             if (c2 >= INF32) {
                 ovf_d = true;
             } else if (c2 < d) {
                 d = (int32_t)c2;
-                sg = mul_chk(sc.sv, J.g.rvv_S[t], ovf_s);
+                sg = mul_chk(sc.sv, R.rvvS[t], ovf_s);
                 sg_known = true;
             } else {
-                const uint64_t mult = (dvv == rvd) ? J.g.rvv_H[t] : J.g.rvv_S[t];
+                const uint64_t mult = (dvv == rvd) ? R.rvvH[t] : R.rvvS[t];
                 const uint64_t add = mul_chk(sc.sv, mult, ovf_s);
                 if (add != 0) {
                     sg = add_chk(sg_known ? sg : Sg[t], add, ovf_s);
@@ -690,19 +761,46 @@ __device__ __forceinline__ bool pair_update(const UpdateJob &J, const SrcScal &s
     return sg_known;
 }
 
+// Quick reject: neither phase can reach pair (s,t) unless d'(s,v) plus the
+// row-v distance is at most the current d(s,t) (Lemma 4 case 1 otherwise).
+__device__ __forceinline__ bool may_change(int32_t d0, int32_t dv, int32_t rvd, int32_t dvv) {
+    if (dv == INF32) return false;
+    const bool in = rvd != INF32 && (int64_t)dv + rvd <= (int64_t)d0;
+    const bool out = dvv != INF32 && (int64_t)dv + dvv <= (int64_t)d0;
+    return in || out;
+}
+
+__device__ __forceinline__ void note_change(const RowV &R, const SrcScal &sc, const bool same, const int32_t t,
+                                            const int32_t d0, const int32_t rvd, const int32_t dvv,
+                                            const uint64_t *Sg, const USlot &u, BlockShared &sh, bool &ovf_s,
+                                            bool &ovf_d) {
+    if (!may_change(d0, sc.dv, rvd, dvv)) return;
+    int32_t d;
+    uint64_t sg;
+    if (pair_update(R, sc, same, t, d0, rvd, dvv, Sg, d, sg, ovf_s, ovf_d)) {
+        const int32_t pos = atomicAdd(&sh.nb, 1);
+        u.bl_t[pos] = t;
+        u.bl_d[pos] = d;
+        u.bl_s[pos] = sg;
+    }
+}
+
 // Persistent per-source kernel: workgroups pull (job, affected source)
 // items from a device counter until every job's list is empty.  Each item:
-//   1. scan row s (staged in LDS) and list the changed targets B_s with their
-//      new (d, sigma) (the all-pairs step of Alg 3, restricted to row s),
+//   1. scan row s and list the changed targets B_s with their new
+//      (d, sigma) (the all-pairs step of Alg 3, restricted to row s),
 //   2. old partial dependency over B_s (E* by head, old row), sign -1,
 //   3. write the changed pairs (only those) to D and sigma,
 //   4. new partial dependency over B_s (merged E*, new row), sign +1.
-// Every workgroup's slot is laid out for the context-wide n_layout (the largest
-// graph), so the zero-kept arrays sit at the same place for every job.
+// The row is staged in LDS when n <= lds_cap (dynamic LDS of 4*lds_cap bytes).
+// Every workgroup's slot is laid out for the context-wide n_layout (the
+// largest graph), so the zero-kept arrays sit at the same place for every job.
 __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
                                                  char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
                                                  int32_t n_layout) {
-    extern __shared__ int32_t lds_row[];
+    extern __shared__ __align__(16) char dyn_lds[];
+    int32_t *const lds_row = (int32_t *)dyn_lds;
+    const ExpandShared es = expand_at(dyn_lds, lds_cap);
     __shared__ BlockShared sh;
     const int njobs = *njobs_p;
     const int tid = threadIdx.x, bs = blockDim.x;
@@ -715,7 +813,21 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
         GraphCtl *ctl = J.g.ctl;
         if (job_dead(J)) continue;
         const int32_t count = *(volatile int32_t *)&ctl->a_count;
-        const bool has_out = J.n_out > 0;
+        RowV R;
+        R.rvD = J.row_v_D;
+        R.rvS = J.row_v_S;
+        R.rvvD = J.g.rvv_D;
+        R.rvvS = J.g.rvv_S;
+        R.rvvH = J.g.rvv_H;
+        R.has_out = J.n_out > 0;
+        int32_t *const D = J.g.D;
+        uint64_t *const S = J.g.S;
+        const int32_t *const alist = J.g.alist;
+        const SrcScal *const scal = J.g.scal;
+        const int32_t *const xc_ptr = J.g.xc_ptr, *const xc_src = J.g.xc_src, *const xc_w = J.g.xc_w;
+        const int32_t *const yc_ptr = J.g.yc_ptr, *const yc_src = J.g.yc_src, *const yc_w = J.g.yc_w;
+        double *const bc_delta = J.g.bc_delta;
+        const bool vec = (n & 3) == 0;
         if (tid == 0) sh.counter = 0;
         bool ovf_s = false, ovf_d = false;
         for (;;) {
@@ -727,32 +839,55 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
             __syncthreads();
             const int32_t item = sh.item;
             if (item >= count) break;
-            const int32_t s = J.g.alist[item];
-            int32_t *Dg = J.g.D + (size_t)s * n;
-            uint64_t *Sg = J.g.S + (size_t)s * n;
-            const SrcScal sc = J.g.scal[s];
+            const int32_t s = alist[item];
+            int32_t *Dg = D + (size_t)s * n;
+            uint64_t *Sg = S + (size_t)s * n;
+            const SrcScal sc = scal[s];
             const bool same = (sc.flags & 1) != 0;
             int32_t *Drow = Dg;
             if (lds) {
                 for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
                 Drow = lds_row;
+                __syncthreads();
             }
-            __syncthreads();
-            for (int32_t t = tid; t < n; t += bs) {
-                int32_t d;
-                uint64_t sg;
-                if (pair_update(J, sc, same, has_out, t, Drow[t], Sg, d, sg, ovf_s, ovf_d)) {
-                    const int32_t pos = atomicAdd(&sh.nb, 1);
-                    u.bl_t[pos] = t;
-                    u.bl_d[pos] = d;
-                    u.bl_s[pos] = sg;
+            if (vec) {
+                // four quads (16 pairs) per lane in flight
+                const int32_t nq = n >> 2;
+                const int4 *D4 = (const int4 *)Drow;
+                const int4 *R4 = (const int4 *)R.rvD;
+                const int4 *V4 = (const int4 *)R.rvvD;
+                for (int32_t q0 = tid; q0 < nq; q0 += 4 * bs) {
+                    int4 dq[4], rq[4], vq[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int32_t q = q0 + k * bs;
+                        if (q < nq) {
+                            dq[k] = D4[q];
+                            rq[k] = R4[q];
+                            vq[k] = R.has_out ? V4[q] : make_int4(INF32, INF32, INF32, INF32);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int32_t q = q0 + k * bs;
+                        if (q < nq) {
+                            const int32_t t = q << 2;
+                            note_change(R, sc, same, t + 0, dq[k].x, rq[k].x, vq[k].x, Sg, u, sh, ovf_s, ovf_d);
+                            note_change(R, sc, same, t + 1, dq[k].y, rq[k].y, vq[k].y, Sg, u, sh, ovf_s, ovf_d);
+                            note_change(R, sc, same, t + 2, dq[k].z, rq[k].z, vq[k].z, Sg, u, sh, ovf_s, ovf_d);
+                            note_change(R, sc, same, t + 3, dq[k].w, rq[k].w, vq[k].w, Sg, u, sh, ovf_s, ovf_d);
+                        }
+                    }
                 }
+            } else {
+                for (int32_t t = tid; t < n; t += bs)
+                    note_change(R, sc, same, t, Drow[t], R.rvD[t], R.has_out ? R.rvvD[t] : INF32, Sg, u, sh, ovf_s,
+                                ovf_d);
             }
             __syncthreads();
             const int32_t nb = sh.nb;
             if (nb == 0) continue;
-            restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, u.bl_t, nb, u, -1.0, J.g.bc_delta,
-                                   sh);
+            restricted_pass<false>(s, Drow, Sg, xc_ptr, xc_src, xc_w, u.bl_t, nb, u, -1.0, bc_delta, sh, es);
             for (int32_t i = tid; i < nb; i += bs) {
                 const int32_t t = u.bl_t[i];
                 const int32_t d = u.bl_d[i];
@@ -761,8 +896,7 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
                 if (lds) lds_row[t] = d;
             }
             __syncthreads();
-            restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, u.bl_t, nb, u, 1.0, J.g.bc_delta,
-                                   sh);
+            restricted_pass<false>(s, Drow, Sg, yc_ptr, yc_src, yc_w, u.bl_t, nb, u, 1.0, bc_delta, sh, es);
             if (tid == 0) sh.counter += (unsigned long long)nb;
         }
         if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
@@ -938,7 +1072,9 @@ __global__ void k_reset_work(GraphCtl *ctl) {
 // Writes the row to out_row (n values, 0 at s and at unreachable x).
 __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict__ jobs, int32_t s, char *__restrict__ scratch,
                                                     int32_t lds_cap, int32_t n_layout, double *out_row) {
-    extern __shared__ int32_t lds_row[];
+    extern __shared__ __align__(16) char dyn_lds[];
+    int32_t *const lds_row = (int32_t *)dyn_lds;
+    const ExpandShared es = expand_at(dyn_lds, lds_cap);
     __shared__ BlockShared sh;
     const UpdateJob &J = jobs[0];
     const int32_t n = J.g.n;
@@ -956,8 +1092,8 @@ __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict_
     }
     if (lds) Drow = lds_row;
     __syncthreads();
-    restricted_pass<true>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, u.bl_t, sh.nb, u, 1.0,
-                          out_row, sh);
+    restricted_pass<true>(s, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, u.bl_t, sh.nb, u, 1.0,
+                          out_row, sh, es);
 }
 
 // Arcs of DAG(s): the predicate of Eq.1 over E*.

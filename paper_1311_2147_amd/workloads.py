@@ -510,17 +510,16 @@ def mixed_stream(g: Graph, count: int, wmax: int, seed: int, p_ins: float, p_dec
     """Mix of insertions (p_ins), decreases (p_dec) and vertex updates (rest)."""
     rs = rs or Rng(derive_seed(seed, PURPOSE["updates"]))
     st = st or ArcStore(g)
-    complete = (not g.directed) and st.count() == g.n * (g.n - 1) // 2
     out = []
     for _ in range(count):
+        full = st.count() == (g.n * (g.n - 1) if g.directed else g.n * (g.n - 1) // 2)
         r = rs.uniform(1)[0]
         if r < p_ins + p_dec:
-            if r < p_ins and not complete:
-                a, b, w = _draw_insertion(st, rs, wmax)
-                up = Update("edge", u=a, v=b, w=w, insert=True)
-            else:
-                a, b, w = _draw_decrease(st, rs)
-                up = Update("edge", u=a, v=b, w=w)
+            drawn = _draw_insertion(st, rs, wmax) if (r < p_ins and not full) else _draw_decrease(st, rs)
+            if drawn is None:  # nothing left to lower or insert
+                continue
+            a, b, w = drawn
+            up = Update("edge", u=a, v=b, w=w, insert=st.get(a, b) is None)
         else:
             up = _draw_vertex(st, rs, k_vertex, wmax)
         for a, b, w in up.edge_list():

@@ -1,0 +1,180 @@
+"""GPU parity on the workloads' own shapes.
+
+Small variants (oracle after every update) and full sizes (oracle on sampled
+sources after updates, full comparison where a from-scratch recompute takes
+seconds).  Sizes are chosen to span several workgroup tiles with ragged tails.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import bc_err, check_full, check_sampled, make_ctx, say, BC_TOL
+from paper_1311_2147_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _affected_sample(gr, n, rng, k=4):
+    st = gr.stats()
+    srcs = set(int(x) for x in rng.integers(0, n, k))
+    return sorted(srcs)
+
+
+def test_config2_small_every_update():
+    g, ups = W.config2(n=600, n_updates=40)
+    say(f"[c2-small] n={g.n} m={g.m}")
+    ctx = make_ctx(g.n, slots=64)
+    gr = ctx.load_graph(g)
+    cur = g
+    for i, up in enumerate(ups):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        if i % 4 == 3 or i == len(ups) - 1:
+            say(f"[c2-small] check after update {i} |A|={gr.stats()['affected_sources']}")
+            check_full(gr, cur, f"c2-small #{i}", dags=(up.u, up.v), deltas=(up.u, 0, 599))
+    ctx.close()
+
+
+def test_config2_full_size_sampled():
+    g, ups = W.config2()
+    say(f"[c2] n={g.n} m={g.m} updates={len(ups)}")
+    ctx = make_ctx(g.n)
+    gr = ctx.load_graph(g)
+    cur = g
+    rng = np.random.default_rng(2)
+    for i, up in enumerate(ups):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        if i % 32 == 31:
+            srcs = sorted({up.u, up.v, *[int(x) for x in rng.integers(0, g.n, 6)]})
+            say(f"[c2] sampled rows after update {i}: {srcs}")
+            check_sampled(gr, cur, srcs, f"c2 #{i}")
+    say("[c2] full comparison at the end")
+    check_full(gr, cur, "c2 end", estar=True)
+    ctx.close()
+
+
+def test_config3_small_every_update():
+    g, ups = W.config3(n=300, n_updates=12, k=32)
+    ctx = make_ctx(g.n, slots=64)
+    gr = ctx.load_graph(g)
+    cur = g
+    for i, up in enumerate(ups):
+        say(f"[c3-small] vertex update {i} at {up.v} ({len(up.edges)} edges)")
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        check_full(gr, cur, f"c3-small #{i}", dags=(up.v,), deltas=(up.v, 1))
+    ctx.close()
+
+
+def test_config3_full_size():
+    g, ups = W.config3()
+    say(f"[c3] complete n={g.n} m={g.m}")
+    ctx = make_ctx(g.n)
+    gr = ctx.load_graph(g)
+    cur = g
+    rng = np.random.default_rng(3)
+    for i, up in enumerate(ups):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        if i % 16 == 15:
+            srcs = sorted({up.v, *[int(x) for x in rng.integers(0, g.n, 5)]})
+            say(f"[c3] sampled rows after update {i}: {srcs}")
+            check_sampled(gr, cur, srcs, f"c3 #{i}")
+    say("[c3] full comparison at the end")
+    check_full(gr, cur, "c3 end", estar=True)
+    ctx.close()
+
+
+def _run_alone(g, ups):
+    ctx = make_ctx(g.n, slots=32)
+    gr = ctx.load_graph(g)
+    for up in ups:
+        gr.update(up)
+    h = gr.state_hash()
+    bc = gr.scores()
+    ctx.close()
+    return h, bc
+
+
+def test_batched_submit_matches_oracle_and_alone_runs():
+    """Several graphs of uneven sizes, one batched step per round through
+    bc_submit (captured and replayed), against the oracle after every step;
+    then each graph's stream alone through the plain path must give
+    bit-identical D and sigma and BC within tolerance."""
+    work = W.config4(count=6, n_updates=6, lo=200, hi=700)
+    n_max = max(g.n for g, _ in work)
+    ctx = make_ctx(n_max, slots=64)
+    grs = [ctx.load_graph(g) for g, _ in work]
+    curs = [g for g, _ in work]
+    for step in range(6):
+        reqs = [(grs[i], ups[step]) for i, (_, ups) in enumerate(work)]
+        t = ctx.submit(reqs)
+        ctx.wait(t)
+        for i, (_, ups) in enumerate(work):
+            curs[i] = W.apply_update(curs[i], ups[step])
+        say(f"[batch] step {step} done, checking {len(grs)} graphs")
+        for i, gr in enumerate(grs):
+            check_full(gr, curs[i], f"batch g{i} step {step}", estar=(step == 5))
+    mixed = [(gr.state_hash(), gr.scores()) for gr in grs]
+    ctx.close()
+    for i, (g, ups) in enumerate(work):
+        h, bc = _run_alone(g, ups)
+        assert h == mixed[i][0], f"graph {i}: D/sigma differ between alone and mixed runs"
+        assert bc_err(mixed[i][1], bc) <= BC_TOL
+
+
+def test_batched_many_steps_in_one_submit():
+    work = W.config4(count=4, n_updates=10, lo=256, hi=512)
+    n_max = max(g.n for g, _ in work)
+    ctx = make_ctx(n_max, slots=32)
+    grs = [ctx.load_graph(g) for g, _ in work]
+    reqs = []
+    for step in range(10):
+        for i, (_, ups) in enumerate(work):
+            reqs.append((grs[i], ups[step]))
+    t = ctx.submit(reqs)
+    while not ctx.poll(t):
+        pass
+    for i, (g, ups) in enumerate(work):
+        cur = g
+        for up in ups:
+            cur = W.apply_update(cur, up)
+        check_full(gr := grs[i], cur, f"many-steps g{i}", estar=True)
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [4096, 32768])
+def test_chunglu_sampled(n):
+    g = W.config5_graph(n, 6 if n == 32768 else 0)
+    ups = W.mixed_stream(g, 24, 1000, 55, 0.35, 0.35, 16)
+    say(f"[c5 n={n}] loading m={g.m}")
+    ctx = make_ctx(n)
+    gr = ctx.load_graph(g)
+    cur = g
+    rng = np.random.default_rng(n)
+    for i, up in enumerate(ups):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        if i % 6 == 5:
+            srcs = sorted({up.v, *[int(x) for x in rng.integers(0, n, 3)]})
+            say(f"[c5 n={n}] update {i} |A|={gr.stats()['affected_sources']}: sampled rows {srcs}")
+            check_sampled(gr, cur, srcs, f"c5 n={n} #{i}")
+            # E* arcs leaving the sampled rows: exactly the arcs with w == d(a, b)
+            r = oracle.rows(cur, srcs)
+            a, b, w = gr.estar()
+            got = {(int(x), int(y), int(z)) for x, y, z in zip(a, b, w) if int(x) in srcs}
+            ga, gb, gw = cur.arcs()
+            want = set()
+            for k, s in enumerate(srcs):
+                sel = ga == s
+                for y, z in zip(gb[sel], gw[sel]):
+                    if r["D"][k, y] == z:
+                        want.add((s, int(y), int(z)))
+            assert got == want, f"E* rows differ after update {i}"
+    if n <= 8192:
+        say(f"[c5 n={n}] full comparison at the end")
+        check_full(gr, cur, f"c5 n={n} end", estar=False)
+    ctx.close()

@@ -66,15 +66,18 @@ enum {
 typedef struct bc_ctx bc_ctx;
 typedef int32_t bc_graph_id;
 
+/* bc_config.flags */
+#define BC_FLAG_TIMING 1 /* time every update step and its per-source kernel with HIP events */
+
 typedef struct {
     int32_t device;         /* HIP device ordinal */
-    int32_t flags;          /* reserved, 0 */
+    int32_t flags;          /* BC_FLAG_* bits */
     void *stream;           /* hipStream_t to order all work on; NULL: the library makes one */
     void *scratch;          /* device buffer for per-workgroup work areas (caller owns it) */
     uint64_t scratch_bytes; /* its size; see bc_scratch_bytes */
     uint64_t memory_budget; /* admission limit for the sum of graph arenas, 0 = none */
-    int32_t slots;          /* persistent workgroups of the per-source kernel, 0 = one per CU */
-    int32_t block;          /* threads per workgroup of the per-source kernel, 0 = 1024 */
+    int32_t slots;          /* persistent workgroups of the per-source kernel, 0 = 1024 */
+    int32_t block;          /* threads per workgroup of the per-source kernel (64, 128, 192 or 256), 0 = 256 */
 } bc_config;
 
 typedef struct {
@@ -179,10 +182,24 @@ typedef struct {
     int64_t affected_sources; /* |A| of the last update (sum over its phases) */
     int64_t changed_pairs;    /* pairs (s,t) whose d or sigma changed */
     int64_t estar_arcs;       /* |E*| after the update */
-    int64_t max_levels;       /* deepest DAG level count seen by the per-source kernel */
+    int64_t max_levels;       /* deepest DAG level count seen by the static pass */
     int64_t updates_applied;  /* updates since load */
+    int64_t total_affected;   /* sum of |A| over all updates since load */
+    int64_t total_changed;    /* sum of changed pairs over all updates since load */
 } bc_update_stats;
 bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id g, bc_update_stats *out);
+
+/* Kernel timing of a context created with BC_FLAG_TIMING: HIP events on the
+ * context's stream bracket every update step (all its kernels) and, inside
+ * it, the per-source kernel.  Totals cover the steps finished since the last
+ * bc_reset_timing (bc_get_timing synchronises first). */
+typedef struct {
+    double step_ms;          /* summed duration of update steps */
+    double source_ms;        /* summed duration of the per-source kernel */
+    int64_t steps;           /* update steps timed (one launch of each kernel) */
+} bc_timing;
+bc_status bc_get_timing(bc_ctx *ctx, bc_timing *out);
+bc_status bc_reset_timing(bc_ctx *ctx);
 
 const char *bc_status_string(bc_status s);
 const char *bc_last_error(bc_ctx *ctx);

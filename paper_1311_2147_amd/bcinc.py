@@ -62,7 +62,15 @@ class bc_request(ctypes.Structure):
 
 class bc_update_stats(ctypes.Structure):
     _fields_ = [("affected_sources", ctypes.c_int64), ("changed_pairs", ctypes.c_int64),
-                ("estar_arcs", ctypes.c_int64), ("max_levels", ctypes.c_int64), ("updates_applied", ctypes.c_int64)]
+                ("estar_arcs", ctypes.c_int64), ("max_levels", ctypes.c_int64), ("updates_applied", ctypes.c_int64),
+                ("total_affected", ctypes.c_int64), ("total_changed", ctypes.c_int64)]
+
+
+class bc_timing(ctypes.Structure):
+    _fields_ = [("step_ms", ctypes.c_double), ("source_ms", ctypes.c_double), ("steps", ctypes.c_int64)]
+
+
+BC_FLAG_TIMING = 1
 
 
 _P = ctypes.c_void_p
@@ -88,6 +96,8 @@ _SIGS = {
     "bc_get_delta": (_i32, [_P, _i32, _i32, _P]),
     "bc_state_hash": (_i32, [_P, _i32, _P]),
     "bc_get_stats": (_i32, [_P, _i32, ctypes.POINTER(bc_update_stats)]),
+    "bc_get_timing": (_i32, [_P, ctypes.POINTER(bc_timing)]),
+    "bc_reset_timing": (_i32, [_P]),
     "bc_status_string": (ctypes.c_char_p, [_i32]),
     "bc_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -134,14 +144,15 @@ class Context:
     """A bcinc context on one GPU (bc_create / bc_destroy)."""
 
     def __init__(self, device: int = 0, n_max: int = 4096, slots: int = 0, block: int = 0, memory_budget: int = 0,
-                 stream=None):
+                 stream=None, timing: bool = False):
         import torch
 
         self.device = device
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.scratch_bytes = bc_scratch_bytes(n_max, slots)
         self._scratch, addr = _device_buffer(self.scratch_bytes, device)
-        cfg = bc_config(device, 0, self.stream.cuda_stream, addr, self.scratch_bytes, memory_budget, slots, block)
+        flags = BC_FLAG_TIMING if timing else 0
+        cfg = bc_config(device, flags, self.stream.cuda_stream, addr, self.scratch_bytes, memory_budget, slots, block)
         h = ctypes.c_void_p()
         rc = _lib.bc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != BC_OK:
@@ -215,6 +226,14 @@ class Context:
 
     def sync(self):
         self._check(_lib.bc_sync(self.h), "bc_sync")
+
+    def timing(self) -> dict:
+        t = bc_timing()
+        self._check(_lib.bc_get_timing(self.h, ctypes.byref(t)), "bc_get_timing")
+        return {"step_ms": t.step_ms, "source_ms": t.source_ms, "steps": t.steps}
+
+    def reset_timing(self):
+        self._check(_lib.bc_reset_timing(self.h), "bc_reset_timing")
 
 
 class Graph:

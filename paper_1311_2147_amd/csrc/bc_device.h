@@ -27,8 +27,14 @@ constexpr int32_t LDS_ROW_MAX = 36864;
 //   ES_FILTER  YC                       -> XC (arcs with w == d after the update)
 enum { ES_BUILD = 0, ES_BUILD_C = 1, ES_MERGE = 2, ES_FILTER = 3 };
 
-// Flags of the restricted dependency pass.
+// Flags of the restricted dependency pass.  The LDS table keeps them apart;
+// the global-memory pass packs them with the successor count in one word.
 enum : int32_t { F_VIS = 1, F_B = 2 };
+constexpr int32_t W_COUNT = 0x0fffffff, W_B = 1 << 29, W_VIS = 1 << 30;
+
+// Sources whose changed-target set exceeds this many targets are deferred by
+// the per-source kernel to its wide-workgroup companion.
+constexpr int32_t BIG_B = 512;
 
 // Sticky status bits of a graph.
 enum : int32_t { ST_SIGMA_OVF = 1, ST_DIST_OVF = 2, ST_ESTAR_CAP = 4 };
@@ -42,10 +48,15 @@ struct GraphCtl {
     int32_t es_m;       // arcs in X (E* by tail, built by the static pass)
     int32_t esc_m;      // arcs in XC (E* by head, kept current)
     int32_t esc_m_tmp;  // arcs in YC (E* by head plus the updated arcs)
-    int32_t pad0;
+    int32_t t_count;    // candidate targets of the update in flight
+    int32_t big_count;  // deferred (large) sources of the update in flight
+    int32_t big_next;   // next deferred source to process
+    int32_t pad1;
     unsigned long long changed_pairs;  // statistic of the last update
     unsigned long long affected_last;  // |A| of the last update
     unsigned long long updates;        // updates applied since load
+    unsigned long long affected_total; // sums over all updates since load
+    unsigned long long changed_total;
 };
 
 // Per-source scalars of the update in flight (Alg 4 output).
@@ -75,10 +86,14 @@ struct GraphPtrs {
     int32_t *es_cnt;  // n + 1 counts / offsets for rebuilding
     SrcScal *scal;    // n
     int32_t *alist;   // n, affected sources
+    int32_t *biglist; // n, affected sources deferred to the wide kernel
     int32_t *rv_D;    // snapshot of row v before the update (n)
     uint64_t *rv_S;
     int32_t *rvv_D;   // row v'' after the Out phase (n)
     uint64_t *rvv_S, *rvv_H;
+    int32_t *tlist;   // candidate targets of the update in flight (n)
+    int32_t *tl_rvD;  // d(v,t) for each candidate (compact copy)
+    int32_t *tl_rvvD; // d''(v,t) for each candidate (compact copy)
     GraphCtl *ctl;
     // Full arc set by tail and by head (static recompute and E* build).
     int32_t *arc_ptr, *arc_dst, *arc_w;

@@ -28,8 +28,9 @@ namespace {
 constexpr int RING = 4;            // job staging slots in flight
 constexpr int JCAP = 256;          // jobs per staging slot
 constexpr size_t MISC_BYTES = 4096;
-constexpr int DEFAULT_SLOTS = 2048; // 8 persistent single-wave workgroups per CU of an MI355X
-constexpr int DEFAULT_BLOCK = 64;   // one wave per affected source
+constexpr int DEFAULT_SLOTS = 1024; // 4 persistent workgroups per CU of an MI355X
+constexpr int DEFAULT_BLOCK = 256;  // 4 waves per affected source
+constexpr int WIDE_LDS_MAX = 16384; // rows the wide kernel stages in LDS (two workgroups per CU)
 constexpr int64_t W_MAX = (int64_t)INF32 - 1;
 
 size_t ring_slot_bytes() { return align256(256 + sizeof(UpdateJob) * JCAP); }
@@ -139,6 +140,13 @@ struct bc_ctx {
     hipEvent_t ring_ev[RING] = {};
     bool ring_used[RING] = {};
     int ring_next = 0;
+    // timing (BC_FLAG_TIMING): per staging slot, events at step start, around
+    // the per-source kernel, and at step end
+    bool timing = false;
+    hipEvent_t tev[RING][4] = {};  // before parts 0, 1, 2 and after part 2
+    bool tev_pending[RING] = {};
+    double step_ms = 0, source_ms = 0;
+    int64_t timed_steps = 0;
     std::map<std::tuple<int, int, size_t, int, int>, StepGraph> graph_cache;
     // tickets
     uint64_t next_ticket = 1;
@@ -185,8 +193,11 @@ int usable_slots(bc_ctx *ctx, int32_t n_max, size_t *slot_bytes) {
 
 int lds_cap_for(int32_t n_max) { return std::min<int32_t>(n_max, LDS_ROW_MAX); }
 
-// Dynamic LDS of k_source / k_delta_row: staged row plus 20 bytes per thread.
-size_t source_lds_bytes(int lds_cap, int block) { return align256((size_t)lds_cap * 4) + 20 * (size_t)block; }
+// Dynamic LDS of k_source / k_delta_row: staged row, 20 bytes per thread of
+// expansion arrays, and the small sub-DAG table.
+size_t source_lds_bytes(int lds_cap, int block) {
+    return align256((size_t)lds_cap * 4) + align256(20 * (size_t)block) + small_dag_bytes();
+}
 
 // Arena layout of one graph (every piece 256-byte aligned).
 struct Carve {
@@ -210,9 +221,10 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     size_t oyp = c.take(4 * ((size_t)n + 1)), oys = c.take(4 * (size_t)es_cap), oyd = c.take(4 * (size_t)es_cap),
            oyw = c.take(4 * (size_t)es_cap);
     size_t ocnt = c.take(4 * ((size_t)n + 1));
-    size_t osc = c.take(sizeof(SrcScal) * (size_t)n), oal = c.take(4 * (size_t)n);
+    size_t osc = c.take(sizeof(SrcScal) * (size_t)n), oal = c.take(4 * (size_t)n), obig = c.take(4 * (size_t)n);
     size_t orvd = c.take(4 * (size_t)n), orvs = c.take(8 * (size_t)n);
     size_t orvvd = c.take(4 * (size_t)n), orvvs = c.take(8 * (size_t)n), orvvh = c.take(8 * (size_t)n);
+    size_t otl = c.take(4 * (size_t)n), otlr = c.take(4 * (size_t)n), otlrr = c.take(4 * (size_t)n);
     size_t octl = c.take(sizeof(GraphCtl));
     size_t oap = c.take(4 * ((size_t)n + 1)), oad = c.take(4 * (size_t)arc_cap), oaw = c.take(4 * (size_t)arc_cap);
     size_t oip = c.take(4 * ((size_t)n + 1)), ois = c.take(4 * (size_t)arc_cap), oiw = c.take(4 * (size_t)arc_cap);
@@ -241,11 +253,15 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     P.es_cnt = (int32_t *)(base + ocnt);
     P.scal = (SrcScal *)(base + osc);
     P.alist = (int32_t *)(base + oal);
+    P.biglist = (int32_t *)(base + obig);
     P.rv_D = (int32_t *)(base + orvd);
     P.rv_S = (uint64_t *)(base + orvs);
     P.rvv_D = (int32_t *)(base + orvvd);
     P.rvv_S = (uint64_t *)(base + orvvs);
     P.rvv_H = (uint64_t *)(base + orvvh);
+    P.tlist = (int32_t *)(base + otl);
+    P.tl_rvD = (int32_t *)(base + otlr);
+    P.tl_rvvD = (int32_t *)(base + otlrr);
     P.ctl = (GraphCtl *)(base + octl);
     P.arc_ptr = (int32_t *)(base + oap);
     P.arc_dst = (int32_t *)(base + oad);
@@ -262,12 +278,37 @@ GraphRec *get_graph(bc_ctx *ctx, bc_graph_id g) {
     return (r && r->live) ? r : nullptr;
 }
 
+// Adds the timed durations of slot r's last step (its events have completed).
+bc_status harvest_timing(bc_ctx *ctx, int r) {
+    if (!ctx->tev_pending[r]) return BC_OK;
+    float a = 0, b = 0;
+    HIPCHK(hipEventElapsedTime(&a, ctx->tev[r][0], ctx->tev[r][3]));  // whole step
+    HIPCHK(hipEventElapsedTime(&b, ctx->tev[r][1], ctx->tev[r][2]));  // per-source kernel
+    ctx->step_ms += a;
+    ctx->source_ms += b;
+    ctx->timed_steps += 1;
+    ctx->tev_pending[r] = false;
+    return BC_OK;
+}
+
+bc_status harvest_all(bc_ctx *ctx) {
+    for (int r = 0; r < RING; ++r)
+        if (ctx->tev_pending[r]) {
+            HIPCHK(hipEventSynchronize(ctx->tev[r][3]));
+            bc_status st = harvest_timing(ctx, r);
+            if (st) return st;
+        }
+    return BC_OK;
+}
+
 // Acquire a staging slot (waits until its previous use has finished).
 bc_status ring_acquire(bc_ctx *ctx, int *slot) {
     int r = ctx->ring_next;
     ctx->ring_next = (r + 1) % RING;
     if (ctx->ring_used[r]) HIPCHK(hipEventSynchronize(ctx->ring_ev[r]));
     ctx->ring_used[r] = false;
+    bc_status st = harvest_timing(ctx, r);
+    if (st) return st;
     *slot = r;
     return BC_OK;
 }
@@ -297,29 +338,57 @@ struct LaunchShape {
     size_t slot_bytes;
     int lds_cap;      // static pass: rows up to this size are staged in LDS
     int src_lds_cap;  // per-source kernel: rows up to this size are staged in LDS
+    int wide_slots;   // workgroups of the wide per-source kernel
+    int wide_lds_cap; // and its LDS staging limit
     int32_t n_layout;
 };
 
-// The update kernel sequence for the jobs staged in ring slot r.
-bc_status launch_update_sequence(bc_ctx *ctx, int r, const LaunchShape &L) {
+// The update kernel sequence for the jobs staged in ring slot r, in three
+// parts: 0 = begin, scan, row v'', E* merge; 1 = the per-source kernel;
+// 2 = E* filter and commit.
+bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part) {
     const UpdateJob *jobs = ring_jobs_dev(ctx, r);
     const int32_t *nj = ring_njobs_dev(ctx, r);
     hipStream_t st = ctx->stream;
     const int g_elem = (int)std::min<int64_t>(((int64_t)L.n_max + 255) / 256, 2048);
     const int g_wave = (int)std::min<int64_t>(((int64_t)L.n_max * 64 + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_scan, dim3(g_elem), dim3(256), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_rowv, dim3(g_elem), dim3(256), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_es_count<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_es_scan<ES_MERGE>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), source_lds_bytes(L.src_lds_cap, ctx->block), st, jobs,
-                       nj, slots_dev(ctx), L.slot_bytes, L.src_lds_cap, L.n_layout);
-    hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_es_scatter<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-    hipLaunchKernelGGL(k_commit, dim3(g_elem), dim3(256), 0, st, jobs, nj, 0);
+    if (part == 0) {
+        hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_scan, dim3(g_elem), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_targets, dim3(g_elem), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_count<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_scan<ES_MERGE>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+    } else if (part == 1) {
+        hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), source_lds_bytes(L.src_lds_cap, ctx->block), st,
+                           jobs, nj, slots_dev(ctx), L.slot_bytes, L.src_lds_cap, L.n_layout);
+        hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(512), source_lds_bytes(L.wide_lds_cap, 512), st,
+                           jobs, nj, slots_dev(ctx), L.slot_bytes, L.wide_lds_cap, L.n_layout);
+    } else {
+        hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_scatter<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_commit, dim3(g_elem), dim3(256), 0, st, jobs, nj, 0);
+    }
     HIPCHK(hipGetLastError());
+    return BC_OK;
+}
+
+// Captured graph of one part, instantiated once per staging slot and shape.
+bc_status part_graph(bc_ctx *ctx, int r, const LaunchShape &L, int part, hipGraphExec_t *exec) {
+    auto key = std::make_tuple(r, L.njobs, L.slot_bytes, L.slots, L.src_lds_cap * 4 + part);
+    auto it = ctx->graph_cache.find(key);
+    if (it == ctx->graph_cache.end()) {
+        StepGraph sg;
+        HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        bc_status cst = launch_update_part(ctx, r, L, part);
+        hipError_t ce = hipStreamEndCapture(ctx->stream, &sg.graph);
+        if (cst) return cst;
+        if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
+        HIPCHK(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+        it = ctx->graph_cache.emplace(key, sg).first;
+    }
+    *exec = it->second.exec;
     return BC_OK;
 }
 
@@ -331,7 +400,12 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     L->slots = usable_slots(ctx, ctx->n_layout, &L->slot_bytes);
     if (L->slots < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for one work slot at this n");
     L->lds_cap = lds_cap_for(L->n_max);
-    L->src_lds_cap = std::min<int32_t>(L->n_max, ctx->src_lds_max);
+    // the row is staged only when it fits; otherwise no LDS is reserved for it
+    L->src_lds_cap = L->n_max <= ctx->src_lds_max ? L->n_max : 0;
+    // wide kernel: two 512-thread workgroups per CU; its row staging leaves
+    // room for the expansion arrays and the small-DAG table
+    L->wide_slots = std::min(L->slots, 2 * ctx->cu_count);
+    L->wide_lds_cap = L->n_max <= WIDE_LDS_MAX ? L->n_max : 0;
     return BC_OK;
 }
 
@@ -342,23 +416,20 @@ bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_gra
     int r;
     if ((st = ring_acquire(ctx, &r))) return st;
     if ((st = ring_stage(ctx, r, jobs))) return st;
-    if (!use_graph) {
-        if ((st = launch_update_sequence(ctx, r, L))) return st;
-    } else {
-        auto key = std::make_tuple(r, L.njobs, L.slot_bytes, L.slots, L.lds_cap);
-        auto it = ctx->graph_cache.find(key);
-        if (it == ctx->graph_cache.end()) {
-            StepGraph sg;
-            HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-            bc_status cst = launch_update_sequence(ctx, r, L);
-            hipError_t ce = hipStreamEndCapture(ctx->stream, &sg.graph);
-            if (cst) return cst;
-            if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
-            HIPCHK(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
-            it = ctx->graph_cache.emplace(key, sg).first;
+    const bool timed = ctx->timing;
+    // timing events sit on the stream between the parts (never inside a graph)
+    for (int part = 0; part < 3; ++part) {
+        if (timed) HIPCHK(hipEventRecord(ctx->tev[r][part], ctx->stream));
+        if (!use_graph) {
+            if ((st = launch_update_part(ctx, r, L, part))) return st;
+        } else {
+            hipGraphExec_t exec;
+            if ((st = part_graph(ctx, r, L, part, &exec))) return st;
+            HIPCHK(hipGraphLaunch(exec, ctx->stream));
         }
-        HIPCHK(hipGraphLaunch(it->second.exec, ctx->stream));
     }
+    if (timed) HIPCHK(hipEventRecord(ctx->tev[r][3], ctx->stream));
+    if (timed) ctx->tev_pending[r] = true;
     return ring_release(ctx, r);
 }
 
@@ -581,6 +652,7 @@ bc_status set_lds_limit(bc_ctx *ctx, const void *fn) {
 bc_status set_lds_limits(bc_ctx *ctx) {
     bc_status st;
     if ((st = set_lds_limit(ctx, (const void *)k_source))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_source_wide))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_sssp))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_static))) return st;
     return set_lds_limit(ctx, (const void *)k_delta_row);
@@ -658,7 +730,7 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
     ctx->budget = cfg->memory_budget;
     ctx->slots = cfg->slots > 0 ? cfg->slots : DEFAULT_SLOTS;
     ctx->block = cfg->block > 0 ? cfg->block : DEFAULT_BLOCK;
-    if (ctx->block % 64 != 0 || ctx->block > 1024) {
+    if (ctx->block % 64 != 0 || ctx->block > 256) {
         delete ctx;
         return BC_ERR_INVALID_ARG;
     }
@@ -684,7 +756,12 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
         if (e != hipSuccess) return bail(e, "hipHostMalloc");
         e = hipEventCreateWithFlags(&ctx->ring_ev[r], hipEventDisableTiming);
         if (e != hipSuccess) return bail(e, "hipEventCreate");
+        for (int q = 0; q < 4; ++q) {
+            e = hipEventCreate(&ctx->tev[r][q]);
+            if (e != hipSuccess) return bail(e, "hipEventCreate");
+        }
     }
+    ctx->timing = (cfg->flags & BC_FLAG_TIMING) != 0;
     if (set_lds_limits(ctx) != BC_OK) {
         fprintf(stderr, "bcinc: %s\n", ctx->last_error.c_str());
         delete ctx;
@@ -711,6 +788,8 @@ bc_status bc_destroy(bc_ctx *ctx) {
         if (ctx->h_jobs[r]) (void)hipHostFree(ctx->h_jobs[r]);
         if (ctx->h_njobs[r]) (void)hipHostFree(ctx->h_njobs[r]);
         if (ctx->ring_ev[r]) (void)hipEventDestroy(ctx->ring_ev[r]);
+        for (int q = 0; q < 4; ++q)
+            if (ctx->tev[r][q]) (void)hipEventDestroy(ctx->tev[r][q]);
     }
     for (auto *g : ctx->graphs) delete g;
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -1023,7 +1102,7 @@ bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
     bc_status st;
     if ((st = ring_acquire(ctx, &r))) return st;
     if ((st = ring_stage(ctx, r, jobs))) return st;
-    const int lds = std::min<int32_t>(g->n, 32768);  // row plus 20 KiB of expansion arrays fit in 160 KiB
+    const int lds = std::min<int32_t>(g->n, 28672);  // row, expansion arrays and small-DAG table fit in 160 KiB
     // the row lands in slot 0's B-list value area, unused by this pass
     double *row = (double *)(slots_dev(ctx) + update_layout(ctx->n_layout).bl_s);
     hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), source_lds_bytes(lds, 1024), ctx->stream,
@@ -1064,6 +1143,29 @@ bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id gid, bc_update_stats *out) {
     out->estar_arcs = c.esc_m;
     out->max_levels = c.max_levels;
     out->updates_applied = (int64_t)g->updates;
+    out->total_affected = (int64_t)c.affected_total;
+    out->total_changed = (int64_t)c.changed_total;
+    return BC_OK;
+}
+
+bc_status bc_get_timing(bc_ctx *ctx, bc_timing *out) {
+    if (!ctx || !out) return BC_ERR_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    bc_status st = harvest_all(ctx);
+    if (st) return st;
+    out->step_ms = ctx->step_ms;
+    out->source_ms = ctx->source_ms;
+    out->steps = ctx->timed_steps;
+    return BC_OK;
+}
+
+bc_status bc_reset_timing(bc_ctx *ctx) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    bc_status st = harvest_all(ctx);
+    if (st) return st;
+    ctx->step_ms = ctx->source_ms = 0;
+    ctx->timed_steps = 0;
     return BC_OK;
 }
 

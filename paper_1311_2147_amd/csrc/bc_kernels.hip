@@ -2,7 +2,8 @@
 //
 // Update pipeline for a batch of jobs (one update on each of several graphs):
 //   k_scan        affected sources A and Alg 4 scalars (Eq.6, Eq.7)
-//   k_rowv        row v'' of the Out phase (Alg 4 on the reverse graph)
+//   k_targets     row v'' of the Out phase (Alg 4 on the reverse graph) and
+//                 the candidate targets of the update
 //   k_es_*        E* (by head) plus the updated arcs (buffer YC)
 //   k_source      per affected source: changed targets by Lemma 2 / Lemma 4,
 //                 old and new partial dependencies over them, BC difference
@@ -160,62 +161,106 @@ __global__ void __launch_bounds__(256) k_scan(const UpdateJob *__restrict__ jobs
     }
 }
 
-// ------------------------------------------------------------ k_rowv -------
+// ------------------------------------------------------------ k_targets ----
 
+// Row v'' and the candidate targets of an update, one thread per target t.
+//
 // Row v'' (Section 4, Out phase): with E_o = {(v, x_j)}, Alg 4 on G'_R gives
 // d''(v,t) = min(d'(v,t), min_j w'(v,x_j) + d'(x_j,t)) and the counts
 // sigma''_vt, sigma-hat''_vt.  The rows x_j of G' are formed on the fly by
-// the In-phase rule from the old rows.  Also snapshots the old row v, which
-// the source v itself rewrites during the update.
-__global__ void __launch_bounds__(256) k_rowv(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
+// the In-phase rule from the old rows.  The old row v is snapshotted, since
+// the source v itself rewrites it during the update.
+//
+// Candidates: a pair (s,t) can change in the In phase only if
+// d'(s,v) + d(v,t) <= d(s,t) with d'(s,v) = d(s,u_j) + w'_j for some in-arc,
+// and d(s,t) <= d(s,u_j) + d(u_j,t), hence only if w'_j + d(v,t) <= d(u_j,t)
+// (for an arc update this is the target set of the tail u).  It can change in
+// the Out phase only if row v'' changed at t (d''(v,t) < d'(v,t), or a tie
+// with new paths).  The union T is listed once per update, with row v and
+// row v'' at t copied next to it, so each affected source scans T instead of
+// its whole row.
+__global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
     const int njobs = *njobs_p;
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (J.n_out == 0) continue;
         const int32_t n = J.g.n, v = J.v;
         const int32_t *D = J.g.D;
         const uint64_t *S = J.g.S;
         bool ovf_s = false, ovf_d = false;
-        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-            const int32_t dvt = D[(size_t)v * n + t];
-            const uint64_t svt = S[(size_t)v * n + t];
-            J.g.rv_D[t] = dvt;
-            J.g.rv_S[t] = svt;
-            int64_t cur = dvt;
-            uint64_t sig = svt, hat = 0;
-            for (int k = 0; k < J.n_out; ++k) {
-                const int32_t x = J.out_head[k];
-                const SrcScal sc = J.g.scal[x];
-                int32_t d1 = D[(size_t)x * n + t];
-                uint64_t s1 = 0;
-                bool s1_known = false;
-                int64_t c;
-                if (in_rule(d1, sc.dv, dvt, c)) {
-                    if (c >= INF32) { ovf_d = true; }
-                    else if (c < d1) { d1 = (int32_t)c; s1 = mul_chk(sc.sv, svt, ovf_s); s1_known = true; }
-                    else {
-                        s1 = add_chk(S[(size_t)x * n + t], mul_chk((sc.flags & 1) ? sc.hv : sc.sv, svt, ovf_s), ovf_s);
-                        s1_known = true;
+        for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+            const int32_t t = (int32_t)(base + threadIdx.x);
+            bool cand = false;
+            int32_t dvt = INF32, cur = INF32;
+            if (t < n) {
+                dvt = D[(size_t)v * n + t];
+                if (dvt != INF32) {
+                    for (int k = 0; k < J.n_in; ++k) {
+                        const int32_t dut = D[(size_t)J.in_tail[k] * n + t];
+                        if ((int64_t)J.in_w[k] + dvt <= (int64_t)dut) {
+                            cand = true;
+                            break;
+                        }
                     }
                 }
-                if (d1 == INF32) continue;
-                const int64_t cc = (int64_t)J.out_w[k] + d1;
-                if (cc >= INF32) { ovf_d = true; continue; }
-                if (cc <= cur) {
-                    if (!s1_known) s1 = S[(size_t)x * n + t];
-                    if (cc == cur) {
-                        sig = add_chk(sig, s1, ovf_s);
-                        hat = add_chk(hat, s1, ovf_s);
-                    } else {
-                        cur = cc;
-                        sig = s1;
-                        hat = 0;
+                cur = dvt;
+                if (J.n_out > 0) {
+                    const uint64_t svt = S[(size_t)v * n + t];
+                    J.g.rv_D[t] = dvt;
+                    J.g.rv_S[t] = svt;
+                    int64_t c64 = dvt;
+                    uint64_t sig = svt, hat = 0;
+                    for (int k = 0; k < J.n_out; ++k) {
+                        const int32_t x = J.out_head[k];
+                        const SrcScal sc = J.g.scal[x];
+                        int32_t d1 = D[(size_t)x * n + t];
+                        uint64_t s1 = 0;
+                        bool s1_known = false;
+                        int64_t c;
+                        if (in_rule(d1, sc.dv, dvt, c)) {
+                            if (c >= INF32) { ovf_d = true; }
+                            else if (c < d1) { d1 = (int32_t)c; s1 = mul_chk(sc.sv, svt, ovf_s); s1_known = true; }
+                            else {
+                                s1 = add_chk(S[(size_t)x * n + t], mul_chk((sc.flags & 1) ? sc.hv : sc.sv, svt, ovf_s),
+                                             ovf_s);
+                                s1_known = true;
+                            }
+                        }
+                        if (d1 == INF32) continue;
+                        const int64_t cc = (int64_t)J.out_w[k] + d1;
+                        if (cc >= INF32) { ovf_d = true; continue; }
+                        if (cc <= c64) {
+                            if (!s1_known) s1 = S[(size_t)x * n + t];
+                            if (cc == c64) {
+                                sig = add_chk(sig, s1, ovf_s);
+                                hat = add_chk(hat, s1, ovf_s);
+                            } else {
+                                c64 = cc;
+                                sig = s1;
+                                hat = 0;
+                            }
+                        }
                     }
+                    cur = (int32_t)c64;
+                    J.g.rvv_D[t] = cur;
+                    J.g.rvv_S[t] = sig;
+                    J.g.rvv_H[t] = hat;
+                    if (cur < dvt || hat != 0) cand = true;
                 }
             }
-            J.g.rvv_D[t] = (int32_t)cur;
-            J.g.rvv_S[t] = sig;
-            J.g.rvv_H[t] = hat;
+            const uint64_t mask = __ballot(cand);
+            if (mask) {
+                const int lane = lane_id();
+                const int leader = __ffsll((unsigned long long)mask) - 1;
+                int32_t b0 = 0;
+                if (lane == leader) b0 = atomicAdd(&J.g.ctl->t_count, (int32_t)__popcll(mask));
+                b0 = __shfl(b0, leader, 64);
+                if (cand) {
+                    const int32_t pos = b0 + (int32_t)popc_below(mask, lane);
+                    J.g.tlist[pos] = t;
+                    J.g.tl_rvD[pos] = dvt;
+                    J.g.tl_rvvD[pos] = cur;
+                }
+            }
         }
         if (ovf_s) atomicOr(&J.g.ctl->status, ST_SIGMA_OVF);
         if (ovf_d) atomicOr(&J.g.ctl->status, ST_DIST_OVF);
@@ -399,6 +444,7 @@ struct BlockShared {
     int32_t head, tail, next, nlev;
     int32_t item;
     int32_t nb;
+    int32_t ovf, progress;
     int32_t scan[40];
     unsigned long long counter;
 };
@@ -544,8 +590,8 @@ struct ExpandShared {
     double *val;
 };
 
-// Dynamic LDS of the per-source kernels: the staged row (4 * lds_cap bytes)
-// followed by the expansion arrays (20 bytes per thread).
+// Dynamic LDS of the per-source kernels: the staged row (4 * lds_cap bytes),
+// the expansion arrays (20 bytes per thread), then the small-DAG table.
 __device__ __forceinline__ ExpandShared expand_at(char *dyn, int32_t lds_cap) {
     ExpandShared es;
     char *p = dyn + align256((size_t)lds_cap * 4);
@@ -594,7 +640,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
     for (int32_t i = tid; i < nB; i += bs) {
         const int32_t t = Bt[i];
         if (t == s || Drow[t] == INF32) continue;
-        u.flags[t] = F_VIS | F_B;
+        u.outdeg[t] = W_VIS | W_B;
         u.sub[atomicAdd(&sh.next, 1)] = t;
     }
     __syncthreads();
@@ -624,8 +670,9 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
                 const int32_t a = csrc[e];
                 const int32_t da = Drow[a];
                 if (da != INF32 && (int64_t)da + cw[e] == (int64_t)Drow[xv]) {
-                    atomicAdd(&u.outdeg[a], 1);
-                    if ((atomicOr(&u.flags[a], F_VIS) & F_VIS) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
+                    // one more successor inside the sub-DAG; the first arc
+                    // found into a vertex not yet seen adds it to the list
+                    if ((atomicAdd(&u.outdeg[a], 1) & (W_COUNT | W_VIS)) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
                 }
             }
             __syncthreads();
@@ -640,7 +687,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
     __syncthreads();
     for (int32_t i = tid; i < nsub; i += bs) {
         const int32_t x = u.sub[i];
-        if (u.outdeg[x] == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
+        if ((u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
     }
     __syncthreads();
     int32_t qn = sh.tail;
@@ -660,7 +707,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
                     else atomicAdd(&out[x], sign * ax);
                 }
                 // each predecessor a receives sigma_sa * coef
-                coef = (((u.flags[x] & F_B) ? 1.0 : 0.0) + ax) / (double)Srow[x];
+                coef = (((u.outdeg[x] & W_B) ? 1.0 : 0.0) + ax) / (double)Srow[x];
                 b0 = cptr[x];
                 deg = cptr[x + 1] - b0;
             }
@@ -680,7 +727,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
                 const int32_t da = Drow[a];
                 if (da != INF32 && (int64_t)da + cw[e] == (int64_t)Drow[xv]) {
                     atomicAdd(&u.acc[a], (double)Srow[a] * es.val[i]);
-                    if (atomicSub(&u.outdeg[a], 1) == 1) qb[atomicAdd(&sh.tail, 1)] = a;
+                    if ((atomicSub(&u.outdeg[a], 1) & W_COUNT) == 1) qb[atomicAdd(&sh.tail, 1)] = a;
                 }
             }
             __syncthreads();
@@ -693,11 +740,194 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
     }
     for (int32_t i = tid; i < nsub; i += bs) {
         const int32_t x = u.sub[i];
-        u.flags[x] = 0;
         u.outdeg[x] = 0;
         u.acc[x] = 0.0;
     }
     __syncthreads();
+}
+
+// Small sub-DAGs in LDS.  Most sources' sub-DAGs hold a few dozen vertices,
+// so the partial-dependency pass keeps their per-vertex state in an
+// open-addressing hash table in LDS (with d(s,x) and sigma_sx cached), records
+// the sub-DAG's arcs while discovering it, and runs the Kahn rounds over that
+// arc list without touching global memory.  Only the E* in-arcs and the
+// predecessors' distances are read from global memory.  A sub-DAG that
+// outgrows the table is redone by restricted_pass (nothing global has been
+// written by then).
+constexpr int SD_SLOTS = 256;     // hash slots (power of two)
+constexpr int SD_CAP = 192;       // most vertices admitted (load factor 3/4)
+constexpr int SD_ARCS = 512;      // most sub-DAG arcs
+
+struct SmallDag {
+    int32_t *key, *flags, *outdeg, *dval, *round;
+    double *acc, *coef;
+    uint64_t *sval;
+    int16_t *sub, *arc_a, *arc_x;
+};
+
+__host__ __device__ constexpr size_t small_dag_bytes() {
+    return (size_t)SD_SLOTS * (5 * 4 + 3 * 8 + 2) + (size_t)SD_ARCS * 4 + 256;
+}
+
+__device__ __forceinline__ SmallDag small_dag_at(char *p) {
+    SmallDag d;
+    d.acc = (double *)p;             p += 8 * SD_SLOTS;
+    d.coef = (double *)p;            p += 8 * SD_SLOTS;
+    d.sval = (uint64_t *)p;          p += 8 * SD_SLOTS;
+    d.key = (int32_t *)p;            p += 4 * SD_SLOTS;
+    d.flags = (int32_t *)p;          p += 4 * SD_SLOTS;
+    d.outdeg = (int32_t *)p;         p += 4 * SD_SLOTS;
+    d.dval = (int32_t *)p;           p += 4 * SD_SLOTS;
+    d.round = (int32_t *)p;          p += 4 * SD_SLOTS;
+    d.sub = (int16_t *)p;            p += 2 * SD_SLOTS;
+    d.arc_a = (int16_t *)p;          p += 2 * SD_ARCS;
+    d.arc_x = (int16_t *)p;
+    return d;
+}
+
+// Slot of vertex x, inserting it if absent; -1 if the table is full.
+__device__ __forceinline__ int32_t sd_slot(const SmallDag &d, int32_t x, bool &inserted) {
+    uint32_t h = ((uint32_t)x * 2654435761u) >> 24;
+    inserted = false;
+    for (int p = 0; p < SD_SLOTS; ++p) {
+        const int32_t slot = (int32_t)((h + (uint32_t)p) & (SD_SLOTS - 1));
+        const int32_t prev = atomicCAS(&d.key[slot], -1, x);
+        if (prev == -1) {
+            inserted = true;
+            return slot;
+        }
+        if (prev == x) return slot;
+    }
+    return -1;
+}
+
+// The partial dependency of restricted_pass with all per-vertex state in
+// LDS.  Returns false (and leaves global memory untouched) if the sub-DAG
+// does not fit.
+__device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Srow,
+                           const int32_t *__restrict__ cptr, const int32_t *__restrict__ csrc,
+                           const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
+                           const double sign, double *out, BlockShared &sh, const ExpandShared &es,
+                           const SmallDag &d) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int32_t i = tid; i < SD_SLOTS; i += bs) {
+        d.key[i] = -1;
+        d.flags[i] = 0;
+        d.outdeg[i] = 0;
+        d.acc[i] = 0.0;
+        d.round[i] = -1;
+    }
+    if (tid == 0) {
+        sh.next = 0;
+        sh.tail = 0;  // arcs
+        sh.ovf = 0; // overflow
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < nB; i += bs) {
+        const int32_t t = Bt[i];
+        const int32_t dt = Drow[t];
+        if (t == s || dt == INF32) continue;
+        bool ins;
+        const int32_t slot = sd_slot(d, t, ins);
+        const int32_t pos = atomicAdd(&sh.next, 1);
+        if (slot < 0 || pos >= SD_CAP) {
+            sh.ovf = 1;
+            continue;
+        }
+        d.flags[slot] = F_VIS | F_B;
+        d.dval[slot] = dt;
+        d.sval[slot] = Srow[t];
+        d.sub[pos] = (int16_t)slot;
+    }
+    __syncthreads();
+    if (sh.ovf) return false;
+    int32_t lo = 0, hi = sh.next;
+    __syncthreads();
+    while (lo < hi) {
+        for (int32_t c = lo; c < hi; c += bs) {
+            const int32_t idx = c + tid;
+            int32_t sx = 0, b0 = 0, deg = 0;
+            if (idx < hi) {
+                sx = d.sub[idx];
+                const int32_t x = d.key[sx];
+                b0 = cptr[x];
+                deg = cptr[x + 1] - b0;
+            }
+            int32_t total;
+            const int32_t off = block_excl_scan(deg, sh.scan, total);
+            es.off[tid] = off;
+            es.vtx[tid] = sx;
+            es.beg[tid] = b0;
+            __syncthreads();
+            const int32_t nv = min(bs, hi - c);
+            for (int32_t j = tid; j < total; j += bs) {
+                const int32_t i = find_owner(es, nv, j);
+                const int32_t sxv = es.vtx[i];
+                const int32_t e = es.beg[i] + (j - es.off[i]);
+                const int32_t a = csrc[e];
+                const int32_t da = Drow[a];
+                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)d.dval[sxv]) {
+                    bool ins;
+                    const int32_t sa = sd_slot(d, a, ins);
+                    const int32_t k = atomicAdd(&sh.tail, 1);
+                    if (sa < 0 || k >= SD_ARCS) {
+                        sh.ovf = 1;
+                        continue;
+                    }
+                    d.arc_a[k] = (int16_t)sa;
+                    d.arc_x[k] = (int16_t)sxv;
+                    atomicAdd(&d.outdeg[sa], 1);
+                    if ((atomicOr(&d.flags[sa], F_VIS) & F_VIS) == 0) {
+                        d.dval[sa] = da;
+                        d.sval[sa] = Srow[a];
+                        const int32_t pos = atomicAdd(&sh.next, 1);
+                        if (pos >= SD_CAP) sh.ovf = 1;
+                        else d.sub[pos] = (int16_t)sa;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const bool ovf = sh.ovf != 0;
+        lo = hi;
+        hi = sh.next;
+        __syncthreads();
+        if (ovf) return false;
+    }
+    const int32_t nsub = hi, narcs = sh.tail;
+    // Kahn from the sinks over the recorded arcs, all in LDS.  Round r makes
+    // final the vertices whose successors all became final before r.
+    for (int32_t i = tid; i < nsub; i += bs) {
+        const int32_t sx = d.sub[i];
+        if (d.outdeg[sx] == 0) d.round[sx] = 0;
+    }
+    __syncthreads();
+    for (int32_t r = 0;; ++r) {
+        if (tid == 0) sh.progress = 0;
+        __syncthreads();
+        // the vertices final in round r publish their coefficient and BC term
+        for (int32_t i = tid; i < nsub; i += bs) {
+            const int32_t sx = d.sub[i];
+            if (d.round[sx] != r) continue;
+            const double ax = d.acc[sx];
+            const int32_t x = d.key[sx];
+            if (x != s && ax != 0.0) atomicAdd(&out[x], sign * ax);
+            d.coef[sx] = (((d.flags[sx] & F_B) ? 1.0 : 0.0) + ax) / (double)d.sval[sx];
+            sh.progress = 1;
+        }
+        __syncthreads();
+        if (sh.progress == 0) break;
+        // and push to their predecessors
+        for (int32_t k = tid; k < narcs; k += bs) {
+            const int32_t sx = d.arc_x[k];
+            if (d.round[sx] != r) continue;
+            const int32_t sa = d.arc_a[k];
+            atomicAdd(&d.acc[sa], (double)d.sval[sa] * d.coef[sx]);
+            if (atomicSub(&d.outdeg[sa], 1) == 1) d.round[sa] = r + 1;
+        }
+        __syncthreads();
+    }
+    return true;
 }
 
 // Row-v data an update reads for every pair (s,t) of an affected row.
@@ -770,11 +1000,12 @@ __device__ __forceinline__ bool may_change(int32_t d0, int32_t dv, int32_t rvd, 
     return in || out;
 }
 
+// Slow path of the row scan (a pair that passed may_change): full Lemma 4
+// update and, if the pair changes, an entry in the B list.  Kept out of line
+// so the unrolled scan stays small.
 __device__ __forceinline__ void note_change(const RowV &R, const SrcScal &sc, const bool same, const int32_t t,
-                                            const int32_t d0, const int32_t rvd, const int32_t dvv,
-                                            const uint64_t *Sg, const USlot &u, BlockShared &sh, bool &ovf_s,
-                                            bool &ovf_d) {
-    if (!may_change(d0, sc.dv, rvd, dvv)) return;
+                                         const int32_t d0, const int32_t rvd, const int32_t dvv, const uint64_t *Sg,
+                                         const USlot &u, BlockShared &sh, bool &ovf_s, bool &ovf_d) {
     int32_t d;
     uint64_t sg;
     if (pair_update(R, sc, same, t, d0, rvd, dvv, Sg, d, sg, ovf_s, ovf_d)) {
@@ -783,6 +1014,12 @@ __device__ __forceinline__ void note_change(const RowV &R, const SrcScal &sc, co
         u.bl_d[pos] = d;
         u.bl_s[pos] = sg;
     }
+}
+
+// Bit mask of the pairs of one quad that may change.
+__device__ __forceinline__ uint32_t quad_mask(const int4 d, const int4 r, const int4 v, const int32_t dv) {
+    return (may_change(d.x, dv, r.x, v.x) ? 1u : 0u) | (may_change(d.y, dv, r.y, v.y) ? 2u : 0u) |
+           (may_change(d.z, dv, r.z, v.z) ? 4u : 0u) | (may_change(d.w, dv, r.w, v.w) ? 8u : 0u);
 }
 
 // Persistent per-source kernel: workgroups pull (job, affected source)
@@ -795,14 +1032,18 @@ __device__ __forceinline__ void note_change(const RowV &R, const SrcScal &sc, co
 // The row is staged in LDS when n <= lds_cap (dynamic LDS of 4*lds_cap bytes).
 // Every workgroup's slot is laid out for the context-wide n_layout (the
 // largest graph), so the zero-kept arrays sit at the same place for every job.
-__global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
-                                                 char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
-                                                 int32_t n_layout) {
-    extern __shared__ __align__(16) char dyn_lds[];
+//
+// WIDE = false: the affected list, small workgroups, small sub-DAGs in LDS;
+// a source with more than BIG_B changed targets is deferred (before anything
+// is written) to the deferred list.  WIDE = true: the deferred list, one
+// 512-thread workgroup per source, sub-DAGs in global memory.
+template <bool WIDE>
+__device__ void source_items(const UpdateJob *__restrict__ jobs, const int32_t njobs, char *__restrict__ scratch,
+                             size_t slot_bytes, int32_t lds_cap, int32_t n_layout, char *dyn_lds) {
     int32_t *const lds_row = (int32_t *)dyn_lds;
     const ExpandShared es = expand_at(dyn_lds, lds_cap);
+    const SmallDag sd = small_dag_at(dyn_lds + align256((size_t)lds_cap * 4) + align256(20 * (size_t)blockDim.x));
     __shared__ BlockShared sh;
-    const int njobs = *njobs_p;
     const int tid = threadIdx.x, bs = blockDim.x;
     char *slot_base = scratch + (size_t)blockIdx.x * slot_bytes;
     for (int j = 0; j < njobs; ++j) {
@@ -812,7 +1053,9 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
         const USlot u = uslot_at(slot_base, n_layout);
         GraphCtl *ctl = J.g.ctl;
         if (job_dead(J)) continue;
-        const int32_t count = *(volatile int32_t *)&ctl->a_count;
+        const int32_t count = WIDE ? *(volatile int32_t *)&ctl->big_count : *(volatile int32_t *)&ctl->a_count;
+        const int32_t *const items = WIDE ? J.g.biglist : J.g.alist;
+        int32_t *const next_item = WIDE ? &ctl->big_next : &ctl->work_next;
         RowV R;
         R.rvD = J.row_v_D;
         R.rvS = J.row_v_S;
@@ -822,24 +1065,28 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
         R.has_out = J.n_out > 0;
         int32_t *const D = J.g.D;
         uint64_t *const S = J.g.S;
-        const int32_t *const alist = J.g.alist;
         const SrcScal *const scal = J.g.scal;
         const int32_t *const xc_ptr = J.g.xc_ptr, *const xc_src = J.g.xc_src, *const xc_w = J.g.xc_w;
         const int32_t *const yc_ptr = J.g.yc_ptr, *const yc_src = J.g.yc_src, *const yc_w = J.g.yc_w;
         double *const bc_delta = J.g.bc_delta;
         const bool vec = (n & 3) == 0;
+        // scan the candidate list when it is short enough that gathers beat
+        // streaming the whole row
+        const int32_t t_count = *(volatile int32_t *)&ctl->t_count;
+        const bool use_tlist = (int64_t)t_count * 8 <= (int64_t)n;
+        const int32_t *const tlist = J.g.tlist, *const tl_rvD = J.g.tl_rvD, *const tl_rvvD = J.g.tl_rvvD;
         if (tid == 0) sh.counter = 0;
         bool ovf_s = false, ovf_d = false;
         for (;;) {
             __syncthreads();
             if (tid == 0) {
-                sh.item = atomicAdd(&ctl->work_next, 1);
+                sh.item = atomicAdd(next_item, 1);
                 sh.nb = 0;
             }
             __syncthreads();
             const int32_t item = sh.item;
             if (item >= count) break;
-            const int32_t s = alist[item];
+            const int32_t s = items[item];
             int32_t *Dg = D + (size_t)s * n;
             uint64_t *Sg = S + (size_t)s * n;
             const SrcScal sc = scal[s];
@@ -850,44 +1097,57 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
                 Drow = lds_row;
                 __syncthreads();
             }
-            if (vec) {
-                // four quads (16 pairs) per lane in flight
+            if (use_tlist) {
+                // gather only the candidate targets T of this update
+                for (int32_t i = tid; i < t_count; i += bs) {
+                    const int32_t t = tlist[i];
+                    const int32_t d0 = Drow[t], rvd = tl_rvD[i], dvv = R.has_out ? tl_rvvD[i] : INF32;
+                    if (may_change(d0, sc.dv, rvd, dvv)) note_change(R, sc, same, t, d0, rvd, dvv, Sg, u, sh, ovf_s, ovf_d);
+                }
+            } else if (vec) {
+                // four quads (16 pairs) per lane in flight; the unrolled part
+                // only applies the distance filter, flagged pairs are redone
+                // one at a time from memory (they are rare)
                 const int32_t nq = n >> 2;
                 const int4 *D4 = (const int4 *)Drow;
                 const int4 *R4 = (const int4 *)R.rvD;
                 const int4 *V4 = (const int4 *)R.rvvD;
+                const int4 inf4 = make_int4(INF32, INF32, INF32, INF32);
                 for (int32_t q0 = tid; q0 < nq; q0 += 4 * bs) {
                     int4 dq[4], rq[4], vq[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int32_t q = q0 + k * bs;
-                        if (q < nq) {
-                            dq[k] = D4[q];
-                            rq[k] = R4[q];
-                            vq[k] = R.has_out ? V4[q] : make_int4(INF32, INF32, INF32, INF32);
-                        }
+                        dq[k] = (q < nq) ? D4[q] : inf4;
+                        rq[k] = (q < nq) ? R4[q] : inf4;
+                        vq[k] = (R.has_out && q < nq) ? V4[q] : inf4;
                     }
+                    uint32_t m = 0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int32_t q = q0 + k * bs;
-                        if (q < nq) {
-                            const int32_t t = q << 2;
-                            note_change(R, sc, same, t + 0, dq[k].x, rq[k].x, vq[k].x, Sg, u, sh, ovf_s, ovf_d);
-                            note_change(R, sc, same, t + 1, dq[k].y, rq[k].y, vq[k].y, Sg, u, sh, ovf_s, ovf_d);
-                            note_change(R, sc, same, t + 2, dq[k].z, rq[k].z, vq[k].z, Sg, u, sh, ovf_s, ovf_d);
-                            note_change(R, sc, same, t + 3, dq[k].w, rq[k].w, vq[k].w, Sg, u, sh, ovf_s, ovf_d);
-                        }
+                    for (int k = 0; k < 4; ++k) m |= quad_mask(dq[k], rq[k], vq[k], sc.dv) << (4 * k);
+                    while (m) {
+                        const int b = __ffs(m) - 1;
+                        m &= m - 1;
+                        const int32_t t = ((q0 + (b >> 2) * bs) << 2) + (b & 3);
+                        note_change(R, sc, same, t, Drow[t], R.rvD[t], R.has_out ? R.rvvD[t] : INF32, Sg, u, sh,
+                                    ovf_s, ovf_d);
                     }
                 }
             } else {
-                for (int32_t t = tid; t < n; t += bs)
-                    note_change(R, sc, same, t, Drow[t], R.rvD[t], R.has_out ? R.rvvD[t] : INF32, Sg, u, sh, ovf_s,
-                                ovf_d);
+                for (int32_t t = tid; t < n; t += bs) {
+                    const int32_t d0 = Drow[t], rvd = R.rvD[t], dvv = R.has_out ? R.rvvD[t] : INF32;
+                    if (may_change(d0, sc.dv, rvd, dvv)) note_change(R, sc, same, t, d0, rvd, dvv, Sg, u, sh, ovf_s, ovf_d);
+                }
             }
             __syncthreads();
             const int32_t nb = sh.nb;
             if (nb == 0) continue;
-            restricted_pass<false>(s, Drow, Sg, xc_ptr, xc_src, xc_w, u.bl_t, nb, u, -1.0, bc_delta, sh, es);
+            if (!WIDE && nb > BIG_B) {
+                if (tid == 0) J.g.biglist[atomicAdd(&ctl->big_count, 1)] = s;
+                continue;
+            }
+            if (WIDE || !small_pass(s, Drow, Sg, xc_ptr, xc_src, xc_w, u.bl_t, nb, -1.0, bc_delta, sh, es, sd))
+                restricted_pass<false>(s, Drow, Sg, xc_ptr, xc_src, xc_w, u.bl_t, nb, u, -1.0, bc_delta, sh, es);
             for (int32_t i = tid; i < nb; i += bs) {
                 const int32_t t = u.bl_t[i];
                 const int32_t d = u.bl_d[i];
@@ -896,7 +1156,8 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
                 if (lds) lds_row[t] = d;
             }
             __syncthreads();
-            restricted_pass<false>(s, Drow, Sg, yc_ptr, yc_src, yc_w, u.bl_t, nb, u, 1.0, bc_delta, sh, es);
+            if (WIDE || !small_pass(s, Drow, Sg, yc_ptr, yc_src, yc_w, u.bl_t, nb, 1.0, bc_delta, sh, es, sd))
+                restricted_pass<false>(s, Drow, Sg, yc_ptr, yc_src, yc_w, u.bl_t, nb, u, 1.0, bc_delta, sh, es);
             if (tid == 0) sh.counter += (unsigned long long)nb;
         }
         if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
@@ -904,6 +1165,21 @@ __global__ void __launch_bounds__(1024) k_source(const UpdateJob *__restrict__ j
         __syncthreads();
         if (tid == 0 && sh.counter) atomicAdd(&ctl->changed_pairs, sh.counter);
     }
+}
+
+__global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
+                                                char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
+                                                int32_t n_layout) {
+    extern __shared__ __align__(16) char dyn_lds[];
+    source_items<false>(jobs, *njobs_p, scratch, slot_bytes, lds_cap, n_layout, dyn_lds);
+}
+
+// The deferred sources, one 512-thread workgroup each (runs after k_source).
+__global__ void __launch_bounds__(512) k_source_wide(const UpdateJob *__restrict__ jobs,
+                                                     const int32_t *__restrict__ njobs_p, char *__restrict__ scratch,
+                                                     size_t slot_bytes, int32_t lds_cap, int32_t n_layout) {
+    extern __shared__ __align__(16) char dyn_lds[];
+    source_items<true>(jobs, *njobs_p, scratch, slot_bytes, lds_cap, n_layout, dyn_lds);
 }
 
 // ------------------------------------------------------------ commit -------
@@ -936,9 +1212,15 @@ __global__ void __launch_bounds__(256) k_commit(const UpdateJob *__restrict__ jo
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             GraphCtl *c = J.g.ctl;
             c->affected_last = (unsigned long long)c->a_count;
+            if (!replace) {
+                c->updates += 1;
+                c->affected_total += (unsigned long long)c->a_count;
+                c->changed_total += c->changed_pairs;
+            }
             c->a_count = 0;
             c->work_next = 0;
-            if (!replace) c->updates += 1;
+            c->big_count = 0;
+            c->big_next = 0;
         }
     }
 }
@@ -951,6 +1233,9 @@ __global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__res
         c->changed_pairs = 0;
         c->a_count = 0;
         c->work_next = 0;
+        c->t_count = 0;
+        c->big_count = 0;
+        c->big_next = 0;
     }
 }
 

@@ -114,6 +114,18 @@ bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
                         void *arena, uint64_t arena_bytes, bc_graph_id *out);
 bc_status bc_free_graph(bc_ctx *ctx, bc_graph_id g);
 
+/* A second resident graph with the state of g at this point of the stream:
+ * every update enqueued on g so far is included (device copy of g's arena,
+ * ordered on the context's stream, plus a copy of the host arc mirror).  The
+ * two then evolve independently.  Used to try updates or launch schedules on
+ * a copy (the schedule autotuner replays sample updates on clones).
+ *   arena: caller-allocated device memory of at least g's
+ *     bc_graph_bytes(n, arc_capacity, estar_capacity), 256-byte aligned,
+ *     owned by the caller, untouched by it until bc_free_graph of the clone.
+ * Errors: BC_ERR_INVALID_ARG (no such graph, null or misaligned arena),
+ * BC_ERR_CAPACITY (arena too small), BC_ERR_ADMISSION (over budget). */
+bc_status bc_clone_graph(bc_ctx *ctx, bc_graph_id g, void *arena, uint64_t arena_bytes, bc_graph_id *out);
+
 /* Incremental edge update (Section 3, Alg 3 with Lemma 2 and Alg 2): arc
  * (u,v) of a directed graph, or edge {u,v} of an undirected one (two arc
  * updates, Section 3 undirected paragraph), gets weight w.  w must be below
@@ -186,6 +198,7 @@ typedef struct {
     int64_t updates_applied;  /* updates since load */
     int64_t total_affected;   /* sum of |A| over all updates since load */
     int64_t total_changed;    /* sum of changed pairs over all updates since load */
+    int64_t deferred_sources; /* sources of the last update run by the wide kernel (bc_schedule) */
 } bc_update_stats;
 bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id g, bc_update_stats *out);
 
@@ -200,6 +213,33 @@ typedef struct {
 } bc_timing;
 bc_status bc_get_timing(bc_ctx *ctx, bc_timing *out);
 bc_status bc_reset_timing(bc_ctx *ctx);
+
+/* Launch schedule of the per-source step (the all-pairs part of Alg 3 with
+ * the dependency accumulation of Alg 1, one affected source per workgroup).
+ * It changes only how affected sources map onto workgroups, never a result:
+ * every schedule reaches the same D, sigma, DAG and (within rounding order)
+ * BC.  A source whose changed-target set has more than big_b entries is
+ * deferred to a second kernel with wider workgroups (wide_block threads),
+ * which stages the source's distance row in LDS when wide_stage is set and the
+ * row fits (n <= 36864).  Fields set to 0 keep their current value.
+ *   block:      threads per workgroup of the first kernel: 64, 128, 192, 256
+ *   slots:      its persistent workgroups (at most bc_config.slots)
+ *   big_b:      deferral threshold, 1..1024
+ *   wide_block: threads per workgroup of the wide kernel: 256 or 512
+ *   wide_stage: 1 = stage rows in LDS when they fit, 2 = never stage
+ *   wide_slots: persistent workgroups of the wide kernel (at most slots)
+ * bc_set_schedule synchronises the context's stream before it switches.
+ * Errors: BC_ERR_INVALID_ARG for a value out of range (nothing changes). */
+typedef struct {
+    int32_t block;
+    int32_t slots;
+    int32_t big_b;
+    int32_t wide_block;
+    int32_t wide_stage;
+    int32_t wide_slots;
+} bc_schedule;
+bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s);
+bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out);
 
 const char *bc_status_string(bc_status s);
 const char *bc_last_error(bc_ctx *ctx);

@@ -63,12 +63,20 @@ class bc_request(ctypes.Structure):
 class bc_update_stats(ctypes.Structure):
     _fields_ = [("affected_sources", ctypes.c_int64), ("changed_pairs", ctypes.c_int64),
                 ("estar_arcs", ctypes.c_int64), ("max_levels", ctypes.c_int64), ("updates_applied", ctypes.c_int64),
-                ("total_affected", ctypes.c_int64), ("total_changed", ctypes.c_int64)]
+                ("total_affected", ctypes.c_int64), ("total_changed", ctypes.c_int64),
+                ("deferred_sources", ctypes.c_int64)]
 
 
 class bc_timing(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_double), ("source_ms", ctypes.c_double), ("steps", ctypes.c_int64)]
 
+
+class bc_schedule(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("slots", ctypes.c_int32), ("big_b", ctypes.c_int32),
+                ("wide_block", ctypes.c_int32), ("wide_stage", ctypes.c_int32), ("wide_slots", ctypes.c_int32)]
+
+
+SCHEDULE_FIELDS = tuple(f for f, _ in bc_schedule._fields_)
 
 BC_FLAG_TIMING = 1
 
@@ -82,6 +90,7 @@ _SIGS = {
     "bc_destroy": (_i32, [_P]),
     "bc_load_graph": (_i32, [_P, _i32, _i64, _P, _P, _P, _i32, _i64, _i64, _P, _u64, ctypes.POINTER(_i32)]),
     "bc_free_graph": (_i32, [_P, _i32]),
+    "bc_clone_graph": (_i32, [_P, _i32, _P, _u64, ctypes.POINTER(_i32)]),
     "bc_update_edge": (_i32, [_P, _i32, _i32, _i32, _i64]),
     "bc_update_vertex": (_i32, [_P, _i32, _i32, _i32, ctypes.POINTER(bc_edge)]),
     "bc_submit": (_i32, [_P, _i32, ctypes.POINTER(bc_request), ctypes.POINTER(_u64), ctypes.POINTER(_i32)]),
@@ -98,6 +107,8 @@ _SIGS = {
     "bc_get_stats": (_i32, [_P, _i32, ctypes.POINTER(bc_update_stats)]),
     "bc_get_timing": (_i32, [_P, ctypes.POINTER(bc_timing)]),
     "bc_reset_timing": (_i32, [_P]),
+    "bc_set_schedule": (_i32, [_P, ctypes.POINTER(bc_schedule)]),
+    "bc_get_schedule": (_i32, [_P, ctypes.POINTER(bc_schedule)]),
     "bc_status_string": (ctypes.c_char_p, [_i32]),
     "bc_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -235,6 +246,20 @@ class Context:
     def reset_timing(self):
         self._check(_lib.bc_reset_timing(self.h), "bc_reset_timing")
 
+    def schedule(self) -> dict:
+        s = bc_schedule()
+        self._check(_lib.bc_get_schedule(self.h, ctypes.byref(s)), "bc_get_schedule")
+        return {f: getattr(s, f) for f in SCHEDULE_FIELDS}
+
+    def set_schedule(self, **fields):
+        """Changes the per-source launch schedule (bc_set_schedule); fields not
+        given keep their value."""
+        bad = set(fields) - set(SCHEDULE_FIELDS)
+        if bad:
+            raise TypeError(f"unknown schedule fields {sorted(bad)}")
+        s = bc_schedule(**{f: int(fields.get(f, 0)) for f in SCHEDULE_FIELDS})
+        self._check(_lib.bc_set_schedule(self.h, ctypes.byref(s)), "bc_set_schedule")
+
 
 class Graph:
     """A graph resident on the device (bc_graph_id)."""
@@ -306,6 +331,16 @@ class Graph:
         st = bc_update_stats()
         self.ctx._check(_lib.bc_get_stats(self.ctx.h, self.gid, ctypes.byref(st)), "bc_get_stats")
         return {f: getattr(st, f) for f, _ in bc_update_stats._fields_}
+
+    def clone(self) -> "Graph":
+        """bc_clone_graph: an independent resident copy of this graph's state."""
+        arena, addr = _device_buffer(self.nbytes, self.ctx.device)
+        gid = ctypes.c_int32()
+        self.ctx._check(_lib.bc_clone_graph(self.ctx.h, self.gid, addr, self.nbytes, ctypes.byref(gid)),
+                        "bc_clone_graph")
+        gr = Graph(self.ctx, gid.value, self.n, self.directed, arena, self.nbytes)
+        self.ctx.graphs.append(gr)
+        return gr
 
     def free(self):
         self.ctx._check(_lib.bc_free_graph(self.ctx.h, self.gid), "bc_free_graph")

@@ -51,7 +51,9 @@ struct GraphCtl {
     int32_t t_count;    // candidate targets of the update in flight
     int32_t big_count;  // deferred (large) sources of the update in flight
     int32_t big_next;   // next deferred source to process
-    int32_t pad1;
+    int32_t big_last;   // deferred sources of the last update (statistic)
+    int32_t dag_count;  // listed sources of the update in flight (row kernel output)
+    int32_t dag_next;   // next listed source of the DAG kernel
     unsigned long long changed_pairs;  // statistic of the last update
     unsigned long long affected_last;  // |A| of the last update
     unsigned long long updates;        // updates applied since load
@@ -68,6 +70,27 @@ struct SrcScal {
     uint64_t sv;
     uint64_t hv;
 };
+
+// A source whose changed targets the row kernel listed: entries
+// [off, off + nb) of the step's target pool.
+struct DItem {
+    int32_t s;
+    int32_t nb;
+    int64_t off;
+};
+
+// Target pool of one update step: the changed targets (with their new d and
+// sigma) of every listed source of every job, bump-allocated.
+struct StepPool {
+    int32_t *t;
+    int32_t *d;
+    uint64_t *s;
+    unsigned long long *next;
+    int64_t cap;
+};
+
+// Most changed targets the row kernel lists for one source (in LDS).
+constexpr int32_t LCAP = 1024;
 
 // Device pointers and sizes of one graph.  A copy rides in every job.
 struct GraphPtrs {
@@ -87,6 +110,7 @@ struct GraphPtrs {
     SrcScal *scal;    // n
     int32_t *alist;   // n, affected sources
     int32_t *biglist; // n, affected sources deferred to the wide kernel
+    DItem *dlist;     // n, sources listed by the row kernel
     int32_t *rv_D;    // snapshot of row v before the update (n)
     uint64_t *rv_S;
     int32_t *rvv_D;   // row v'' after the Out phase (n)
@@ -94,6 +118,10 @@ struct GraphPtrs {
     int32_t *tlist;   // candidate targets of the update in flight (n)
     int32_t *tl_rvD;  // d(v,t) for each candidate (compact copy)
     int32_t *tl_rvvD; // d''(v,t) for each candidate (compact copy)
+    int32_t *f_any;   // n: min of f_in and f_out, where f_in = d(v,t) if the In phase can
+                      // change a pair (s,t), else INF32, and f_out likewise for the Out
+                      // phase with d''(v,t)
+    int32_t *f_out;
     GraphCtl *ctl;
     // Full arc set by tail and by head (static recompute and E* build).
     int32_t *arc_ptr, *arc_dst, *arc_w;

@@ -30,7 +30,7 @@ constexpr int JCAP = 256;          // jobs per staging slot
 constexpr size_t MISC_BYTES = 4096;
 constexpr int DEFAULT_SLOTS = 1024; // 4 persistent workgroups per CU of an MI355X
 constexpr int DEFAULT_BLOCK = 256;  // 4 waves per affected source
-constexpr int WIDE_LDS_MAX = 16384; // rows the wide kernel stages in LDS (two workgroups per CU)
+constexpr int DEFAULT_WIDE_BLOCK = 512;
 constexpr int64_t W_MAX = (int64_t)INF32 - 1;
 
 size_t ring_slot_bytes() { return align256(256 + sizeof(UpdateJob) * JCAP); }
@@ -127,9 +127,17 @@ struct bc_ctx {
     uint64_t scratch_bytes = 0;
     uint64_t budget = 0;
     uint64_t in_use = 0;
-    int slots = DEFAULT_SLOTS;
-    int block = DEFAULT_BLOCK;
+    int slots = DEFAULT_SLOTS;  // workgroup slots the scratch buffer was sized for
     int cu_count = 256;
+    // launch schedule of the per-source step (bc_schedule)
+    int block = DEFAULT_BLOCK;
+    int run_slots = 0;   // 0: every usable slot
+    int big_b = BIG_B;
+    int wide_block = DEFAULT_WIDE_BLOCK;
+    int wide_stage = 1;
+    int wide_slots = 0;  // 0: one workgroup per CU when staging, else two
+    size_t wide_lds_limit = 0;  // dynamic LDS the wide kernel may use
+    int rows_grid = 1024;       // workgroups of the row kernel (all resident)
     int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
     int32_t src_lds_max = 8192;  // per-source kernel stages rows up to this n in LDS
     std::vector<GraphRec *> graphs;
@@ -180,12 +188,27 @@ char *ring_dev(bc_ctx *ctx, int r) { return ctx->scratch + (size_t)r * ring_slot
 UpdateJob *ring_jobs_dev(bc_ctx *ctx, int r) { return (UpdateJob *)(ring_dev(ctx, r) + 256); }
 int32_t *ring_njobs_dev(bc_ctx *ctx, int r) { return (int32_t *)ring_dev(ctx, r); }
 char *misc_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes(); }
-char *slots_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes() + MISC_BYTES; }
+
+// Target pool of an update step (after the misc area): 256 entries per vertex
+// of the largest graph, at least 2^20; 16 bytes per entry.
+int64_t pool_entries(int32_t n_max) { return std::max<int64_t>(int64_t(1) << 20, 256 * (int64_t)n_max); }
+size_t pool_bytes(int32_t n_max) { return align256(16 * (size_t)pool_entries(n_max)); }
+char *pool_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes() + MISC_BYTES; }
+StepPool step_pool(bc_ctx *ctx) {
+    StepPool p;
+    p.cap = pool_entries(ctx->n_layout);
+    p.t = (int32_t *)pool_dev(ctx);
+    p.d = p.t + p.cap;
+    p.s = (uint64_t *)(p.d + p.cap);
+    p.next = (unsigned long long *)(misc_dev(ctx) + 2048);
+    return p;
+}
+char *slots_dev(bc_ctx *ctx) { return pool_dev(ctx) + pool_bytes(ctx->n_layout); }
 
 int usable_slots(bc_ctx *ctx, int32_t n_max, size_t *slot_bytes) {
     const size_t sb = slot_bytes_for(n_max);
     *slot_bytes = sb;
-    const uint64_t fixed = ring_bytes() + MISC_BYTES;
+    const uint64_t fixed = ring_bytes() + MISC_BYTES + pool_bytes(n_max);
     if (ctx->scratch_bytes <= fixed) return 0;
     const uint64_t avail = (ctx->scratch_bytes - fixed) / sb;
     return (int)std::min<uint64_t>((uint64_t)ctx->slots, avail);
@@ -196,7 +219,7 @@ int lds_cap_for(int32_t n_max) { return std::min<int32_t>(n_max, LDS_ROW_MAX); }
 // Dynamic LDS of k_source / k_delta_row: staged row, 20 bytes per thread of
 // expansion arrays, and the small sub-DAG table.
 size_t source_lds_bytes(int lds_cap, int block) {
-    return align256((size_t)lds_cap * 4) + align256(20 * (size_t)block) + small_dag_bytes();
+    return align256((size_t)lds_cap * 4) + align256(XB * (size_t)block) + small_dag_bytes();
 }
 
 // Arena layout of one graph (every piece 256-byte aligned).
@@ -222,6 +245,8 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
            oyw = c.take(4 * (size_t)es_cap);
     size_t ocnt = c.take(4 * ((size_t)n + 1));
     size_t osc = c.take(sizeof(SrcScal) * (size_t)n), oal = c.take(4 * (size_t)n), obig = c.take(4 * (size_t)n);
+    size_t odl2 = c.take(sizeof(DItem) * (size_t)n);
+    size_t ofi = c.take(4 * (size_t)n), ofo = c.take(4 * (size_t)n);
     size_t orvd = c.take(4 * (size_t)n), orvs = c.take(8 * (size_t)n);
     size_t orvvd = c.take(4 * (size_t)n), orvvs = c.take(8 * (size_t)n), orvvh = c.take(8 * (size_t)n);
     size_t otl = c.take(4 * (size_t)n), otlr = c.take(4 * (size_t)n), otlrr = c.take(4 * (size_t)n);
@@ -254,6 +279,9 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     P.scal = (SrcScal *)(base + osc);
     P.alist = (int32_t *)(base + oal);
     P.biglist = (int32_t *)(base + obig);
+    P.dlist = (DItem *)(base + odl2);
+    P.f_any = (int32_t *)(base + ofi);
+    P.f_out = (int32_t *)(base + ofo);
     P.rv_D = (int32_t *)(base + orvd);
     P.rv_S = (uint64_t *)(base + orvs);
     P.rvv_D = (int32_t *)(base + orvvd);
@@ -352,18 +380,21 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
     hipStream_t st = ctx->stream;
     const int g_elem = (int)std::min<int64_t>(((int64_t)L.n_max + 255) / 256, 2048);
     const int g_wave = (int)std::min<int64_t>(((int64_t)L.n_max * 64 + 255) / 256, 4096);
+    const StepPool pool = step_pool(ctx);
     if (part == 0) {
-        hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, jobs, nj, pool);
         hipLaunchKernelGGL(k_scan, dim3(g_elem), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_targets, dim3(g_elem), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_count<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_scan<ES_MERGE>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
     } else if (part == 1) {
+        hipLaunchKernelGGL(k_rows, dim3(ctx->rows_grid), dim3(256), 0, st, jobs, nj, ctx->big_b, pool);
         hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), source_lds_bytes(L.src_lds_cap, ctx->block), st,
-                           jobs, nj, slots_dev(ctx), L.slot_bytes, L.src_lds_cap, L.n_layout);
-        hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(512), source_lds_bytes(L.wide_lds_cap, 512), st,
-                           jobs, nj, slots_dev(ctx), L.slot_bytes, L.wide_lds_cap, L.n_layout);
+                           jobs, nj, slots_dev(ctx), L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
+        hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(ctx->wide_block),
+                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block), st, jobs, nj, slots_dev(ctx),
+                           L.slot_bytes, L.wide_lds_cap, L.n_layout);
     } else {
         hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
@@ -399,13 +430,16 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     L->n_layout = ctx->n_layout;
     L->slots = usable_slots(ctx, ctx->n_layout, &L->slot_bytes);
     if (L->slots < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for one work slot at this n");
+    if (ctx->run_slots > 0) L->slots = std::min(L->slots, ctx->run_slots);
     L->lds_cap = lds_cap_for(L->n_max);
     // the row is staged only when it fits; otherwise no LDS is reserved for it
     L->src_lds_cap = L->n_max <= ctx->src_lds_max ? L->n_max : 0;
-    // wide kernel: two 512-thread workgroups per CU; its row staging leaves
-    // room for the expansion arrays and the small-DAG table
-    L->wide_slots = std::min(L->slots, 2 * ctx->cu_count);
-    L->wide_lds_cap = L->n_max <= WIDE_LDS_MAX ? L->n_max : 0;
+    // wide kernel: the row is staged when it fits beside the expansion arrays
+    // and the small-DAG table; one workgroup per CU then, else two
+    const bool stage = ctx->wide_stage == 1 && source_lds_bytes(L->n_max, ctx->wide_block) <= ctx->wide_lds_limit;
+    L->wide_lds_cap = stage ? L->n_max : 0;
+    const int per_cu = stage && source_lds_bytes(L->n_max, ctx->wide_block) * 2 > ctx->wide_lds_limit ? 1 : 2;
+    L->wide_slots = std::min(L->slots, ctx->wide_slots > 0 ? ctx->wide_slots : per_cu * ctx->cu_count);
     return BC_OK;
 }
 
@@ -640,19 +674,20 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
     return BC_OK;
 }
 
-bc_status set_lds_limit(bc_ctx *ctx, const void *fn) {
+bc_status set_lds_limit(bc_ctx *ctx, const void *fn, size_t *limit = nullptr) {
     hipFuncAttributes attr;
     HIPCHK(hipFuncGetAttributes(&attr, fn));
     // all of a gfx950 workgroup's 160 KiB of LDS, less what the kernel declares statically
     const int bytes = 160 * 1024 - (int)attr.sharedSizeBytes;
     HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    if (limit) *limit = (size_t)bytes;
     return BC_OK;
 }
 
 bc_status set_lds_limits(bc_ctx *ctx) {
     bc_status st;
     if ((st = set_lds_limit(ctx, (const void *)k_source))) return st;
-    if ((st = set_lds_limit(ctx, (const void *)k_source_wide))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_source_wide, &ctx->wide_lds_limit))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_sssp))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_static))) return st;
     return set_lds_limit(ctx, (const void *)k_delta_row);
@@ -675,7 +710,7 @@ uint64_t bc_graph_bytes(int32_t n, int64_t arc_capacity, int64_t estar_capacity)
 uint64_t bc_scratch_bytes(int32_t n_max, int32_t slots) {
     if (n_max <= 0) return 0;
     if (slots <= 0) slots = DEFAULT_SLOTS;
-    return ring_bytes() + MISC_BYTES + (uint64_t)slots * slot_bytes_for(n_max);
+    return ring_bytes() + MISC_BYTES + pool_bytes(n_max) + (uint64_t)slots * slot_bytes_for(n_max);
 }
 
 const char *bc_status_string(bc_status s) {
@@ -762,6 +797,13 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
         }
     }
     ctx->timing = (cfg->flags & BC_FLAG_TIMING) != 0;
+    {
+        // the row kernel is persistent: as many workgroups as stay resident
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_rows, 256, 0);
+        if (e != hipSuccess) return bail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        ctx->rows_grid = std::max(1, per_cu) * ctx->cu_count;
+    }
     if (set_lds_limits(ctx) != BC_OK) {
         fprintf(stderr, "bcinc: %s\n", ctx->last_error.c_str());
         delete ctx;
@@ -772,6 +814,46 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
     e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return bail(e, "hipStreamSynchronize");
     *out = ctx;
+    return BC_OK;
+}
+
+bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s) {
+    if (!ctx || !s) return BC_ERR_INVALID_ARG;
+    const int block = s->block ? s->block : ctx->block;
+    const int slots = s->slots ? s->slots : ctx->run_slots;
+    const int big_b = s->big_b ? s->big_b : ctx->big_b;
+    const int wide_block = s->wide_block ? s->wide_block : ctx->wide_block;
+    const int wide_stage = s->wide_stage ? s->wide_stage : ctx->wide_stage;
+    const int wide_slots = s->wide_slots ? s->wide_slots : ctx->wide_slots;
+    if (block < 64 || block > 256 || block % 64 != 0 || slots < 0 || slots > ctx->slots || big_b < 1 || big_b > LCAP ||
+        (wide_block != 256 && wide_block != 512) || (wide_stage != 1 && wide_stage != 2) || wide_slots < 0 ||
+        wide_slots > ctx->slots)
+        return fail(ctx, BC_ERR_INVALID_ARG, "schedule value out of range");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // captured step graphs hold the old launch shapes
+    for (auto &kv : ctx->graph_cache) {
+        if (kv.second.exec) HIPCHK(hipGraphExecDestroy(kv.second.exec));
+        if (kv.second.graph) HIPCHK(hipGraphDestroy(kv.second.graph));
+    }
+    ctx->graph_cache.clear();
+    ctx->block = block;
+    ctx->run_slots = slots;
+    ctx->big_b = big_b;
+    ctx->wide_block = wide_block;
+    ctx->wide_stage = wide_stage;
+    ctx->wide_slots = wide_slots;
+    return BC_OK;
+}
+
+bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out) {
+    if (!ctx || !out) return BC_ERR_INVALID_ARG;
+    out->block = ctx->block;
+    out->slots = ctx->run_slots;
+    out->big_b = ctx->big_b;
+    out->wide_block = ctx->wide_block;
+    out->wide_stage = ctx->wide_stage;
+    out->wide_slots = ctx->wide_slots;
     return BC_OK;
 }
 
@@ -875,6 +957,31 @@ bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
         ctx->in_use -= arena_bytes;
         return st;
     }
+    return BC_OK;
+}
+
+bc_status bc_clone_graph(bc_ctx *ctx, bc_graph_id gid, void *arena, uint64_t arena_bytes, bc_graph_id *out) {
+    GraphRec *src = get_graph(ctx, gid);
+    if (!src) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    if (!out || !arena) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_clone_graph");
+    if (((uintptr_t)arena & 255) != 0) return fail(ctx, BC_ERR_INVALID_ARG, "arena not 256-byte aligned");
+    const uint64_t need = bc_graph_bytes(src->n, src->arc_cap, src->es_cap);
+    if (arena_bytes < need) return fail(ctx, BC_ERR_CAPACITY, "arena smaller than bc_graph_bytes");
+    if (ctx->budget && ctx->in_use + arena_bytes > ctx->budget)
+        return fail(ctx, BC_ERR_ADMISSION, "graph state would exceed the memory budget");
+    HIPCHK(hipSetDevice(ctx->device));
+    // stream-ordered: the copy sees every update enqueued on the source so far,
+    // which the host mirror already holds
+    HIPCHK(hipMemcpyAsync(arena, src->arena, need, hipMemcpyDeviceToDevice, ctx->stream));
+    GraphRec *g = new GraphRec(*src);
+    g->arena = (char *)arena;
+    g->arena_bytes = arena_bytes;
+    size_t total = 0;
+    g->P = carve((char *)arena, g->n, g->arc_cap, g->es_cap, &total);
+    g->P.directed = g->directed;
+    ctx->graphs.push_back(g);
+    ctx->in_use += arena_bytes;
+    *out = (bc_graph_id)(ctx->graphs.size() - 1);
     return BC_OK;
 }
 
@@ -1145,6 +1252,7 @@ bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id gid, bc_update_stats *out) {
     out->updates_applied = (int64_t)g->updates;
     out->total_affected = (int64_t)c.affected_total;
     out->total_changed = (int64_t)c.changed_total;
+    out->deferred_sources = c.big_last;
     return BC_OK;
 }
 

@@ -35,11 +35,13 @@ __device__ __forceinline__ uint64_t add_chk(uint64_t a, uint64_t b, bool &ovf) {
 // d'(s,v) = d(s,v); case 3 adds sigma'_sv * sigma_vt when d'(s,v) < d(s,v);
 // case 4 replaces both.  The arc update is the special case E_i = {(u,v)}:
 // it reproduces the three cases of Lemma 2.  For t = v it returns Alg 4's
-// d'(s,v), sigma'_sv.
+// d'(s,v), sigma'_sv.  An unreachable pair (d0 = INF32) with a finite c is
+// always taken, so that a c of 2^31-1 or more reaches the caller's distance
+// overflow check.
 __device__ __forceinline__ bool in_rule(int32_t d0, int32_t dv, int32_t dvt, int64_t &c) {
     if (dv == INF32 || dvt == INF32) return false;
     c = (int64_t)dv + (int64_t)dvt;
-    return c <= (int64_t)d0;
+    return c <= (int64_t)d0 || d0 == INF32;
 }
 
 // A graph whose E* outgrew its buffers is dead until reloaded: every kernel
@@ -178,7 +180,10 @@ __global__ void __launch_bounds__(256) k_scan(const UpdateJob *__restrict__ jobs
 // the Out phase only if row v'' changed at t (d''(v,t) < d'(v,t), or a tie
 // with new paths).  The union T is listed once per update, with row v and
 // row v'' at t copied next to it, so each affected source scans T instead of
-// its whole row.
+// its whole row when T is short.  For whole-row scans the two tests are kept
+// per target as filter rows: f_out = d''(v,t) on Out candidates, INF32
+// elsewhere, and f_any = min(f_in, f_out) with f_in = d(v,t) on In
+// candidates, INF32 elsewhere.
 __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
     const int njobs = *njobs_p;
     for (int j = 0; j < njobs; ++j) {
@@ -189,7 +194,7 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
         bool ovf_s = false, ovf_d = false;
         for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
             const int32_t t = (int32_t)(base + threadIdx.x);
-            bool cand = false;
+            bool cand = false, cand_out = false;
             int32_t dvt = INF32, cur = INF32;
             if (t < n) {
                 dvt = D[(size_t)v * n + t];
@@ -202,6 +207,7 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
                         }
                     }
                 }
+                const int32_t f_in = cand ? dvt : INF32;
                 cur = dvt;
                 if (J.n_out > 0) {
                     const uint64_t svt = S[(size_t)v * n + t];
@@ -244,8 +250,12 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
                     J.g.rvv_D[t] = cur;
                     J.g.rvv_S[t] = sig;
                     J.g.rvv_H[t] = hat;
-                    if (cur < dvt || hat != 0) cand = true;
+                    cand_out = cur < dvt || hat != 0;
+                    cand = cand || cand_out;
                 }
+                const int32_t f_out = cand_out ? cur : INF32;
+                J.g.f_out[t] = f_out;
+                J.g.f_any[t] = min(f_in, f_out);
             }
             const uint64_t mask = __ballot(cand);
             if (mask) {
@@ -443,7 +453,7 @@ __global__ void __launch_bounds__(256) k_es_scatter(const UpdateJob *__restrict_
 struct BlockShared {
     int32_t head, tail, next, nlev;
     int32_t item;
-    int32_t nb;
+    int32_t nb, nf;
     int32_t ovf, progress;
     int32_t scan[40];
     unsigned long long counter;
@@ -583,15 +593,20 @@ __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t 
 }
 
 // Arc-parallel expansion helpers: the in-arcs of a list of vertices are
-// flattened with a block-wide scan of their in-degrees, so every lane takes
-// one arc and all predecessor loads of a level are in flight together.
+// flattened with a block-wide scan of their in-degrees; each lane takes XU
+// consecutive arcs and issues their loads together.
+constexpr int XU = 4;
+
 struct ExpandShared {
-    int32_t *off, *vtx, *beg;
+    int32_t *off, *vtx, *beg, *dx;
     double *val;
 };
 
+// Bytes of expansion arrays per thread (val, off, vtx, beg, dx).
+constexpr size_t XB = 24;
+
 // Dynamic LDS of the per-source kernels: the staged row (4 * lds_cap bytes),
-// the expansion arrays (20 bytes per thread), then the small-DAG table.
+// the expansion arrays (XB bytes per thread), then the small-DAG table.
 __device__ __forceinline__ ExpandShared expand_at(char *dyn, int32_t lds_cap) {
     ExpandShared es;
     char *p = dyn + align256((size_t)lds_cap * 4);
@@ -599,6 +614,7 @@ __device__ __forceinline__ ExpandShared expand_at(char *dyn, int32_t lds_cap) {
     es.off = (int32_t *)(p + 8 * blockDim.x);
     es.vtx = es.off + blockDim.x;
     es.beg = es.vtx + blockDim.x;
+    es.dx = es.beg + blockDim.x;
     return es;
 }
 
@@ -612,16 +628,40 @@ __device__ __forceinline__ int32_t find_owner(const ExpandShared &es, int32_t nv
     return lo;
 }
 
+// Arcs jb .. jb+XU-1 of an expansion chunk of nv vertices and total arcs:
+// for each, the owning chunk entry iv and the arc id ev (ok false past the
+// end).  One binary search, then a forward walk (the arcs are consecutive).
+__device__ __forceinline__ void chunk_arcs(const ExpandShared &es, const int32_t nv, const int32_t total,
+                                           const int32_t jb, int32_t (&iv)[XU], int32_t (&ev)[XU], bool (&ok)[XU]) {
+    int32_t i = find_owner(es, nv, jb);
+#pragma unroll
+    for (int k = 0; k < XU; ++k) {
+        const int32_t j = jb + k;
+        ok[k] = j < total;
+        iv[k] = 0;
+        ev[k] = 0;
+        if (ok[k]) {
+            while (i + 1 < nv && es.off[i + 1] <= j) ++i;
+            iv[k] = i;
+            ev[k] = es.beg[i] + (j - es.off[i]);
+        }
+    }
+}
+
 // Partial dependency of source s over a target set B (one workgroup):
 //   delta_B(x) = sum_{t in B} delta_st(x)
 //              = sum_{w : x in P_s(w)} sigma_sx / sigma_sw * ([w in B] + delta_B(w)),
 // Eq.4 with the indicator of B in place of 1.  It is non-zero only on the
-// ancestors of B in DAG(s), so only that sub-DAG is visited:
-//   1. backward BFS from B over DAG predecessor arcs (E* by head, Eq.1),
-//      counting each sub-DAG vertex's successors inside the sub-DAG,
-//   2. Kahn from the sub-DAG's sinks (a reverse topological order, which
-//      serves the accumulation, Section 2.1): each vertex pushes its term to
-//      its predecessors once all its successors have pushed to it.
+// ancestors of B in DAG(s):
+//   1. the vertices to visit and their successor counts: either a backward
+//      BFS from B over DAG predecessor arcs (E* by head, Eq.1), counting each
+//      sub-DAG vertex's successors inside the sub-DAG, or (full) one sweep
+//      over all of E* counting every reachable vertex's DAG successors, for
+//      large B where the sub-DAG is most of DAG(s) (vertices outside it get
+//      delta_B = 0 and change nothing),
+//   2. Kahn from the sinks (a reverse topological order, which serves the
+//      accumulation, Section 2.1): each vertex pushes its term to its
+//      predecessors once all its successors have pushed to it.
 // Targets whose d(s,t) and sigma_st do not change keep the same set of
 // shortest paths, so delta_st is unchanged for them and the BC difference of
 // source s is delta'_B - delta_B with B the changed targets (Alg 3 re-runs
@@ -629,67 +669,114 @@ __device__ __forceinline__ int32_t find_owner(const ExpandShared &es, int32_t nv
 // OUT_ROW: delta_B goes to out[x] (introspection); otherwise
 // out[x] += sign * delta_B(x) for x != s (out = the BC difference).
 template <bool OUT_ROW>
-__device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Srow,
-                                const int32_t *__restrict__ cptr, const int32_t *__restrict__ csrc,
+__device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t *__restrict__ Drow,
+                                const uint64_t *__restrict__ Srow, const int32_t *__restrict__ cptr,
+                                const int32_t *__restrict__ csrc, const int32_t *__restrict__ cdst,
                                 const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
-                                const USlot &u, const double sign, double *out, BlockShared &sh,
+                                const bool full, const USlot &u, const double sign, double *out, BlockShared &sh,
                                 const ExpandShared &es) {
     const int tid = threadIdx.x, bs = blockDim.x;
-    if (tid == 0) sh.next = 0;
+    if (tid == 0) {
+        sh.next = 0;
+        sh.tail = 0;
+    }
     __syncthreads();
     for (int32_t i = tid; i < nB; i += bs) {
         const int32_t t = Bt[i];
         if (t == s || Drow[t] == INF32) continue;
-        u.outdeg[t] = W_VIS | W_B;
-        u.sub[atomicAdd(&sh.next, 1)] = t;
+        if (full) {
+            u.outdeg[t] = W_B;
+        } else {
+            u.outdeg[t] = W_VIS | W_B;
+            u.sub[atomicAdd(&sh.next, 1)] = t;
+        }
     }
     __syncthreads();
-    int32_t lo = 0, hi = sh.next;
-    __syncthreads();
-    // 1. backward BFS, one level per round, arc-parallel within a round
-    while (lo < hi) {
-        for (int32_t c = lo; c < hi; c += bs) {
-            const int32_t idx = c + tid;
-            int32_t x = 0, b0 = 0, deg = 0;
-            if (idx < hi) {
-                x = u.sub[idx];
-                b0 = cptr[x];
-                deg = cptr[x + 1] - b0;
-            }
-            int32_t total;
-            const int32_t off = block_excl_scan(deg, sh.scan, total);
-            es.off[tid] = off;
-            es.vtx[tid] = x;
-            es.beg[tid] = b0;
-            __syncthreads();
-            const int32_t nv = min(bs, hi - c);
-            for (int32_t j = tid; j < total; j += bs) {
-                const int32_t i = find_owner(es, nv, j);
-                const int32_t xv = es.vtx[i];
-                const int32_t e = es.beg[i] + (j - es.off[i]);
-                const int32_t a = csrc[e];
-                const int32_t da = Drow[a];
-                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)Drow[xv]) {
-                    // one more successor inside the sub-DAG; the first arc
-                    // found into a vertex not yet seen adds it to the list
-                    if ((atomicAdd(&u.outdeg[a], 1) & (W_COUNT | W_VIS)) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
+    int32_t nsub;
+    if (full) {
+        // 1. every DAG(s) arc: one more successor of its tail
+        const int32_t m = cptr[n];
+        for (int32_t e0 = tid; e0 < m; e0 += XU * bs) {
+            int32_t av[XU], bv[XU], wv[XU];
+#pragma unroll
+            for (int k = 0; k < XU; ++k) {
+                const int32_t e = e0 + k * bs;
+                av[k] = 0;
+                bv[k] = 0;
+                wv[k] = 0;
+                if (e < m) {
+                    av[k] = csrc[e];
+                    bv[k] = cdst[e];
+                    wv[k] = cw[e];
                 }
             }
+#pragma unroll
+            for (int k = 0; k < XU; ++k) {
+                if (e0 + k * bs >= m) continue;
+                const int32_t da = Drow[av[k]];
+                if (da != INF32 && (int64_t)da + wv[k] == (int64_t)Drow[bv[k]]) atomicAdd(&u.outdeg[av[k]], 1);
+            }
+        }
+        __syncthreads();
+        for (int32_t x = tid; x < n; x += bs)
+            if (Drow[x] != INF32 && (u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
+        nsub = n;
+    } else {
+        int32_t lo = 0, hi = sh.next;
+        __syncthreads();
+        // 1. backward BFS, one level per round, arc-parallel within a round
+        while (lo < hi) {
+            for (int32_t c = lo; c < hi; c += bs) {
+                const int32_t idx = c + tid;
+                int32_t x = 0, b0 = 0, deg = 0, dx = 0;
+                if (idx < hi) {
+                    x = u.sub[idx];
+                    b0 = cptr[x];
+                    deg = cptr[x + 1] - b0;
+                    dx = Drow[x];
+                }
+                int32_t total;
+                const int32_t off = block_excl_scan(deg, sh.scan, total);
+                es.off[tid] = off;
+                es.vtx[tid] = x;
+                es.beg[tid] = b0;
+                es.dx[tid] = dx;
+                __syncthreads();
+                const int32_t nv = min(bs, hi - c);
+                for (int32_t jb = tid * XU; jb < total; jb += bs * XU) {
+                    int32_t iv[XU], ev[XU], av[XU], wv[XU];
+                    bool ok[XU];
+                    chunk_arcs(es, nv, total, jb, iv, ev, ok);
+#pragma unroll
+                    for (int k = 0; k < XU; ++k) {
+                        av[k] = ok[k] ? csrc[ev[k]] : 0;
+                        wv[k] = ok[k] ? cw[ev[k]] : 0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < XU; ++k) {
+                        if (!ok[k]) continue;
+                        const int32_t a = av[k];
+                        const int32_t da = Drow[a];
+                        // one more successor inside the sub-DAG; the first arc
+                        // found into a vertex not yet seen adds it to the list
+                        if (da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]])
+                            if ((atomicAdd(&u.outdeg[a], 1) & (W_COUNT | W_VIS)) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
+                    }
+                }
+                __syncthreads();
+            }
+            lo = hi;
+            hi = sh.next;
             __syncthreads();
         }
-        lo = hi;
-        hi = sh.next;
-        __syncthreads();
-    }
-    const int32_t nsub = hi;
-    // 2. Kahn from the sinks of the sub-DAG
-    if (tid == 0) sh.tail = 0;
-    __syncthreads();
-    for (int32_t i = tid; i < nsub; i += bs) {
-        const int32_t x = u.sub[i];
-        if ((u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
+        nsub = hi;
+        for (int32_t i = tid; i < nsub; i += bs) {
+            const int32_t x = u.sub[i];
+            if ((u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
+        }
     }
     __syncthreads();
+    // 2. Kahn from the sinks
     int32_t qn = sh.tail;
     int32_t *qa = u.q1, *qb = u.q2;
     __syncthreads();
@@ -697,7 +784,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
         if (tid == 0) sh.tail = 0;
         for (int32_t c = 0; c < qn; c += bs) {
             const int32_t idx = c + tid;
-            int32_t x = 0, b0 = 0, deg = 0;
+            int32_t x = 0, b0 = 0, deg = 0, dx = 0;
             double coef = 0.0;
             if (idx < qn) {
                 x = qa[idx];
@@ -710,23 +797,43 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
                 coef = (((u.outdeg[x] & W_B) ? 1.0 : 0.0) + ax) / (double)Srow[x];
                 b0 = cptr[x];
                 deg = cptr[x + 1] - b0;
+                dx = Drow[x];
             }
             int32_t total;
             const int32_t off = block_excl_scan(deg, sh.scan, total);
             es.off[tid] = off;
             es.vtx[tid] = x;
             es.beg[tid] = b0;
+            es.dx[tid] = dx;
             es.val[tid] = coef;
             __syncthreads();
             const int32_t nv = min(bs, qn - c);
-            for (int32_t j = tid; j < total; j += bs) {
-                const int32_t i = find_owner(es, nv, j);
-                const int32_t xv = es.vtx[i];
-                const int32_t e = es.beg[i] + (j - es.off[i]);
-                const int32_t a = csrc[e];
-                const int32_t da = Drow[a];
-                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)Drow[xv]) {
-                    atomicAdd(&u.acc[a], (double)Srow[a] * es.val[i]);
+            for (int32_t jb = tid * XU; jb < total; jb += bs * XU) {
+                int32_t iv[XU], ev[XU], av[XU], wv[XU];
+                bool ok[XU];
+                chunk_arcs(es, nv, total, jb, iv, ev, ok);
+#pragma unroll
+                for (int k = 0; k < XU; ++k) {
+                    av[k] = ok[k] ? csrc[ev[k]] : 0;
+                    wv[k] = ok[k] ? cw[ev[k]] : 0;
+                }
+                double cf[XU];
+#pragma unroll
+                for (int k = 0; k < XU; ++k) {
+                    cf[k] = 0.0;
+                    if (!ok[k]) continue;
+                    const int32_t da = Drow[av[k]];
+                    ok[k] = da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]];
+                    if (ok[k]) cf[k] = es.val[iv[k]];
+                }
+                uint64_t sa[XU];
+#pragma unroll
+                for (int k = 0; k < XU; ++k) sa[k] = (ok[k] && cf[k] != 0.0) ? Srow[av[k]] : 0;
+#pragma unroll
+                for (int k = 0; k < XU; ++k) {
+                    if (!ok[k]) continue;
+                    const int32_t a = av[k];
+                    if (cf[k] != 0.0) atomicAdd(&u.acc[a], (double)sa[k] * cf[k]);
                     if ((atomicSub(&u.outdeg[a], 1) & W_COUNT) == 1) qb[atomicAdd(&sh.tail, 1)] = a;
                 }
             }
@@ -738,10 +845,17 @@ __device__ void restricted_pass(const int32_t s, const int32_t *__restrict__ Dro
         qb = tmp;
         __syncthreads();
     }
-    for (int32_t i = tid; i < nsub; i += bs) {
-        const int32_t x = u.sub[i];
-        u.outdeg[x] = 0;
-        u.acc[x] = 0.0;
+    if (full) {
+        for (int32_t x = tid; x < n; x += bs) {
+            u.outdeg[x] = 0;
+            u.acc[x] = 0.0;
+        }
+    } else {
+        for (int32_t i = tid; i < nsub; i += bs) {
+            const int32_t x = u.sub[i];
+            u.outdeg[x] = 0;
+            u.acc[x] = 0.0;
+        }
     }
     __syncthreads();
 }
@@ -993,172 +1107,196 @@ __device__ __forceinline__ bool pair_update(const RowV &R, const SrcScal &sc, co
 
 // Quick reject: neither phase can reach pair (s,t) unless d'(s,v) plus the
 // row-v distance is at most the current d(s,t) (Lemma 4 case 1 otherwise).
-__device__ __forceinline__ bool may_change(int32_t d0, int32_t dv, int32_t rvd, int32_t dvv) {
+// in_on is false for a source whose In phase is void: d'(s,v) = d(s,v) with
+// no new paths into v (sigma-hat'_sv = 0), where a tie adds 0 paths and a
+// strict gain would break the triangle inequality of the old distances.
+__device__ __forceinline__ bool may_change(int32_t d0, int32_t dv, int32_t rvd, int32_t dvv, bool in_on) {
     if (dv == INF32) return false;
-    const bool in = rvd != INF32 && (int64_t)dv + rvd <= (int64_t)d0;
-    const bool out = dvv != INF32 && (int64_t)dv + dvv <= (int64_t)d0;
+    const bool in = in_on && rvd != INF32 && ((int64_t)dv + rvd <= (int64_t)d0 || d0 == INF32);
+    const bool out = dvv != INF32 && ((int64_t)dv + dvv <= (int64_t)d0 || d0 == INF32);
     return in || out;
 }
 
-// Slow path of the row scan (a pair that passed may_change): full Lemma 4
-// update and, if the pair changes, an entry in the B list.  Kept out of line
-// so the unrolled scan stays small.
-__device__ __forceinline__ void note_change(const RowV &R, const SrcScal &sc, const bool same, const int32_t t,
-                                         const int32_t d0, const int32_t rvd, const int32_t dvv, const uint64_t *Sg,
-                                         const USlot &u, BlockShared &sh, bool &ovf_s, bool &ovf_d) {
-    int32_t d;
-    uint64_t sg;
-    if (pair_update(R, sc, same, t, d0, rvd, dvv, Sg, d, sg, ovf_s, ovf_d)) {
-        const int32_t pos = atomicAdd(&sh.nb, 1);
-        u.bl_t[pos] = t;
-        u.bl_d[pos] = d;
-        u.bl_s[pos] = sg;
+// The same test against one filter row f (f_any, or f_out when the In phase
+// is void) for a finite d'(s,v): d'(s,v) + f(t) <= d(s,t), or t unreachable.
+// Finite distances are below 2^31-1, so the sum of two fits in 32 unsigned
+// bits.
+__device__ __forceinline__ bool may_change1(int32_t d0, int32_t dv, int32_t f) {
+    return f != INF32 && ((uint32_t)dv + (uint32_t)f <= (uint32_t)d0 || d0 == INF32);
+}
+
+// Changed-target list a row scan fills: entries go to (t, d, s) up to cap;
+// the count (BlockShared::nb) keeps going past cap, and then the list is
+// incomplete.
+struct BList {
+    int32_t *t, *d;
+    uint64_t *s;
+    int32_t cap;
+};
+
+// Bit mask of the pairs of one quad that may change (dv finite).
+__device__ __forceinline__ uint32_t quad_mask(const int4 d, const int4 f, const int32_t dv) {
+    return (may_change1(d.x, dv, f.x) ? 1u : 0u) | (may_change1(d.y, dv, f.y) ? 2u : 0u) |
+           (may_change1(d.z, dv, f.z) ? 4u : 0u) | (may_change1(d.w, dv, f.w) ? 8u : 0u);
+}
+
+// Row scan of affected source s (the all-pairs step of Alg 3, restricted to
+// row s), in two phases:
+//   1. the distance filter (may_change) over the candidate targets when that
+//      list is short, else over the whole row against the filter rows; the
+//      targets that pass go to F (up to fcap; the count in sh.nf goes on),
+//   2. after a barrier, all lanes share the flagged targets: the full
+//      Lemma 4 update of each (from the rows themselves), and the pairs that
+//      change go to the B list L with their new values (count in sh.nb).
+// Keeping the second phase out of the streaming loop keeps that loop small
+// and spreads the flagged pairs over the workgroup.  The caller zeroes sh.nf
+// and sh.nb before; if sh.nf > fcap after the call, the B list is incomplete.
+__device__ __forceinline__ void scan_row(const UpdateJob &J, const RowV &R, const SrcScal &sc, const bool same,
+                                         const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Sg,
+                                         const bool use_tlist, const int32_t t_count, int32_t *F, const int32_t fcap,
+                                         const BList &L, BlockShared &sh, bool &ovf_s, bool &ovf_d) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int32_t n = J.g.n;
+    const bool in_on = !same || sc.hv != 0;
+    auto flag = [&](int32_t t) {
+        const int32_t pos = atomicAdd(&sh.nf, 1);
+        if (pos < fcap) F[pos] = t;
+    };
+    if (use_tlist) {
+        const int32_t *const tlist = J.g.tlist, *const tl_rvD = J.g.tl_rvD, *const tl_rvvD = J.g.tl_rvvD;
+        for (int32_t i = tid; i < t_count; i += bs) {
+            const int32_t t = tlist[i];
+            if (may_change(Drow[t], sc.dv, tl_rvD[i], R.has_out ? tl_rvvD[i] : INF32, in_on)) flag(t);
+        }
+    } else if (sc.dv == INF32) {
+        // v unreachable from s: no pair of the row can change
+    } else if ((n & 3) == 0) {
+        // eight quads (32 pairs) per lane in flight, tested against one
+        // filter row
+        const int32_t nq = n >> 2;
+        const int4 *D4 = (const int4 *)Drow;
+        const int4 *F4 = (const int4 *)(in_on ? J.g.f_any : J.g.f_out);
+        for (int32_t q0 = tid; q0 < nq; q0 += 8 * bs) {
+            int4 dq[8], fq[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int32_t q = q0 + k * bs;
+                dq[k] = (q < nq) ? D4[q] : make_int4(0, 0, 0, 0);
+                fq[k] = (q < nq) ? F4[q] : make_int4(INF32, INF32, INF32, INF32);
+            }
+            uint32_t m = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) m |= quad_mask(dq[k], fq[k], sc.dv) << (4 * k);
+            while (m) {
+                const int b = __ffs(m) - 1;
+                m &= m - 1;
+                flag(((q0 + (b >> 2) * bs) << 2) + (b & 3));
+            }
+        }
+    } else {
+        const int32_t *f = in_on ? J.g.f_any : J.g.f_out;
+        for (int32_t t = tid; t < n; t += bs)
+            if (may_change1(Drow[t], sc.dv, f[t])) flag(t);
+    }
+    __syncthreads();
+    const int32_t nf = min(sh.nf, fcap);
+    for (int32_t i = tid; i < nf; i += bs) {
+        const int32_t t = F[i];
+        int32_t d;
+        uint64_t sg;
+        if (pair_update(R, sc, same, t, Drow[t], R.rvD[t], R.has_out ? R.rvvD[t] : INF32, Sg, d, sg, ovf_s, ovf_d)) {
+            const int32_t pos = atomicAdd(&sh.nb, 1);
+            if (pos < L.cap) {
+                L.t[pos] = t;
+                L.d[pos] = d;
+                L.s[pos] = sg;
+            }
+        }
     }
 }
 
-// Bit mask of the pairs of one quad that may change.
-__device__ __forceinline__ uint32_t quad_mask(const int4 d, const int4 r, const int4 v, const int32_t dv) {
-    return (may_change(d.x, dv, r.x, v.x) ? 1u : 0u) | (may_change(d.y, dv, r.y, v.y) ? 2u : 0u) |
-           (may_change(d.z, dv, r.z, v.z) ? 4u : 0u) | (may_change(d.w, dv, r.w, v.w) ? 8u : 0u);
+__device__ __forceinline__ RowV row_v_of(const UpdateJob &J) {
+    RowV R;
+    R.rvD = J.row_v_D;
+    R.rvS = J.row_v_S;
+    R.rvvD = J.g.rvv_D;
+    R.rvvS = J.g.rvv_S;
+    R.rvvH = J.g.rvv_H;
+    R.has_out = J.n_out > 0;
+    return R;
 }
 
-// Persistent per-source kernel: workgroups pull (job, affected source)
-// items from a device counter until every job's list is empty.  Each item:
-//   1. scan row s and list the changed targets B_s with their new
-//      (d, sigma) (the all-pairs step of Alg 3, restricted to row s),
-//   2. old partial dependency over B_s (E* by head, old row), sign -1,
-//   3. write the changed pairs (only those) to D and sigma,
-//   4. new partial dependency over B_s (merged E*, new row), sign +1.
-// The row is staged in LDS when n <= lds_cap (dynamic LDS of 4*lds_cap bytes).
-// Every workgroup's slot is laid out for the context-wide n_layout (the
-// largest graph), so the zero-kept arrays sit at the same place for every job.
-//
-// WIDE = false: the affected list, small workgroups, small sub-DAGs in LDS;
-// a source with more than BIG_B changed targets is deferred (before anything
-// is written) to the deferred list.  WIDE = true: the deferred list, one
-// 512-thread workgroup per source, sub-DAGs in global memory.
-template <bool WIDE>
-__device__ void source_items(const UpdateJob *__restrict__ jobs, const int32_t njobs, char *__restrict__ scratch,
-                             size_t slot_bytes, int32_t lds_cap, int32_t n_layout, char *dyn_lds) {
-    int32_t *const lds_row = (int32_t *)dyn_lds;
-    const ExpandShared es = expand_at(dyn_lds, lds_cap);
-    const SmallDag sd = small_dag_at(dyn_lds + align256((size_t)lds_cap * 4) + align256(20 * (size_t)blockDim.x));
+// Row kernel (persistent): workgroups pull affected sources from a device
+// counter and scan their rows (scan_row).  A source's changed targets are
+// collected in LDS; up to big_b of them are copied to the step's target pool
+// and the source is listed for the DAG kernel, more (or a full pool) defer
+// the source to the wide kernel, which scans the row again.  Nothing in D or
+// sigma is written here: the old partial dependency still needs the old row.
+__global__ void __launch_bounds__(256) k_rows(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
+                                              int32_t big_b, StepPool pool) {
+    __shared__ int32_t lt[LCAP], ld[LCAP], lf[LCAP];
+    __shared__ uint64_t ls[LCAP];
     __shared__ BlockShared sh;
+    __shared__ long long sh_off;
     const int tid = threadIdx.x, bs = blockDim.x;
-    char *slot_base = scratch + (size_t)blockIdx.x * slot_bytes;
+    const int njobs = *njobs_p;
+    const BList L{lt, ld, ls, min(big_b, LCAP)};
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        const int32_t n = J.g.n;
-        const bool lds = n <= lds_cap;
-        const USlot u = uslot_at(slot_base, n_layout);
-        GraphCtl *ctl = J.g.ctl;
         if (job_dead(J)) continue;
-        const int32_t count = WIDE ? *(volatile int32_t *)&ctl->big_count : *(volatile int32_t *)&ctl->a_count;
-        const int32_t *const items = WIDE ? J.g.biglist : J.g.alist;
-        int32_t *const next_item = WIDE ? &ctl->big_next : &ctl->work_next;
-        RowV R;
-        R.rvD = J.row_v_D;
-        R.rvS = J.row_v_S;
-        R.rvvD = J.g.rvv_D;
-        R.rvvS = J.g.rvv_S;
-        R.rvvH = J.g.rvv_H;
-        R.has_out = J.n_out > 0;
-        int32_t *const D = J.g.D;
-        uint64_t *const S = J.g.S;
-        const SrcScal *const scal = J.g.scal;
-        const int32_t *const xc_ptr = J.g.xc_ptr, *const xc_src = J.g.xc_src, *const xc_w = J.g.xc_w;
-        const int32_t *const yc_ptr = J.g.yc_ptr, *const yc_src = J.g.yc_src, *const yc_w = J.g.yc_w;
-        double *const bc_delta = J.g.bc_delta;
-        const bool vec = (n & 3) == 0;
-        // scan the candidate list when it is short enough that gathers beat
-        // streaming the whole row
+        GraphCtl *ctl = J.g.ctl;
+        const int32_t n = J.g.n;
+        const int32_t count = *(volatile int32_t *)&ctl->a_count;
+        const RowV R = row_v_of(J);
         const int32_t t_count = *(volatile int32_t *)&ctl->t_count;
         const bool use_tlist = (int64_t)t_count * 8 <= (int64_t)n;
-        const int32_t *const tlist = J.g.tlist, *const tl_rvD = J.g.tl_rvD, *const tl_rvvD = J.g.tl_rvvD;
         if (tid == 0) sh.counter = 0;
         bool ovf_s = false, ovf_d = false;
         for (;;) {
             __syncthreads();
             if (tid == 0) {
-                sh.item = atomicAdd(next_item, 1);
+                sh.item = atomicAdd(&ctl->work_next, 1);
                 sh.nb = 0;
+                sh.nf = 0;
             }
             __syncthreads();
             const int32_t item = sh.item;
             if (item >= count) break;
-            const int32_t s = items[item];
-            int32_t *Dg = D + (size_t)s * n;
-            uint64_t *Sg = S + (size_t)s * n;
-            const SrcScal sc = scal[s];
-            const bool same = (sc.flags & 1) != 0;
-            int32_t *Drow = Dg;
-            if (lds) {
-                for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
-                Drow = lds_row;
-                __syncthreads();
-            }
-            if (use_tlist) {
-                // gather only the candidate targets T of this update
-                for (int32_t i = tid; i < t_count; i += bs) {
-                    const int32_t t = tlist[i];
-                    const int32_t d0 = Drow[t], rvd = tl_rvD[i], dvv = R.has_out ? tl_rvvD[i] : INF32;
-                    if (may_change(d0, sc.dv, rvd, dvv)) note_change(R, sc, same, t, d0, rvd, dvv, Sg, u, sh, ovf_s, ovf_d);
-                }
-            } else if (vec) {
-                // four quads (16 pairs) per lane in flight; the unrolled part
-                // only applies the distance filter, flagged pairs are redone
-                // one at a time from memory (they are rare)
-                const int32_t nq = n >> 2;
-                const int4 *D4 = (const int4 *)Drow;
-                const int4 *R4 = (const int4 *)R.rvD;
-                const int4 *V4 = (const int4 *)R.rvvD;
-                const int4 inf4 = make_int4(INF32, INF32, INF32, INF32);
-                for (int32_t q0 = tid; q0 < nq; q0 += 4 * bs) {
-                    int4 dq[4], rq[4], vq[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int32_t q = q0 + k * bs;
-                        dq[k] = (q < nq) ? D4[q] : inf4;
-                        rq[k] = (q < nq) ? R4[q] : inf4;
-                        vq[k] = (R.has_out && q < nq) ? V4[q] : inf4;
-                    }
-                    uint32_t m = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) m |= quad_mask(dq[k], rq[k], vq[k], sc.dv) << (4 * k);
-                    while (m) {
-                        const int b = __ffs(m) - 1;
-                        m &= m - 1;
-                        const int32_t t = ((q0 + (b >> 2) * bs) << 2) + (b & 3);
-                        note_change(R, sc, same, t, Drow[t], R.rvD[t], R.has_out ? R.rvvD[t] : INF32, Sg, u, sh,
-                                    ovf_s, ovf_d);
-                    }
-                }
-            } else {
-                for (int32_t t = tid; t < n; t += bs) {
-                    const int32_t d0 = Drow[t], rvd = R.rvD[t], dvv = R.has_out ? R.rvvD[t] : INF32;
-                    if (may_change(d0, sc.dv, rvd, dvv)) note_change(R, sc, same, t, d0, rvd, dvv, Sg, u, sh, ovf_s, ovf_d);
-                }
-            }
+            const int32_t s = J.g.alist[item];
+            const SrcScal sc = J.g.scal[s];
+            const int32_t *Drow = J.g.D + (size_t)s * n;
+            const uint64_t *Sg = J.g.S + (size_t)s * n;
+            scan_row(J, R, sc, (sc.flags & 1) != 0, Drow, Sg, use_tlist, t_count, lf, LCAP, L, sh, ovf_s, ovf_d);
             __syncthreads();
             const int32_t nb = sh.nb;
-            if (nb == 0) continue;
-            if (!WIDE && nb > BIG_B) {
-                if (tid == 0) J.g.biglist[atomicAdd(&ctl->big_count, 1)] = s;
-                continue;
-            }
-            if (WIDE || !small_pass(s, Drow, Sg, xc_ptr, xc_src, xc_w, u.bl_t, nb, -1.0, bc_delta, sh, es, sd))
-                restricted_pass<false>(s, Drow, Sg, xc_ptr, xc_src, xc_w, u.bl_t, nb, u, -1.0, bc_delta, sh, es);
-            for (int32_t i = tid; i < nb; i += bs) {
-                const int32_t t = u.bl_t[i];
-                const int32_t d = u.bl_d[i];
-                Sg[t] = u.bl_s[i];
-                Dg[t] = d;
-                if (lds) lds_row[t] = d;
+            if (nb == 0 && sh.nf <= LCAP) continue;
+            if (tid == 0) {
+                long long off = -1;
+                if (nb <= L.cap && sh.nf <= LCAP) {
+                    const unsigned long long o = atomicAdd(pool.next, (unsigned long long)nb);
+                    if (o + (unsigned long long)nb <= (unsigned long long)pool.cap) off = (long long)o;
+                }
+                if (off >= 0) {
+                    DItem it;
+                    it.s = s;
+                    it.nb = nb;
+                    it.off = off;
+                    J.g.dlist[atomicAdd(&ctl->dag_count, 1)] = it;
+                    sh.counter += (unsigned long long)nb;
+                } else {
+                    J.g.biglist[atomicAdd(&ctl->big_count, 1)] = s;
+                }
+                sh_off = off;
             }
             __syncthreads();
-            if (WIDE || !small_pass(s, Drow, Sg, yc_ptr, yc_src, yc_w, u.bl_t, nb, 1.0, bc_delta, sh, es, sd))
-                restricted_pass<false>(s, Drow, Sg, yc_ptr, yc_src, yc_w, u.bl_t, nb, u, 1.0, bc_delta, sh, es);
-            if (tid == 0) sh.counter += (unsigned long long)nb;
+            const long long off = sh_off;
+            if (off >= 0) {
+                for (int32_t i = tid; i < nb; i += bs) {
+                    pool.t[off + i] = lt[i];
+                    pool.d[off + i] = ld[i];
+                    pool.s[off + i] = ls[i];
+                }
+            }
         }
         if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
         if (ovf_d) atomicOr(&ctl->status, ST_DIST_OVF);
@@ -1167,19 +1305,140 @@ __device__ void source_items(const UpdateJob *__restrict__ jobs, const int32_t n
     }
 }
 
-__global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
-                                                char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
-                                                int32_t n_layout) {
-    extern __shared__ __align__(16) char dyn_lds[];
-    source_items<false>(jobs, *njobs_p, scratch, slot_bytes, lds_cap, n_layout, dyn_lds);
+// One listed source with its changed targets B (Bt, Bd, Bs; nb of them):
+//   1. old partial dependency over B (E* by head, old row), sign -1,
+//   2. write the changed pairs (only those) to D and sigma,
+//   3. new partial dependency over B (merged E*, new row), sign +1.
+// Small sub-DAGs run in LDS (small_pass), larger ones in the workgroup's slot.
+__device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t s, const int32_t *__restrict__ Bt,
+                                              const int32_t *__restrict__ Bd, const uint64_t *__restrict__ Bs,
+                                              const int32_t nb, const bool lds, int32_t *lds_row, const USlot &u,
+                                              BlockShared &sh, const ExpandShared &es, const SmallDag &sd,
+                                              const bool try_small) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int32_t n = J.g.n;
+    int32_t *const Dg = J.g.D + (size_t)s * n;
+    uint64_t *const Sg = J.g.S + (size_t)s * n;
+    const int32_t *Drow = lds ? lds_row : Dg;
+    double *const bc_delta = J.g.bc_delta;
+    // a large B (here 1/16 of the row or more) makes the sub-DAG most of
+    // DAG(s): sweep all of E* instead of walking back from B
+    const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
+    if (!try_small || !small_pass(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd))
+        restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u, -1.0,
+                               bc_delta, sh, es);
+    for (int32_t i = tid; i < nb; i += bs) {
+        const int32_t t = Bt[i];
+        const int32_t d = Bd[i];
+        Sg[t] = Bs[i];
+        Dg[t] = d;
+        if (lds) lds_row[t] = d;
+    }
+    __syncthreads();
+    if (!try_small || !small_pass(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
+        restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb, full, u, 1.0,
+                               bc_delta, sh, es);
 }
 
-// The deferred sources, one 512-thread workgroup each (runs after k_source).
+// DAG kernel (persistent): workgroups pull the sources the row kernel listed
+// and run update_source on each.  The row is staged in LDS when n <= lds_cap
+// (dynamic LDS of 4*lds_cap bytes).  Every workgroup's slot is laid out for
+// the context-wide n_layout (the largest graph), so the zero-kept arrays sit
+// at the same place for every job.
+__global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
+                                                char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
+                                                int32_t n_layout, StepPool pool) {
+    extern __shared__ __align__(16) char dyn_lds[];
+    int32_t *const lds_row = (int32_t *)dyn_lds;
+    const ExpandShared es = expand_at(dyn_lds, lds_cap);
+    const SmallDag sd = small_dag_at(dyn_lds + align256((size_t)lds_cap * 4) + align256(XB * (size_t)blockDim.x));
+    __shared__ BlockShared sh;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int njobs = *njobs_p;
+    const USlot u = uslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
+    for (int j = 0; j < njobs; ++j) {
+        const UpdateJob &J = jobs[j];
+        if (job_dead(J)) continue;
+        GraphCtl *ctl = J.g.ctl;
+        const int32_t n = J.g.n;
+        const bool lds = n <= lds_cap;
+        const int32_t count = *(volatile int32_t *)&ctl->dag_count;
+        for (;;) {
+            __syncthreads();
+            if (tid == 0) sh.item = atomicAdd(&ctl->dag_next, 1);
+            __syncthreads();
+            const int32_t item = sh.item;
+            if (item >= count) break;
+            const DItem it = J.g.dlist[item];
+            if (lds) {
+                const int32_t *Dg = J.g.D + (size_t)it.s * n;
+                for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
+                __syncthreads();
+            }
+            update_source(J, it.s, pool.t + it.off, pool.d + it.off, pool.s + it.off, it.nb, lds, lds_row, u, sh, es,
+                          sd, true);
+        }
+    }
+}
+
+// Wide kernel (persistent, runs after the DAG kernel): the deferred sources,
+// one workgroup of up to 512 threads each.  Each scans its row again into the
+// slot's full-length B list, then runs update_source with the sub-DAGs in
+// global memory.
 __global__ void __launch_bounds__(512) k_source_wide(const UpdateJob *__restrict__ jobs,
                                                      const int32_t *__restrict__ njobs_p, char *__restrict__ scratch,
                                                      size_t slot_bytes, int32_t lds_cap, int32_t n_layout) {
     extern __shared__ __align__(16) char dyn_lds[];
-    source_items<true>(jobs, *njobs_p, scratch, slot_bytes, lds_cap, n_layout, dyn_lds);
+    int32_t *const lds_row = (int32_t *)dyn_lds;
+    const ExpandShared es = expand_at(dyn_lds, lds_cap);
+    const SmallDag sd = small_dag_at(dyn_lds + align256((size_t)lds_cap * 4) + align256(XB * (size_t)blockDim.x));
+    __shared__ BlockShared sh;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int njobs = *njobs_p;
+    const USlot u = uslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
+    for (int j = 0; j < njobs; ++j) {
+        const UpdateJob &J = jobs[j];
+        if (job_dead(J)) continue;
+        GraphCtl *ctl = J.g.ctl;
+        const int32_t n = J.g.n;
+        const bool lds = n <= lds_cap;
+        const int32_t count = *(volatile int32_t *)&ctl->big_count;
+        const RowV R = row_v_of(J);
+        const int32_t t_count = *(volatile int32_t *)&ctl->t_count;
+        const bool use_tlist = (int64_t)t_count * 8 <= (int64_t)n;
+        const BList L{u.bl_t, u.bl_d, u.bl_s, n};
+        if (tid == 0) sh.counter = 0;
+        bool ovf_s = false, ovf_d = false;
+        for (;;) {
+            __syncthreads();
+            if (tid == 0) {
+                sh.item = atomicAdd(&ctl->big_next, 1);
+                sh.nb = 0;
+                sh.nf = 0;
+            }
+            __syncthreads();
+            const int32_t item = sh.item;
+            if (item >= count) break;
+            const int32_t s = J.g.biglist[item];
+            const SrcScal sc = J.g.scal[s];
+            const int32_t *Dg = J.g.D + (size_t)s * n;
+            if (lds) {
+                for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
+                __syncthreads();
+            }
+            scan_row(J, R, sc, (sc.flags & 1) != 0, lds ? lds_row : Dg, J.g.S + (size_t)s * n, use_tlist, t_count,
+                     u.q1, n, L, sh, ovf_s, ovf_d);
+            __syncthreads();
+            const int32_t nb = sh.nb;
+            if (nb == 0) continue;
+            update_source(J, s, u.bl_t, u.bl_d, u.bl_s, nb, lds, lds_row, u, sh, es, sd, false);
+            if (tid == 0) sh.counter += (unsigned long long)nb;
+        }
+        if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
+        if (ovf_d) atomicOr(&ctl->status, ST_DIST_OVF);
+        __syncthreads();
+        if (tid == 0 && sh.counter) atomicAdd(&ctl->changed_pairs, sh.counter);
+    }
 }
 
 // ------------------------------------------------------------ commit -------
@@ -1212,6 +1471,7 @@ __global__ void __launch_bounds__(256) k_commit(const UpdateJob *__restrict__ jo
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             GraphCtl *c = J.g.ctl;
             c->affected_last = (unsigned long long)c->a_count;
+            c->big_last = c->big_count;
             if (!replace) {
                 c->updates += 1;
                 c->affected_total += (unsigned long long)c->a_count;
@@ -1221,13 +1481,16 @@ __global__ void __launch_bounds__(256) k_commit(const UpdateJob *__restrict__ jo
             c->work_next = 0;
             c->big_count = 0;
             c->big_next = 0;
+            c->dag_count = 0;
+            c->dag_next = 0;
         }
     }
 }
 
 // Clears the statistics that accumulate during an update (before k_scan).
-__global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
+__global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p, StepPool pool) {
     const int njobs = *njobs_p;
+    if (threadIdx.x == 0) *pool.next = 0;
     for (int j = threadIdx.x; j < njobs; j += blockDim.x) {
         GraphCtl *c = jobs[j].g.ctl;
         c->changed_pairs = 0;
@@ -1236,6 +1499,8 @@ __global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__res
         c->t_count = 0;
         c->big_count = 0;
         c->big_next = 0;
+        c->dag_count = 0;
+        c->dag_next = 0;
     }
 }
 
@@ -1377,7 +1642,8 @@ __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict_
     }
     if (lds) Drow = lds_row;
     __syncthreads();
-    restricted_pass<true>(s, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, u.bl_t, sh.nb, u, 1.0,
+    restricted_pass<true>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, u.bl_t,
+                          sh.nb, true, u, 1.0,
                           out_row, sh, es);
 }
 

@@ -38,14 +38,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_kernel_bytes(n, d_affected, d_changed, steps_per_graph, vertex_updates):
-    """Algorithmic bytes of the per-source kernel over a window, one graph:
-    every affected row of D is read (4 bytes per pair), each changed pair reads
-    sigma and writes d and sigma (20 bytes), and every step reads row v (12
-    bytes per target) plus, for vertex updates, row v'' (20 bytes per target)."""
-    return 4 * n * d_affected + 20 * d_changed + 12 * n * steps_per_graph + 20 * n * vertex_updates
-
-
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +49,7 @@ def main():
     ap.add_argument("--latency-requests", type=int, default=160)
     ap.add_argument("--cpu-sources", type=int, default=4096)
     ap.add_argument("--legs", default="batched,plain,recompute,latency,cpu")
+    ap.add_argument("--tune-sample", type=int, default=8, help="updates per graph in the autotuner's sample (0: no tuning)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,6 +93,23 @@ def main():
     load_s = (time.perf_counter() - t) / G
     log(f"loaded (static GPU Brandes) {load_s:.3f}s per graph; E* arcs {grs[0].stats()['estar_arcs']}")
 
+    # --------------------------------------------------------------- autotune
+    # The schedule autotuner replays a separately drawn sample of updates
+    # (same mix, different seed) on device clones of the graphs; the chosen
+    # schedule serves the batched and served legs, the plain leg keeps the
+    # library default.
+    default_sched = ctx.schedule()
+    tuned = default_sched
+    tune_s = 0.0
+    if args.tune_sample > 0:
+        samples = [W.mixed_stream(g, args.tune_sample, 1000, W.derive_seed(5, 4000 + gi), 0.35, 0.35, 16)
+                   for g, gi in zip(graphs, gidx)]
+        sample = [(grs[i], samples[i][k]) for k in range(args.tune_sample) for i in range(G)]
+        t = time.perf_counter()
+        tuned = ctx.autotune(sample)
+        tune_s = time.perf_counter() - t
+        log(f"autotune over {len(sample)} sample updates in {tune_s:.2f}s: {tuned} (default {default_sched})")
+
     # ---------------------------------------------------------------- warmup
     for _ in range(Wm):
         ctx.wait(ctx.submit([(grs[i], take(i)) for i in range(G)]))
@@ -134,6 +144,7 @@ def main():
     comparators = {}
     # ---------------------------------------------------------------- plain
     if "plain" in legs and P > 0:
+        ctx.set_schedule(**default_sched)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(P):
@@ -141,6 +152,7 @@ def main():
             grs[i].update(take(i))
             ctx.sync()
         plain_s = time.perf_counter() - t0
+        ctx.set_schedule(**tuned)
         comparators["plain_updates_per_s"] = P / plain_s
         comparators["batched_over_plain"] = value / (P / plain_s)
         log(f"plain: {P} updates one at a time -> {P / plain_s:.1f} updates/s")
@@ -165,23 +177,22 @@ def main():
         log(f"served {R} Poisson requests at {rate:.1f}/s: p50 {latency['p50']:.2f} ms, p99 {latency['p99']:.2f} ms")
     ctx.sync()
 
-    # ------------------------------------------------------- per-source kernel
-    # HIP events on the library's stream bracket every launch of the
-    # per-source kernel in this run (warmup, batched, plain and served
-    # updates); bytes are summed over the same updates.
+    # ------------------------------------------------------------ row kernel
+    # HIP events on the library's stream bracket every launch of the row
+    # kernel in this run (warmup, batched, plain and served updates: one launch
+    # per step); its algorithmic bytes (the device counts them per update:
+    # 4n per affected row scanned, or 4 per candidate target when the
+    # candidates are scanned instead, plus 8 per changed pair) are summed over
+    # the same updates.
     timing = ctx.timing()
-    alg_bytes = 0
-    for i in range(G):
-        st = grs[i].stats()
-        applied = streams[i][:cursor[i]]
-        nvert = sum(1 for up in applied if up.kind == "vertex")
-        alg_bytes += source_kernel_bytes(n, st["total_affected"], st["total_changed"], len(applied), nvert)
-    src_ms = timing["source_ms"]
+    alg_bytes = sum(gr.stats()["total_scan_bytes"] for gr in grs)
+    rows_ms = timing["rows_ms"]
     launches = max(timing["steps"], 1)
-    achieved = alg_bytes / (src_ms / 1e3) / 1e9 if src_ms > 0 else 0.0
-    log(f"per-source kernel over the run: {launches} launches, avg {src_ms / launches:.3f} ms "
-        f"(step avg {timing['step_ms'] / launches:.3f} ms), {alg_bytes / launches / 1e6:.1f} MB/launch "
-        f"-> {achieved:.1f} GB/s ({100 * achieved / HBM_PEAK_GBS:.2f}% of HBM peak)")
+    achieved = alg_bytes / (rows_ms / 1e3) / 1e9 if rows_ms > 0 else 0.0
+    log(f"row kernel over the run: {launches} launches, avg {rows_ms / launches:.3f} ms, "
+        f"{alg_bytes / launches / 1e6:.1f} MB/launch -> {achieved:.1f} GB/s "
+        f"({100 * achieved / HBM_PEAK_GBS:.2f}% of HBM peak); all per-source kernels avg "
+        f"{timing['source_ms'] / launches:.3f} ms, step avg {timing['step_ms'] / launches:.3f} ms")
 
     # ---------------------------------------------------------------- recompute
     if "recompute" in legs:
@@ -235,20 +246,23 @@ def main():
                         f"of 16 arcs; one update per graph per step",
             "n": n, "graphs": G, "updates_per_step": G, "parallelism": "1 GPU",
             "load_s_per_graph": load_s,
+            "schedule": tuned, "plain_schedule": default_sched, "autotune_s": tune_s,
         },
         "comparators": comparators,
         "latency_ms": latency,
         "roofline": {
-            "kernel": "k_source (per-source update: row scan, partial dependencies)",
+            "kernel": "k_rows (row update: distance filter and Lemma 4 pair update over the affected rows)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "avg_launch_ms": src_ms / launches,
+            "avg_launch_ms": rows_ms / launches,
             "launches": launches,
             "bytes_per_launch": alg_bytes / launches,
+            "per_source_kernels_avg_ms": timing["source_ms"] / launches,
+            "step_avg_ms": timing["step_ms"] / launches,
         },
         "cpu_baseline": cpu,
     }

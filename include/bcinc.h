@@ -67,7 +67,7 @@ typedef struct bc_ctx bc_ctx;
 typedef int32_t bc_graph_id;
 
 /* bc_config.flags */
-#define BC_FLAG_TIMING 1 /* time every update step and its per-source kernel with HIP events */
+#define BC_FLAG_TIMING 1 /* time every update step and its per-source kernels with HIP events */
 
 typedef struct {
     int32_t device;         /* HIP device ordinal */
@@ -76,8 +76,8 @@ typedef struct {
     void *scratch;          /* device buffer for per-workgroup work areas (caller owns it) */
     uint64_t scratch_bytes; /* its size; see bc_scratch_bytes */
     uint64_t memory_budget; /* admission limit for the sum of graph arenas, 0 = none */
-    int32_t slots;          /* persistent workgroups of the per-source kernel, 0 = 1024 */
-    int32_t block;          /* threads per workgroup of the per-source kernel (64, 128, 192 or 256), 0 = 256 */
+    int32_t slots;          /* workgroup slots of the DAG kernel and the static pass, 0 = 2048 */
+    int32_t block;          /* threads per workgroup of the DAG kernel (64, 128, 192 or 256), 0 = 256 */
 } bc_config;
 
 typedef struct {
@@ -199,17 +199,24 @@ typedef struct {
     int64_t total_affected;   /* sum of |A| over all updates since load */
     int64_t total_changed;    /* sum of changed pairs over all updates since load */
     int64_t deferred_sources; /* sources of the last update run by the wide kernel (bc_schedule) */
+    int64_t scan_bytes;       /* algorithmic bytes of the last update's row scans: 4n per affected
+                                 source (4|T| when the update's candidate targets T are scanned
+                                 instead, |T| <= n/8) plus 8 per changed pair (its old sigma) */
+    int64_t total_scan_bytes; /* the same summed over all updates since load */
 } bc_update_stats;
 bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id g, bc_update_stats *out);
 
 /* Kernel timing of a context created with BC_FLAG_TIMING: HIP events on the
  * context's stream bracket every update step (all its kernels) and, inside
- * it, the per-source kernel.  Totals cover the steps finished since the last
- * bc_reset_timing (bc_get_timing synchronises first). */
+ * it, the per-source kernels (the row kernel, which scans the rows of the
+ * affected sources, then the DAG and wide kernels, which run the partial
+ * dependencies) and the row kernel alone.  Totals cover the steps finished
+ * since the last bc_reset_timing (bc_get_timing synchronises first). */
 typedef struct {
     double step_ms;          /* summed duration of update steps */
-    double source_ms;        /* summed duration of the per-source kernel */
+    double source_ms;        /* summed duration of the per-source kernels (row, DAG and wide) */
     int64_t steps;           /* update steps timed (one launch of each kernel) */
+    double rows_ms;          /* summed duration of the row kernel alone */
 } bc_timing;
 bc_status bc_get_timing(bc_ctx *ctx, bc_timing *out);
 bc_status bc_reset_timing(bc_ctx *ctx);
@@ -225,7 +232,7 @@ bc_status bc_reset_timing(bc_ctx *ctx);
  *   block:      threads per workgroup of the first kernel: 64, 128, 192, 256
  *   slots:      its persistent workgroups (at most bc_config.slots)
  *   big_b:      deferral threshold, 1..1024
- *   wide_block: threads per workgroup of the wide kernel: 256 or 512
+ *   wide_block: threads per workgroup of the wide kernel: 256, 512 or 1024
  *   wide_stage: 1 = stage rows in LDS when they fit, 2 = never stage
  *   wide_slots: persistent workgroups of the wide kernel (at most slots)
  * bc_set_schedule synchronises the context's stream before it switches.
@@ -240,6 +247,23 @@ typedef struct {
 } bc_schedule;
 bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s);
 bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out);
+
+/* Autotuner of the launch schedule.  reqs[0..cnt) is a sample of requests
+ * in bc_submit form on resident graphs (typically updates like the expected
+ * stream, drawn for tuning).  For each candidate schedule (block 64, 128 or
+ * 256; wide_block 512 or 1024; big_b 512 or 1024; the other fields as set)
+ * the sample runs on fresh device clones of its graphs, twice (the first run
+ * also captures the step graphs), and the summed device time of the second
+ * run's steps ranks the candidate.  The fastest is set on the context and
+ * returned in *chosen (may be NULL).  The resident graphs are never modified.
+ *   workspace: caller-owned device memory, 256-byte aligned, of at least the
+ *     sum over the distinct sampled graphs of align256(bc_graph_bytes(...)),
+ *     holding the clones during the call.
+ * Synchronises.  Errors: BC_ERR_INVALID_ARG, BC_ERR_CAPACITY (workspace too
+ * small), any validation error of the sample (the schedule is then left as
+ * it was). */
+bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *workspace, uint64_t workspace_bytes,
+                      bc_schedule *chosen);
 
 const char *bc_status_string(bc_status s);
 const char *bc_last_error(bc_ctx *ctx);

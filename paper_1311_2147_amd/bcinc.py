@@ -64,11 +64,13 @@ class bc_update_stats(ctypes.Structure):
     _fields_ = [("affected_sources", ctypes.c_int64), ("changed_pairs", ctypes.c_int64),
                 ("estar_arcs", ctypes.c_int64), ("max_levels", ctypes.c_int64), ("updates_applied", ctypes.c_int64),
                 ("total_affected", ctypes.c_int64), ("total_changed", ctypes.c_int64),
-                ("deferred_sources", ctypes.c_int64)]
+                ("deferred_sources", ctypes.c_int64), ("scan_bytes", ctypes.c_int64),
+                ("total_scan_bytes", ctypes.c_int64)]
 
 
 class bc_timing(ctypes.Structure):
-    _fields_ = [("step_ms", ctypes.c_double), ("source_ms", ctypes.c_double), ("steps", ctypes.c_int64)]
+    _fields_ = [("step_ms", ctypes.c_double), ("source_ms", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("rows_ms", ctypes.c_double)]
 
 
 class bc_schedule(ctypes.Structure):
@@ -109,6 +111,7 @@ _SIGS = {
     "bc_reset_timing": (_i32, [_P]),
     "bc_set_schedule": (_i32, [_P, ctypes.POINTER(bc_schedule)]),
     "bc_get_schedule": (_i32, [_P, ctypes.POINTER(bc_schedule)]),
+    "bc_autotune": (_i32, [_P, _i32, ctypes.POINTER(bc_request), _P, _u64, ctypes.POINTER(bc_schedule)]),
     "bc_status_string": (ctypes.c_char_p, [_i32]),
     "bc_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -207,8 +210,10 @@ class Context:
         self.graphs.append(gr)
         return gr
 
-    def submit(self, requests) -> int:
-        """bc_submit of [(graph, update)] where update has kind/u/v/w/edges."""
+    @staticmethod
+    def _requests(requests):
+        """bc_request array of [(graph, update)]; the edge arrays it points to
+        are returned alongside and must outlive the call."""
         reqs = (bc_request * len(requests))()
         keep = []
         for i, (gr, up) in enumerate(requests):
@@ -220,6 +225,23 @@ class Context:
                 arr = (bc_edge * len(up.edges))(*[bc_edge(a, b, w) for a, b, w in up.edges])
                 keep.append(arr)
                 r.kind, r.v, r.k, r.edges = 1, up.v, len(up.edges), arr
+        return reqs, keep
+
+    def autotune(self, requests) -> dict:
+        """bc_autotune on a sample [(graph, update)]: sets and returns the
+        fastest launch schedule.  The sampled graphs are not modified."""
+        reqs, keep = self._requests(requests)
+        graphs = {gr.gid: gr for gr, _ in requests}
+        nbytes = sum((gr.nbytes + 255) // 256 * 256 for gr in graphs.values())
+        ws, addr = _device_buffer(nbytes, self.device)
+        out = bc_schedule()
+        self._check(_lib.bc_autotune(self.h, len(requests), reqs, addr, nbytes, ctypes.byref(out)), "bc_autotune")
+        del ws, keep
+        return {f: getattr(out, f) for f in SCHEDULE_FIELDS}
+
+    def submit(self, requests) -> int:
+        """bc_submit of [(graph, update)] where update has kind/u/v/w/edges."""
+        reqs, keep = self._requests(requests)
         ticket = ctypes.c_uint64()
         bad = ctypes.c_int32(-1)
         rc = _lib.bc_submit(self.h, len(requests), reqs, ctypes.byref(ticket), ctypes.byref(bad))
@@ -241,7 +263,7 @@ class Context:
     def timing(self) -> dict:
         t = bc_timing()
         self._check(_lib.bc_get_timing(self.h, ctypes.byref(t)), "bc_get_timing")
-        return {"step_ms": t.step_ms, "source_ms": t.source_ms, "steps": t.steps}
+        return {"step_ms": t.step_ms, "source_ms": t.source_ms, "steps": t.steps, "rows_ms": t.rows_ms}
 
     def reset_timing(self):
         self._check(_lib.bc_reset_timing(self.h), "bc_reset_timing")

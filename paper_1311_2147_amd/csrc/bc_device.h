@@ -59,6 +59,8 @@ struct GraphCtl {
     unsigned long long updates;        // updates applied since load
     unsigned long long affected_total; // sums over all updates since load
     unsigned long long changed_total;
+    unsigned long long scan_bytes_last;  // row-scan bytes of the last update (see k_commit)
+    unsigned long long scan_bytes_total;
 };
 
 // Per-source scalars of the update in flight (Alg 4 output).
@@ -165,16 +167,41 @@ __host__ __device__ inline StaticLayout static_layout(int32_t n) {
     return L;
 }
 
-// Per-workgroup scratch of the update pass.  flags / outdeg / acc are kept
-// all-zero between sources (each pass clears exactly the entries it used).
+// Per-workgroup scratch of the DAG kernel's global sub-DAG pass.  outdeg /
+// acc are kept all-zero between sources (each pass clears exactly the
+// entries it used).
 struct UpdateLayout {
-    size_t flags, outdeg, acc, sub, q1, q2, bl_t, bl_d, bl_s, total;
+    size_t outdeg, acc, sub, q1, q2, total;
 };
 
 __host__ __device__ inline UpdateLayout update_layout(int32_t n) {
     UpdateLayout L;
     size_t off = 0;
-    L.flags = off;  off += align256(sizeof(int32_t) * (size_t)n);
+    L.outdeg = off; off += align256(sizeof(int32_t) * (size_t)n);
+    L.acc = off;    off += align256(sizeof(double) * (size_t)n);
+    L.sub = off;    off += align256(sizeof(int32_t) * (size_t)n);
+    L.q1 = off;     off += align256(sizeof(int32_t) * (size_t)n);
+    L.q2 = off;     off += align256(sizeof(int32_t) * (size_t)n);
+    L.total = off;
+    return L;
+}
+
+// Most DAG arcs a full pass records, per vertex of the largest graph.
+constexpr int32_t KARC_PER_VERTEX = 4;
+
+// Per-workgroup scratch of the wide kernel: the arrays of UpdateLayout, the
+// full-length changed-target list (bl_*), and for full passes the recorded
+// DAG arcs (ka = tail, kb = head, kr = tails grouped by head) with per-head
+// counts (kcnt, kept all-zero) and range ends (kend).
+struct WideLayout {
+    size_t outdeg, acc, sub, q1, q2, bl_t, bl_d, bl_s, kcnt, kend, ka, kb, kr, total;
+    int64_t kcap;
+};
+
+__host__ __device__ inline WideLayout wide_layout(int32_t n) {
+    WideLayout L;
+    size_t off = 0;
+    L.kcap = (int64_t)KARC_PER_VERTEX * n;
     L.outdeg = off; off += align256(sizeof(int32_t) * (size_t)n);
     L.acc = off;    off += align256(sizeof(double) * (size_t)n);
     L.sub = off;    off += align256(sizeof(int32_t) * (size_t)n);
@@ -183,13 +210,21 @@ __host__ __device__ inline UpdateLayout update_layout(int32_t n) {
     L.bl_t = off;   off += align256(sizeof(int32_t) * (size_t)n);
     L.bl_d = off;   off += align256(sizeof(int32_t) * (size_t)n);
     L.bl_s = off;   off += align256(sizeof(uint64_t) * (size_t)n);
+    L.kcnt = off;   off += align256(sizeof(int32_t) * (size_t)n);
+    L.kend = off;   off += align256(sizeof(int32_t) * (size_t)n);
+    L.ka = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
+    L.kb = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
+    L.kr = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
     L.total = off;
     return L;
 }
 
+// Workgroup slots: the DAG kernel and the static pass share one region, the
+// wide kernel has its own.
 __host__ __device__ inline size_t slot_bytes_for(int32_t n) {
     const size_t a = static_layout(n).total, b = update_layout(n).total;
     return a > b ? a : b;
 }
+__host__ __device__ inline size_t wide_slot_bytes_for(int32_t n) { return wide_layout(n).total; }
 
 }  // namespace bcinc

@@ -28,7 +28,8 @@ namespace {
 constexpr int RING = 4;            // job staging slots in flight
 constexpr int JCAP = 256;          // jobs per staging slot
 constexpr size_t MISC_BYTES = 4096;
-constexpr int DEFAULT_SLOTS = 1024; // 4 persistent workgroups per CU of an MI355X
+constexpr int DEFAULT_SLOTS = 2048; // 8 persistent workgroups per CU of an MI355X
+constexpr int WIDE_SLOTS_MAX = 256; // wide-kernel slots: one per CU
 constexpr int DEFAULT_BLOCK = 256;  // 4 waves per affected source
 constexpr int DEFAULT_WIDE_BLOCK = 512;
 constexpr int64_t W_MAX = (int64_t)INF32 - 1;
@@ -151,9 +152,9 @@ struct bc_ctx {
     // timing (BC_FLAG_TIMING): per staging slot, events at step start, around
     // the per-source kernel, and at step end
     bool timing = false;
-    hipEvent_t tev[RING][4] = {};  // before parts 0, 1, 2 and after part 2
+    hipEvent_t tev[RING][5] = {};  // before parts 0..3 and after part 3
     bool tev_pending[RING] = {};
-    double step_ms = 0, source_ms = 0;
+    double step_ms = 0, source_ms = 0, rows_ms = 0;
     int64_t timed_steps = 0;
     std::map<std::tuple<int, int, size_t, int, int>, StepGraph> graph_cache;
     // tickets
@@ -203,23 +204,44 @@ StepPool step_pool(bc_ctx *ctx) {
     p.next = (unsigned long long *)(misc_dev(ctx) + 2048);
     return p;
 }
-char *slots_dev(bc_ctx *ctx) { return pool_dev(ctx) + pool_bytes(ctx->n_layout); }
+int wide_slots_for(int slots) { return std::min(slots, WIDE_SLOTS_MAX); }
 
-int usable_slots(bc_ctx *ctx, int32_t n_max, size_t *slot_bytes) {
-    const size_t sb = slot_bytes_for(n_max);
-    *slot_bytes = sb;
-    const uint64_t fixed = ring_bytes() + MISC_BYTES + pool_bytes(n_max);
-    if (ctx->scratch_bytes <= fixed) return 0;
-    const uint64_t avail = (ctx->scratch_bytes - fixed) / sb;
-    return (int)std::min<uint64_t>((uint64_t)ctx->slots, avail);
+// The part of the scratch buffer after the pool, laid out for graphs of up to
+// n vertices: `src` slots of the DAG kernel and the static pass, then `wide`
+// slots of the wide kernel.  Fewer slots than configured when the buffer was
+// sized for a smaller n; zero counts when not even one of each fits.
+struct ScratchPlan {
+    int src = 0, wide = 0;
+    size_t src_bytes = 0, wide_bytes = 0;
+    char *src_base = nullptr, *wide_base = nullptr;
+};
+
+ScratchPlan plan_scratch(bc_ctx *ctx, int32_t n) {
+    ScratchPlan p;
+    p.src_bytes = slot_bytes_for(n);
+    p.wide_bytes = wide_slot_bytes_for(n);
+    const uint64_t fixed = ring_bytes() + MISC_BYTES + pool_bytes(n);
+    if (ctx->scratch_bytes <= fixed) return p;
+    const uint64_t avail = ctx->scratch_bytes - fixed;
+    uint64_t w = (uint64_t)wide_slots_for(ctx->slots);
+    w = std::min<uint64_t>(w, avail / (p.wide_bytes + p.src_bytes));
+    if (w < 1) return p;
+    const uint64_t s = std::min<uint64_t>((uint64_t)ctx->slots, (avail - w * p.wide_bytes) / p.src_bytes);
+    if (s < 1) return p;
+    p.src = (int)s;
+    p.wide = (int)w;
+    p.src_base = pool_dev(ctx) + pool_bytes(n);
+    p.wide_base = p.src_base + s * p.src_bytes;
+    return p;
 }
 
 int lds_cap_for(int32_t n_max) { return std::min<int32_t>(n_max, LDS_ROW_MAX); }
 
-// Dynamic LDS of k_source / k_delta_row: staged row, 20 bytes per thread of
-// expansion arrays, and the small sub-DAG table.
-size_t source_lds_bytes(int lds_cap, int block) {
-    return align256((size_t)lds_cap * 4) + align256(XB * (size_t)block) + small_dag_bytes();
+// Dynamic LDS of the per-source kernels: staged row, XB bytes per thread of
+// expansion arrays, and the small sub-DAG table (which the wide kernel does
+// not use: its workgroups stop before it).
+size_t source_lds_bytes(int lds_cap, int block, bool small = true) {
+    return align256((size_t)lds_cap * 4) + align256(XB * (size_t)block) + (small ? small_dag_bytes() : 0);
 }
 
 // Arena layout of one graph (every piece 256-byte aligned).
@@ -309,11 +331,13 @@ GraphRec *get_graph(bc_ctx *ctx, bc_graph_id g) {
 // Adds the timed durations of slot r's last step (its events have completed).
 bc_status harvest_timing(bc_ctx *ctx, int r) {
     if (!ctx->tev_pending[r]) return BC_OK;
-    float a = 0, b = 0;
-    HIPCHK(hipEventElapsedTime(&a, ctx->tev[r][0], ctx->tev[r][3]));  // whole step
-    HIPCHK(hipEventElapsedTime(&b, ctx->tev[r][1], ctx->tev[r][2]));  // per-source kernel
+    float a = 0, b = 0, c = 0;
+    HIPCHK(hipEventElapsedTime(&a, ctx->tev[r][0], ctx->tev[r][4]));  // whole step
+    HIPCHK(hipEventElapsedTime(&b, ctx->tev[r][1], ctx->tev[r][3]));  // per-source kernels
+    HIPCHK(hipEventElapsedTime(&c, ctx->tev[r][1], ctx->tev[r][2]));  // row kernel
     ctx->step_ms += a;
     ctx->source_ms += b;
+    ctx->rows_ms += c;
     ctx->timed_steps += 1;
     ctx->tev_pending[r] = false;
     return BC_OK;
@@ -322,7 +346,7 @@ bc_status harvest_timing(bc_ctx *ctx, int r) {
 bc_status harvest_all(bc_ctx *ctx) {
     for (int r = 0; r < RING; ++r)
         if (ctx->tev_pending[r]) {
-            HIPCHK(hipEventSynchronize(ctx->tev[r][3]));
+            HIPCHK(hipEventSynchronize(ctx->tev[r][4]));
             bc_status st = harvest_timing(ctx, r);
             if (st) return st;
         }
@@ -367,13 +391,15 @@ struct LaunchShape {
     int lds_cap;      // static pass: rows up to this size are staged in LDS
     int src_lds_cap;  // per-source kernel: rows up to this size are staged in LDS
     int wide_slots;   // workgroups of the wide per-source kernel
+    size_t wide_bytes;
+    char *src_base, *wide_base;
     int wide_lds_cap; // and its LDS staging limit
     int32_t n_layout;
 };
 
-// The update kernel sequence for the jobs staged in ring slot r, in three
-// parts: 0 = begin, scan, row v'', E* merge; 1 = the per-source kernel;
-// 2 = E* filter and commit.
+// The update kernel sequence for the jobs staged in ring slot r, in four
+// parts: 0 = begin, scan, row v'', E* merge; 1 = the row kernel; 2 = the DAG
+// and wide kernels; 3 = E* filter and commit.
 bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part) {
     const UpdateJob *jobs = ring_jobs_dev(ctx, r);
     const int32_t *nj = ring_njobs_dev(ctx, r);
@@ -390,11 +416,12 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
         hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
     } else if (part == 1) {
         hipLaunchKernelGGL(k_rows, dim3(ctx->rows_grid), dim3(256), 0, st, jobs, nj, ctx->big_b, pool);
+    } else if (part == 2) {
         hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), source_lds_bytes(L.src_lds_cap, ctx->block), st,
-                           jobs, nj, slots_dev(ctx), L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
+                           jobs, nj, L.src_base, L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
         hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(ctx->wide_block),
-                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block), st, jobs, nj, slots_dev(ctx),
-                           L.slot_bytes, L.wide_lds_cap, L.n_layout);
+                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block, false), st, jobs, nj, L.wide_base,
+                           L.wide_bytes, L.wide_lds_cap, L.n_layout);
     } else {
         hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
@@ -428,18 +455,24 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     for (auto &j : jobs) L->n_max = std::max(L->n_max, j.g.n);
     L->njobs = (int)jobs.size();
     L->n_layout = ctx->n_layout;
-    L->slots = usable_slots(ctx, ctx->n_layout, &L->slot_bytes);
-    if (L->slots < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for one work slot at this n");
+    const ScratchPlan sp = plan_scratch(ctx, ctx->n_layout);
+    if (sp.src < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small for one work slot at this n");
+    L->slots = sp.src;
+    L->slot_bytes = sp.src_bytes;
+    L->src_base = sp.src_base;
+    L->wide_bytes = sp.wide_bytes;
+    L->wide_base = sp.wide_base;
     if (ctx->run_slots > 0) L->slots = std::min(L->slots, ctx->run_slots);
     L->lds_cap = lds_cap_for(L->n_max);
     // the row is staged only when it fits; otherwise no LDS is reserved for it
     L->src_lds_cap = L->n_max <= ctx->src_lds_max ? L->n_max : 0;
     // wide kernel: the row is staged when it fits beside the expansion arrays
     // and the small-DAG table; one workgroup per CU then, else two
-    const bool stage = ctx->wide_stage == 1 && source_lds_bytes(L->n_max, ctx->wide_block) <= ctx->wide_lds_limit;
+    const size_t wide_lds = source_lds_bytes(L->n_max, ctx->wide_block, false);
+    const bool stage = ctx->wide_stage == 1 && wide_lds <= ctx->wide_lds_limit;
     L->wide_lds_cap = stage ? L->n_max : 0;
-    const int per_cu = stage && source_lds_bytes(L->n_max, ctx->wide_block) * 2 > ctx->wide_lds_limit ? 1 : 2;
-    L->wide_slots = std::min(L->slots, ctx->wide_slots > 0 ? ctx->wide_slots : per_cu * ctx->cu_count);
+    const int per_cu = (stage && wide_lds * 2 > ctx->wide_lds_limit) || ctx->wide_block > 512 ? 1 : 2;
+    L->wide_slots = std::min(sp.wide, ctx->wide_slots > 0 ? ctx->wide_slots : per_cu * ctx->cu_count);
     return BC_OK;
 }
 
@@ -452,7 +485,7 @@ bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_gra
     if ((st = ring_stage(ctx, r, jobs))) return st;
     const bool timed = ctx->timing;
     // timing events sit on the stream between the parts (never inside a graph)
-    for (int part = 0; part < 3; ++part) {
+    for (int part = 0; part < 4; ++part) {
         if (timed) HIPCHK(hipEventRecord(ctx->tev[r][part], ctx->stream));
         if (!use_graph) {
             if ((st = launch_update_part(ctx, r, L, part))) return st;
@@ -462,7 +495,7 @@ bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_gra
             HIPCHK(hipGraphLaunch(exec, ctx->stream));
         }
     }
-    if (timed) HIPCHK(hipEventRecord(ctx->tev[r][3], ctx->stream));
+    if (timed) HIPCHK(hipEventRecord(ctx->tev[r][4], ctx->stream));
     if (timed) ctx->tev_pending[r] = true;
     return ring_release(ctx, r);
 }
@@ -645,11 +678,13 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
     const int32_t *nj = ring_njobs_dev(ctx, r);
     const int slots = std::min<int>(L.slots, n);
     // slots may still hold another layout's lists (n_layout can just have grown)
-    HIPCHK(hipMemsetAsync(slots_dev(ctx), 0, (size_t)L.slots * L.slot_bytes, ctx->stream));
+    const ScratchPlan sp = plan_scratch(ctx, ctx->n_layout);
+    const size_t slot_region = (size_t)sp.src * sp.src_bytes + (size_t)sp.wide * sp.wide_bytes;
+    HIPCHK(hipMemsetAsync(sp.src_base, 0, slot_region, ctx->stream));
     const int g_wave = (int)std::min<int64_t>(((int64_t)n * 64 + 255) / 256, 4096);
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
-    hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, slots_dev(ctx), L.slot_bytes,
+    hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, L.src_base, L.slot_bytes,
                        L.lds_cap, L.n_layout);
     hipLaunchKernelGGL(k_es_count<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
     hipLaunchKernelGGL(k_es_scan<ES_BUILD>, dim3(1), dim3(1024), 0, s, dj, nj);
@@ -658,12 +693,12 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
     hipLaunchKernelGGL(k_es_scan<ES_BUILD_C>, dim3(1), dim3(1024), 0, s, dj, nj);
     hipLaunchKernelGGL(k_es_scatter<ES_BUILD_C>, dim3(g_wave), dim3(256), 0, s, dj, nj);
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
-    hipLaunchKernelGGL(k_static, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, slots_dev(ctx), L.slot_bytes,
+    hipLaunchKernelGGL(k_static, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, L.src_base, L.slot_bytes,
                        L.lds_cap, L.n_layout);
     hipLaunchKernelGGL(k_commit, dim3((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048), dim3(256), 0, s, dj, nj, 1);
     HIPCHK(hipGetLastError());
     // the update kernels expect their per-workgroup flags and sums at zero
-    HIPCHK(hipMemsetAsync(slots_dev(ctx), 0, (size_t)L.slots * L.slot_bytes, s));
+    HIPCHK(hipMemsetAsync(sp.src_base, 0, slot_region, s));
     st = ring_release(ctx, r);
     if (st) return st;
     // the host vectors above are read by the copies: finish before they go
@@ -710,7 +745,8 @@ uint64_t bc_graph_bytes(int32_t n, int64_t arc_capacity, int64_t estar_capacity)
 uint64_t bc_scratch_bytes(int32_t n_max, int32_t slots) {
     if (n_max <= 0) return 0;
     if (slots <= 0) slots = DEFAULT_SLOTS;
-    return ring_bytes() + MISC_BYTES + pool_bytes(n_max) + (uint64_t)slots * slot_bytes_for(n_max);
+    return ring_bytes() + MISC_BYTES + pool_bytes(n_max) + (uint64_t)slots * slot_bytes_for(n_max) +
+           (uint64_t)wide_slots_for(slots) * wide_slot_bytes_for(n_max);
 }
 
 const char *bc_status_string(bc_status s) {
@@ -791,7 +827,7 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
         if (e != hipSuccess) return bail(e, "hipHostMalloc");
         e = hipEventCreateWithFlags(&ctx->ring_ev[r], hipEventDisableTiming);
         if (e != hipSuccess) return bail(e, "hipEventCreate");
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 5; ++q) {
             e = hipEventCreate(&ctx->tev[r][q]);
             if (e != hipSuccess) return bail(e, "hipEventCreate");
         }
@@ -826,7 +862,7 @@ bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s) {
     const int wide_stage = s->wide_stage ? s->wide_stage : ctx->wide_stage;
     const int wide_slots = s->wide_slots ? s->wide_slots : ctx->wide_slots;
     if (block < 64 || block > 256 || block % 64 != 0 || slots < 0 || slots > ctx->slots || big_b < 1 || big_b > LCAP ||
-        (wide_block != 256 && wide_block != 512) || (wide_stage != 1 && wide_stage != 2) || wide_slots < 0 ||
+        (wide_block != 256 && wide_block != 512 && wide_block != 1024) || (wide_stage != 1 && wide_stage != 2) || wide_slots < 0 ||
         wide_slots > ctx->slots)
         return fail(ctx, BC_ERR_INVALID_ARG, "schedule value out of range");
     HIPCHK(hipSetDevice(ctx->device));
@@ -843,6 +879,108 @@ bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s) {
     ctx->wide_block = wide_block;
     ctx->wide_stage = wide_stage;
     ctx->wide_slots = wide_slots;
+    return BC_OK;
+}
+
+// Schedule autotuner.  Every candidate runs the caller's sample twice on
+// fresh device clones of the sampled graphs (the first run also captures the
+// candidate's step graphs); the second run's summed step time (HIP events
+// around each step's kernels) ranks it.  Clones are dropped afterwards, so
+// the resident graphs never see the sample.
+bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *workspace, uint64_t workspace_bytes,
+                      bc_schedule *chosen) {
+    if (!ctx || cnt <= 0 || !reqs || !workspace) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_autotune");
+    if (((uintptr_t)workspace & 255) != 0) return fail(ctx, BC_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    std::vector<int32_t> gids;
+    uint64_t need = 0;
+    for (int32_t i = 0; i < cnt; ++i) {
+        GraphRec *g = get_graph(ctx, reqs[i].graph);
+        if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "sample names no resident graph");
+        if (std::find(gids.begin(), gids.end(), reqs[i].graph) == gids.end()) {
+            gids.push_back(reqs[i].graph);
+            need += align256(bc_graph_bytes(g->n, g->arc_cap, g->es_cap));
+        }
+    }
+    if (workspace_bytes < need) return fail(ctx, BC_ERR_CAPACITY, "autotune workspace below the sampled graphs' bytes");
+    bc_schedule start;
+    bc_get_schedule(ctx, &start);
+    const bool timing0 = ctx->timing;
+    bc_status st = BC_OK;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if ((st = harvest_all(ctx))) return st;
+    const double step0 = ctx->step_ms, src0 = ctx->source_ms, rows0 = ctx->rows_ms;
+    const int64_t steps0 = ctx->timed_steps;
+    const uint64_t budget0 = ctx->budget;
+    ctx->budget = 0;  // the clones live in the caller's workspace, outside the admission budget
+    std::vector<bc_request> mapped(reqs, reqs + cnt);
+    // one sample run on fresh clones; returns the summed step time
+    auto run = [&](double *ms) -> bc_status {
+        const size_t base_id = ctx->graphs.size();
+        char *p = (char *)workspace;
+        bc_status s2 = BC_OK;
+        for (size_t k = 0; k < gids.size() && !s2; ++k) {
+            GraphRec *g = ctx->graphs[gids[k]];
+            const uint64_t b = align256(bc_graph_bytes(g->n, g->arc_cap, g->es_cap));
+            bc_graph_id c;
+            s2 = bc_clone_graph(ctx, gids[k], p, b, &c);
+            p += b;
+        }
+        if (!s2) {
+            for (auto &r : mapped)
+                r.graph = (bc_graph_id)(base_id + (std::find(gids.begin(), gids.end(), r.graph) - gids.begin()));
+            ctx->step_ms = 0;
+            uint64_t ticket = 0;
+            s2 = bc_submit(ctx, cnt, mapped.data(), &ticket, nullptr);
+            if (!s2) s2 = bc_wait(ctx, ticket);
+            if (!s2 && hipStreamSynchronize(ctx->stream) != hipSuccess) s2 = fail(ctx, BC_ERR_HIP, "autotune run");
+            if (!s2) s2 = harvest_all(ctx);
+            *ms = ctx->step_ms;
+            for (size_t k = 0; k < gids.size() && !s2; ++k) {
+                int32_t status = 0;
+                s2 = read_status(ctx, ctx->graphs[base_id + k], &status);
+                if (!s2 && status) s2 = fail(ctx, sticky_to_status(status), "sample failed on a clone");
+            }
+        }
+        (void)hipStreamSynchronize(ctx->stream);
+        while (ctx->graphs.size() > base_id) {
+            GraphRec *g = ctx->graphs.back();
+            if (g->live) ctx->in_use -= g->arena_bytes;
+            delete g;
+            ctx->graphs.pop_back();
+        }
+        for (size_t i = 0; i < mapped.size(); ++i) mapped[i].graph = reqs[i].graph;
+        return s2;
+    };
+    bc_schedule best = start;
+    double best_ms = 1e300;
+    ctx->timing = true;
+    for (int block : {256, 128, 64})
+        for (int wide_block : {512, 1024})
+            for (int big_b : {512, 1024}) {
+                bc_schedule c = start;
+                c.block = block;
+                c.wide_block = wide_block;
+                c.big_b = big_b;
+                c.slots = start.slots ? start.slots : 0;
+                if ((st = bc_set_schedule(ctx, &c))) break;
+                double ms = 0;
+                if ((st = run(&ms))) break;
+                if ((st = run(&ms))) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    bc_get_schedule(ctx, &best);
+                }
+            }
+    ctx->timing = timing0;
+    ctx->step_ms = step0;
+    ctx->source_ms = src0;
+    ctx->rows_ms = rows0;
+    ctx->timed_steps = steps0;
+    ctx->budget = budget0;
+    bc_status st2 = bc_set_schedule(ctx, st ? &start : &best);
+    if (st) return st;
+    if (st2) return st2;
+    if (chosen) *chosen = best;
     return BC_OK;
 }
 
@@ -870,7 +1008,7 @@ bc_status bc_destroy(bc_ctx *ctx) {
         if (ctx->h_jobs[r]) (void)hipHostFree(ctx->h_jobs[r]);
         if (ctx->h_njobs[r]) (void)hipHostFree(ctx->h_njobs[r]);
         if (ctx->ring_ev[r]) (void)hipEventDestroy(ctx->ring_ev[r]);
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 5; ++q)
             if (ctx->tev[r][q]) (void)hipEventDestroy(ctx->tev[r][q]);
     }
     for (auto *g : ctx->graphs) delete g;
@@ -894,8 +1032,7 @@ bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
     if (arena_bytes < need) return fail(ctx, BC_ERR_CAPACITY, "arena smaller than bc_graph_bytes");
     if (ctx->budget && ctx->in_use + arena_bytes > ctx->budget)
         return fail(ctx, BC_ERR_ADMISSION, "graph state would exceed the memory budget");
-    size_t sb;
-    if (usable_slots(ctx, std::max(n, ctx->n_layout), &sb) < 1)
+    if (plan_scratch(ctx, std::max(n, ctx->n_layout)).src < 1)
         return fail(ctx, BC_ERR_CAPACITY, "scratch too small for this n");
     // host mirror (validates ids, loops, weights, duplicates)
     GraphRec *g = new GraphRec();
@@ -1202,18 +1339,19 @@ bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id gid, int32_t s, int32_t *a, int32_
 bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g || s < 0 || s >= g->n || !out) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
-    size_t sb;
-    if (usable_slots(ctx, ctx->n_layout, &sb) < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small");
+    const ScratchPlan sp = plan_scratch(ctx, ctx->n_layout);
+    if (sp.src < 1) return fail(ctx, BC_ERR_CAPACITY, "scratch too small");
     std::vector<UpdateJob> jobs(1, job_template(g));
     int r;
     bc_status st;
     if ((st = ring_acquire(ctx, &r))) return st;
     if ((st = ring_stage(ctx, r, jobs))) return st;
     const int lds = std::min<int32_t>(g->n, 28672);  // row, expansion arrays and small-DAG table fit in 160 KiB
-    // the row lands in slot 0's B-list value area, unused by this pass
-    double *row = (double *)(slots_dev(ctx) + update_layout(ctx->n_layout).bl_s);
+    // the pass runs in wide slot 0; the row lands in its B-list value area,
+    // which the pass does not use
+    double *row = (double *)(sp.wide_base + wide_layout(ctx->n_layout).bl_s);
     hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), source_lds_bytes(lds, 1024), ctx->stream,
-                       ring_jobs_dev(ctx, r), s, slots_dev(ctx), lds, ctx->n_layout, row);
+                       ring_jobs_dev(ctx, r), s, sp.wide_base, lds, ctx->n_layout, row);
     HIPCHK(hipGetLastError());
     if ((st = ring_release(ctx, r))) return st;
     HIPCHK(hipMemcpyAsync(out, row, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
@@ -1253,6 +1391,8 @@ bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id gid, bc_update_stats *out) {
     out->total_affected = (int64_t)c.affected_total;
     out->total_changed = (int64_t)c.changed_total;
     out->deferred_sources = c.big_last;
+    out->scan_bytes = (int64_t)c.scan_bytes_last;
+    out->total_scan_bytes = (int64_t)c.scan_bytes_total;
     return BC_OK;
 }
 
@@ -1263,6 +1403,7 @@ bc_status bc_get_timing(bc_ctx *ctx, bc_timing *out) {
     if (st) return st;
     out->step_ms = ctx->step_ms;
     out->source_ms = ctx->source_ms;
+    out->rows_ms = ctx->rows_ms;
     out->steps = ctx->timed_steps;
     return BC_OK;
 }
@@ -1272,7 +1413,7 @@ bc_status bc_reset_timing(bc_ctx *ctx) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     bc_status st = harvest_all(ctx);
     if (st) return st;
-    ctx->step_ms = ctx->source_ms = 0;
+    ctx->step_ms = ctx->source_ms = ctx->rows_ms = 0;
     ctx->timed_steps = 0;
     return BC_OK;
 }

@@ -455,6 +455,7 @@ struct BlockShared {
     int32_t item;
     int32_t nb, nf;
     int32_t ovf, progress;
+    int32_t nk, kpos;
     int32_t scan[40];
     unsigned long long counter;
 };
@@ -475,16 +476,34 @@ __device__ __forceinline__ SSlot sslot_at(char *base, int32_t n) {
     return s;
 }
 
+// A workgroup's slot.  Slots of the DAG kernel have no B list and no arc
+// record (null pointers, kcap 0).
 struct USlot {
-    int32_t *flags, *outdeg, *sub, *q1, *q2, *bl_t, *bl_d;
+    int32_t *outdeg, *sub, *q1, *q2, *bl_t, *bl_d;
     double *acc;
     uint64_t *bl_s;
+    int32_t *kcnt, *kend, *ka, *kb, *kr;
+    int64_t kcap;
 };
 
 __device__ __forceinline__ USlot uslot_at(char *base, int32_t n) {
     const UpdateLayout L = update_layout(n);
     USlot u;
-    u.flags = (int32_t *)(base + L.flags);
+    u.outdeg = (int32_t *)(base + L.outdeg);
+    u.acc = (double *)(base + L.acc);
+    u.sub = (int32_t *)(base + L.sub);
+    u.q1 = (int32_t *)(base + L.q1);
+    u.q2 = (int32_t *)(base + L.q2);
+    u.bl_t = u.bl_d = nullptr;
+    u.bl_s = nullptr;
+    u.kcnt = u.kend = u.ka = u.kb = u.kr = nullptr;
+    u.kcap = 0;
+    return u;
+}
+
+__device__ __forceinline__ USlot wslot_at(char *base, int32_t n) {
+    const WideLayout L = wide_layout(n);
+    USlot u;
     u.outdeg = (int32_t *)(base + L.outdeg);
     u.acc = (double *)(base + L.acc);
     u.sub = (int32_t *)(base + L.sub);
@@ -493,6 +512,12 @@ __device__ __forceinline__ USlot uslot_at(char *base, int32_t n) {
     u.bl_t = (int32_t *)(base + L.bl_t);
     u.bl_d = (int32_t *)(base + L.bl_d);
     u.bl_s = (uint64_t *)(base + L.bl_s);
+    u.kcnt = (int32_t *)(base + L.kcnt);
+    u.kend = (int32_t *)(base + L.kend);
+    u.ka = (int32_t *)(base + L.ka);
+    u.kb = (int32_t *)(base + L.kb);
+    u.kr = (int32_t *)(base + L.kr);
+    u.kcap = L.kcap;
     return u;
 }
 
@@ -658,10 +683,13 @@ __device__ __forceinline__ void chunk_arcs(const ExpandShared &es, const int32_t
 //      sub-DAG vertex's successors inside the sub-DAG, or (full) one sweep
 //      over all of E* counting every reachable vertex's DAG successors, for
 //      large B where the sub-DAG is most of DAG(s) (vertices outside it get
-//      delta_B = 0 and change nothing),
+//      delta_B = 0 and change nothing); a full pass in a slot with an arc
+//      record also keeps the DAG(s) arcs it finds, grouped by head,
 //   2. Kahn from the sinks (a reverse topological order, which serves the
 //      accumulation, Section 2.1): each vertex pushes its term to its
-//      predecessors once all its successors have pushed to it.
+//      predecessors once all its successors have pushed to it, over the
+//      recorded arcs when there are any, else over its E* in-arcs with the
+//      Eq.1 test.
 // Targets whose d(s,t) and sigma_st do not change keep the same set of
 // shortest paths, so delta_st is unchanged for them and the BC difference of
 // source s is delta'_B - delta_B with B the changed targets (Alg 3 re-runs
@@ -693,9 +721,17 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
     }
     __syncthreads();
     int32_t nsub;
+    bool rec = false;  // Kahn walks recorded arcs
     if (full) {
-        // 1. every DAG(s) arc: one more successor of its tail
+        // 1. every DAG(s) arc: one more successor of its tail, and (with an
+        //    arc record) the arc itself with one more arc into its head
+        if (tid == 0) {
+            sh.nk = 0;
+            sh.kpos = 0;
+        }
+        __syncthreads();
         const int32_t m = cptr[n];
+        const int32_t kcap = (int32_t)u.kcap;
         for (int32_t e0 = tid; e0 < m; e0 += XU * bs) {
             int32_t av[XU], bv[XU], wv[XU];
 #pragma unroll
@@ -714,8 +750,34 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
             for (int k = 0; k < XU; ++k) {
                 if (e0 + k * bs >= m) continue;
                 const int32_t da = Drow[av[k]];
-                if (da != INF32 && (int64_t)da + wv[k] == (int64_t)Drow[bv[k]]) atomicAdd(&u.outdeg[av[k]], 1);
+                if (da != INF32 && (int64_t)da + wv[k] == (int64_t)Drow[bv[k]]) {
+                    atomicAdd(&u.outdeg[av[k]], 1);
+                    if (kcap > 0) {
+                        const int32_t p = atomicAdd(&sh.nk, 1);
+                        if (p < kcap) {
+                            u.ka[p] = av[k];
+                            u.kb[p] = bv[k];
+                            atomicAdd(&u.kcnt[bv[k]], 1);
+                        }
+                    }
+                }
             }
+        }
+        __syncthreads();
+        const int32_t nk = sh.nk;
+        rec = kcap > 0 && nk <= kcap;
+        if (rec) {
+            // group the arcs by head: each head with arcs gets a range
+            // [kend - kcnt, kend); the scatter advances kend from its start
+            for (int32_t x = tid; x < n; x += bs) {
+                const int32_t c = u.kcnt[x];
+                if (c) u.kend[x] = atomicAdd(&sh.kpos, c);
+            }
+            __syncthreads();
+            for (int32_t p = tid; p < nk; p += bs) u.kr[atomicAdd(&u.kend[u.kb[p]], 1)] = u.ka[p];
+        } else if (kcap > 0) {
+            // too many arcs to record: Kahn tests E*; undo the counts
+            for (int32_t p = tid; p < kcap; p += bs) u.kcnt[u.kb[p]] = 0;
         }
         __syncthreads();
         for (int32_t x = tid; x < n; x += bs)
@@ -795,8 +857,13 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 }
                 // each predecessor a receives sigma_sa * coef
                 coef = (((u.outdeg[x] & W_B) ? 1.0 : 0.0) + ax) / (double)Srow[x];
-                b0 = cptr[x];
-                deg = cptr[x + 1] - b0;
+                if (rec) {
+                    deg = u.kcnt[x];
+                    b0 = deg ? u.kend[x] - deg : 0;
+                } else {
+                    b0 = cptr[x];
+                    deg = cptr[x + 1] - b0;
+                }
                 dx = Drow[x];
             }
             int32_t total;
@@ -814,16 +881,18 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 chunk_arcs(es, nv, total, jb, iv, ev, ok);
 #pragma unroll
                 for (int k = 0; k < XU; ++k) {
-                    av[k] = ok[k] ? csrc[ev[k]] : 0;
-                    wv[k] = ok[k] ? cw[ev[k]] : 0;
+                    av[k] = ok[k] ? (rec ? u.kr[ev[k]] : csrc[ev[k]]) : 0;
+                    wv[k] = (ok[k] && !rec) ? cw[ev[k]] : 0;
                 }
                 double cf[XU];
 #pragma unroll
                 for (int k = 0; k < XU; ++k) {
                     cf[k] = 0.0;
                     if (!ok[k]) continue;
-                    const int32_t da = Drow[av[k]];
-                    ok[k] = da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]];
+                    if (!rec) {
+                        const int32_t da = Drow[av[k]];
+                        ok[k] = da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]];
+                    }
                     if (ok[k]) cf[k] = es.val[iv[k]];
                 }
                 uint64_t sa[XU];
@@ -849,6 +918,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
         for (int32_t x = tid; x < n; x += bs) {
             u.outdeg[x] = 0;
             u.acc[x] = 0.0;
+            if (rec) u.kcnt[x] = 0;
         }
     } else {
         for (int32_t i = tid; i < nsub; i += bs) {
@@ -1382,10 +1452,10 @@ __global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jo
 }
 
 // Wide kernel (persistent, runs after the DAG kernel): the deferred sources,
-// one workgroup of up to 512 threads each.  Each scans its row again into the
+// one workgroup of up to 1024 threads each.  Each scans its row again into the
 // slot's full-length B list, then runs update_source with the sub-DAGs in
 // global memory.
-__global__ void __launch_bounds__(512) k_source_wide(const UpdateJob *__restrict__ jobs,
+__global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restrict__ jobs,
                                                      const int32_t *__restrict__ njobs_p, char *__restrict__ scratch,
                                                      size_t slot_bytes, int32_t lds_cap, int32_t n_layout) {
     extern __shared__ __align__(16) char dyn_lds[];
@@ -1395,7 +1465,7 @@ __global__ void __launch_bounds__(512) k_source_wide(const UpdateJob *__restrict
     __shared__ BlockShared sh;
     const int tid = threadIdx.x, bs = blockDim.x;
     const int njobs = *njobs_p;
-    const USlot u = uslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
+    const USlot u = wslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
         if (job_dead(J)) continue;
@@ -1472,10 +1542,17 @@ __global__ void __launch_bounds__(256) k_commit(const UpdateJob *__restrict__ jo
             GraphCtl *c = J.g.ctl;
             c->affected_last = (unsigned long long)c->a_count;
             c->big_last = c->big_count;
+            // algorithmic bytes of the row scans: per affected source its
+            // distance row (4n) or, with the candidate list, the distances at
+            // the candidates (4|T|); sigma is read for the changed pairs only
+            const unsigned long long a = (unsigned long long)c->a_count, t = (unsigned long long)c->t_count;
+            const bool tl = (int64_t)c->t_count * 8 <= (int64_t)n;
+            c->scan_bytes_last = a * 4ull * (tl ? t : (unsigned long long)n) + 8ull * c->changed_pairs;
             if (!replace) {
                 c->updates += 1;
                 c->affected_total += (unsigned long long)c->a_count;
                 c->changed_total += c->changed_pairs;
+                c->scan_bytes_total += c->scan_bytes_last;
             }
             c->a_count = 0;
             c->work_next = 0;
@@ -1629,7 +1706,7 @@ __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict_
     const UpdateJob &J = jobs[0];
     const int32_t n = J.g.n;
     const bool lds = n <= lds_cap;
-    const USlot u = uslot_at(scratch, n_layout);
+    const USlot u = wslot_at(scratch, n_layout);
     if (job_dead(J)) return;
     const int32_t *Dg = J.g.D + (size_t)s * n;
     const int32_t *Drow = Dg;

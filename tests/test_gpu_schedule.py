@@ -1,0 +1,139 @@
+"""Launch schedules, graph clones and the schedule autotuner on the GPU.
+
+A schedule only maps affected sources onto workgroups, so every schedule must
+reach the same state: D, sigma and the DAGs bit-exact (the state hash covers
+D, sigma and E*), BC within the parity tolerance, and both equal to the
+oracle.  Small deferral thresholds push sources through the wide kernel and
+its whole-DAG passes, including the fallback for DAGs with more arcs than
+the pass can record.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_util import BC_TOL, bc_err, check_full, make_ctx, say
+from paper_1311_2147_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [
+    {"block": 256, "wide_block": 512, "big_b": 512, "wide_stage": 1},
+    {"block": 64, "wide_block": 256, "big_b": 1, "wide_stage": 1},
+    {"block": 128, "wide_block": 1024, "big_b": 1, "wide_stage": 2},
+    {"block": 192, "wide_block": 512, "big_b": 4, "wide_stage": 1},
+    {"block": 256, "wide_block": 1024, "big_b": 1024, "wide_stage": 1},
+]
+
+
+def layered(layers: int, width: int, w: int = 1) -> W.Graph:
+    """Complete bipartite joins between consecutive layers, unit weights:
+    DAG(s) of a first-layer source has about (layers-1) * width^2 arcs."""
+    src, dst = [], []
+    for l in range(layers - 1):
+        for i in range(width):
+            for j in range(width):
+                src.append(l * width + i)
+                dst.append((l + 1) * width + j)
+    m = len(src)
+    return W.Graph(layers * width, True, np.array(src, np.int32), np.array(dst, np.int32), np.full(m, w, np.int64))
+
+
+def _run(ctx, gr, ups):
+    for up in ups:
+        gr.update(up)
+    return gr.state_hash(), gr.scores()
+
+
+@pytest.mark.parametrize("shape", ["random", "layered"])
+def test_every_schedule_reaches_the_same_state(shape):
+    if shape == "random":
+        g = W.random_small(300, 0.03, 20, seed=17, directed=True)
+        ups = W.mixed_stream(g, 24, 20, 99, 0.35, 0.35, 12)
+    else:
+        g = layered(8, 12)
+        st = W.ArcStore(g)
+        ups = [W.Update("edge", u=0, v=7 * 12 + 3, w=2), W.Update("edge", u=12, v=5 * 12, w=1),
+               W.Update("vertex", v=30, edges=[(30, 70, 1), (5, 30, 1), (30, 95, 1)]),
+               W.Update("edge", u=2, v=90, w=3)]
+        for up in ups:
+            arcs = [(up.u, up.v)] if up.kind == "edge" else [(a, b) for a, b, _ in up.edges]
+            assert all(st.get(a, b) is None for a, b in arcs)
+    ctx = make_ctx(g.n, slots=16)
+    base = ctx.load_graph(g)
+    ref_hash = ref_bc = None
+    for sch in SCHEDULES:
+        say(f"{shape}: schedule {sch}")
+        ctx.set_schedule(**sch)
+        assert {k: ctx.schedule()[k] for k in sch} == sch
+        cl = base.clone()
+        h, bc = _run(ctx, cl, ups)
+        if ref_hash is None:
+            cur = g
+            for up in ups:
+                cur = W.apply_update(cur, up)
+            check_full(cl, cur, f"{shape} {sch}")
+            ref_hash, ref_bc = h, bc
+        else:
+            assert h == ref_hash, f"{shape}: state differs under {sch}"
+            assert bc_err(bc, ref_bc) <= BC_TOL, f"{shape}: BC differs under {sch}"
+        cl.free()
+    ctx.close()
+
+
+def test_clone_is_an_independent_copy():
+    g = W.random_small(120, 0.05, 9, seed=3, directed=True)
+    ctx = make_ctx(120, slots=8)
+    a = ctx.load_graph(g)
+    ups = W.mixed_stream(g, 6, 9, 5, 0.5, 0.3, 4)
+    a.update(ups[0])
+    b = a.clone()
+    assert b.state_hash() == a.state_hash()
+    assert np.array_equal(b.scores(), a.scores())
+    h_a = a.state_hash()
+    cur = W.apply_update(g, ups[0])
+    for up in ups[1:]:
+        b.update(up)
+        cur = W.apply_update(cur, up)
+    assert a.state_hash() == h_a
+    check_full(b, cur, "clone after updates")
+    check_full(a, W.apply_update(g, ups[0]), "original after clone updates")
+    ctx.close()
+
+
+def test_schedule_rejects_out_of_range_values():
+    from paper_1311_2147_amd import bcinc
+
+    ctx = make_ctx(64, slots=8)
+    before = ctx.schedule()
+    for bad in ({"block": 96}, {"block": 512}, {"big_b": 2000}, {"wide_block": 128}, {"wide_stage": 3},
+                {"slots": 9}):
+        with pytest.raises(bcinc.BcError) as e:
+            ctx.set_schedule(**bad)
+        assert e.value.name == "BC_ERR_INVALID_ARG"
+        assert ctx.schedule() == before
+    ctx.close()
+
+
+def test_autotune_keeps_graphs_and_sets_a_candidate():
+    g1 = W.random_small(200, 0.04, 30, seed=8, directed=True)
+    g2 = W.complete_undirected(64, 64 * 64, seed=4)
+    ctx = make_ctx(200, slots=16)
+    a, b = ctx.load_graph(g1), ctx.load_graph(g2)
+    h0 = (a.state_hash(), b.state_hash())
+    sample = [(a, up) for up in W.mixed_stream(g1, 6, 30, 41, 0.35, 0.35, 8)]
+    sample += [(b, up) for up in W.mixed_stream(g2, 6, 64 * 64, 42, 0.0, 0.7, 8)]
+    chosen = ctx.autotune(sample)
+    say(f"autotune chose {chosen}")
+    assert (a.state_hash(), b.state_hash()) == h0
+    assert ctx.schedule() == chosen
+    assert chosen["block"] in (64, 128, 256) and chosen["wide_block"] in (512, 1024)
+    assert chosen["big_b"] in (512, 1024)
+    # the stream itself, under the chosen schedule
+    ups = W.mixed_stream(g1, 10, 30, 43, 0.35, 0.35, 8)
+    cur = g1
+    for up in ups:
+        a.update(up)
+        cur = W.apply_update(cur, up)
+    check_full(a, cur, "after autotune")
+    ctx.close()

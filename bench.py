@@ -23,8 +23,10 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,6 +34,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rows_chunglu_n32768_traffic.md")
+KERNEL_SOURCES = ("paper_1311_2147_amd/csrc/bc_kernels.hip", "paper_1311_2147_amd/csrc/bc_device.h")
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """HBM bytes per row-kernel launch from the committed counter summary,
+    or None when there is none or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    sha = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", text)
+    val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not sha or not val or sha.group(1) != kernel_sources_sha256():
+        return None
+    return float(val.group(1))
 
 
 def log(msg):
@@ -48,7 +73,7 @@ def main():
     ap.add_argument("--plain", type=int, default=None, help="updates on the plain path (default steps*graphs)")
     ap.add_argument("--latency-requests", type=int, default=160)
     ap.add_argument("--cpu-sources", type=int, default=4096)
-    ap.add_argument("--legs", default="batched,plain,recompute,latency,cpu")
+    ap.add_argument("--legs", default="batched,plain,recompute,latency,cpu,copy")
     ap.add_argument("--tune-sample", type=int, default=8, help="updates per graph in the autotuner's sample (0: no tuning)")
     args = ap.parse_args()
 
@@ -206,6 +231,29 @@ def main():
         comparators["batched_over_recompute"] = value * rec_s
         log(f"full GPU recompute: {rec_s:.3f}s -> {1 / rec_s:.3f} updates/s")
 
+    # ------------------------------------------------------------------ copy
+    # A plain device-to-device copy of 1 GiB: the achievable HBM bandwidth on
+    # this box (read + write bytes over time), and the calibration kernel of
+    # the HBM counter runs.
+    copy_gbs = None
+    if "copy" in legs:
+        nb = 1 << 30
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * nb * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+        del a, b
+        torch.cuda.empty_cache()
+        log(f"device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
+
     # ---------------------------------------------------------------- cpu oracle
     cpu = None
     if "cpu" in legs and args.cpu_sources > 0:
@@ -257,7 +305,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": committed_traffic(),
+            "copy_gbs": copy_gbs,
             "avg_launch_ms": rows_ms / launches,
             "launches": launches,
             "bytes_per_launch": alg_bytes / launches,

@@ -190,11 +190,13 @@ __host__ __device__ inline UpdateLayout update_layout(int32_t n) {
 constexpr int32_t KARC_PER_VERTEX = 4;
 
 // Per-workgroup scratch of the wide kernel: the arrays of UpdateLayout, the
-// full-length changed-target list (bl_*), and for full passes the recorded
-// DAG arcs (ka = tail, kb = head, kr = tails grouped by head) with per-head
-// counts (kcnt, kept all-zero) and range ends (kend).
+// full-length changed-target list (bl_*), for full passes the recorded DAG
+// arcs (ka = tail, kb = head, kr = tails grouped by head) with per-head
+// counts (kcnt, kept all-zero) and range ends (kend), and the new distance
+// and path-count rows of a source whose new pass runs apart from its old one
+// (dnew, snew).
 struct WideLayout {
-    size_t outdeg, acc, sub, q1, q2, bl_t, bl_d, bl_s, kcnt, kend, ka, kb, kr, total;
+    size_t outdeg, acc, sub, q1, q2, bl_t, bl_d, bl_s, kcnt, kend, ka, kb, kr, dnew, snew, total;
     int64_t kcap;
 };
 
@@ -215,8 +217,29 @@ __host__ __device__ inline WideLayout wide_layout(int32_t n) {
     L.ka = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
     L.kb = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
     L.kr = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
+    L.dnew = off;   off += align256(sizeof(int32_t) * (size_t)n);
+    L.snew = off;   off += align256(sizeof(uint64_t) * (size_t)n);
     L.total = off;
     return L;
+}
+
+// Changed-pair list of one deferred source whose old and new passes run on
+// two workgroups: written by the old-pass workgroup, applied to D and sigma
+// by k_wide_apply after the wide kernel.  Header (count) then t, d, sigma.
+__host__ __device__ inline size_t item_region_bytes(int32_t n) {
+    return 256 + align256(4 * (size_t)n) * 2 + align256(8 * (size_t)n);
+}
+struct ItemRegion {
+    int32_t *nb, *t, *d;
+    uint64_t *s;
+};
+__host__ __device__ inline ItemRegion item_region_at(char *base, int32_t n) {
+    ItemRegion r;
+    r.nb = (int32_t *)base;
+    r.t = (int32_t *)(base + 256);
+    r.d = (int32_t *)(base + 256 + align256(4 * (size_t)n));
+    r.s = (uint64_t *)(base + 256 + 2 * align256(4 * (size_t)n));
+    return r;
 }
 
 // Workgroup slots: the DAG kernel and the static pass share one region, the

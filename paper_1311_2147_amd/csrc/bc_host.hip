@@ -208,30 +208,35 @@ int wide_slots_for(int slots) { return std::min(slots, WIDE_SLOTS_MAX); }
 
 // The part of the scratch buffer after the pool, laid out for graphs of up to
 // n vertices: `src` slots of the DAG kernel and the static pass, then `wide`
-// slots of the wide kernel.  Fewer slots than configured when the buffer was
-// sized for a smaller n; zero counts when not even one of each fits.
+// slots of the wide kernel, then as many item regions (changed-pair lists of
+// deferred sources whose two passes run apart).  Fewer slots than configured
+// when the buffer was sized for a smaller n; zero counts when not even one of
+// each fits.
 struct ScratchPlan {
     int src = 0, wide = 0;
-    size_t src_bytes = 0, wide_bytes = 0;
-    char *src_base = nullptr, *wide_base = nullptr;
+    size_t src_bytes = 0, wide_bytes = 0, item_bytes = 0;
+    char *src_base = nullptr, *wide_base = nullptr, *items_base = nullptr;
 };
 
 ScratchPlan plan_scratch(bc_ctx *ctx, int32_t n) {
     ScratchPlan p;
     p.src_bytes = slot_bytes_for(n);
     p.wide_bytes = wide_slot_bytes_for(n);
+    p.item_bytes = item_region_bytes(n);
     const uint64_t fixed = ring_bytes() + MISC_BYTES + pool_bytes(n);
     if (ctx->scratch_bytes <= fixed) return p;
     const uint64_t avail = ctx->scratch_bytes - fixed;
+    const uint64_t per_wide = p.wide_bytes + p.item_bytes;
     uint64_t w = (uint64_t)wide_slots_for(ctx->slots);
-    w = std::min<uint64_t>(w, avail / (p.wide_bytes + p.src_bytes));
+    w = std::min<uint64_t>(w, avail / (per_wide + p.src_bytes));
     if (w < 1) return p;
-    const uint64_t s = std::min<uint64_t>((uint64_t)ctx->slots, (avail - w * p.wide_bytes) / p.src_bytes);
+    const uint64_t s = std::min<uint64_t>((uint64_t)ctx->slots, (avail - w * per_wide) / p.src_bytes);
     if (s < 1) return p;
     p.src = (int)s;
     p.wide = (int)w;
     p.src_base = pool_dev(ctx) + pool_bytes(n);
     p.wide_base = p.src_base + s * p.src_bytes;
+    p.items_base = p.wide_base + w * p.wide_bytes;
     return p;
 }
 
@@ -392,7 +397,8 @@ struct LaunchShape {
     int src_lds_cap;  // per-source kernel: rows up to this size are staged in LDS
     int wide_slots;   // workgroups of the wide per-source kernel
     size_t wide_bytes;
-    char *src_base, *wide_base;
+    char *src_base, *wide_base, *items_base;
+    int item_regions;
     int wide_lds_cap; // and its LDS staging limit
     int32_t n_layout;
 };
@@ -421,7 +427,9 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
                            jobs, nj, L.src_base, L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
         hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(ctx->wide_block),
                            source_lds_bytes(L.wide_lds_cap, ctx->wide_block, false), st, jobs, nj, L.wide_base,
-                           L.wide_bytes, L.wide_lds_cap, L.n_layout);
+                           L.wide_bytes, L.wide_lds_cap, L.n_layout, L.items_base, L.item_regions);
+        hipLaunchKernelGGL(k_wide_apply, dim3(256), dim3(256), 0, st, jobs, nj, L.items_base, L.item_regions,
+                           L.n_layout);
     } else {
         hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
@@ -462,6 +470,8 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     L->src_base = sp.src_base;
     L->wide_bytes = sp.wide_bytes;
     L->wide_base = sp.wide_base;
+    L->items_base = sp.items_base;
+    L->item_regions = sp.wide;
     if (ctx->run_slots > 0) L->slots = std::min(L->slots, ctx->run_slots);
     L->lds_cap = lds_cap_for(L->n_max);
     // the row is staged only when it fits; otherwise no LDS is reserved for it
@@ -746,7 +756,7 @@ uint64_t bc_scratch_bytes(int32_t n_max, int32_t slots) {
     if (n_max <= 0) return 0;
     if (slots <= 0) slots = DEFAULT_SLOTS;
     return ring_bytes() + MISC_BYTES + pool_bytes(n_max) + (uint64_t)slots * slot_bytes_for(n_max) +
-           (uint64_t)wide_slots_for(slots) * wide_slot_bytes_for(n_max);
+           (uint64_t)wide_slots_for(slots) * (wide_slot_bytes_for(n_max) + item_region_bytes(n_max));
 }
 
 const char *bc_status_string(bc_status s) {

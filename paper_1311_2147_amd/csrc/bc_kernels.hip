@@ -374,18 +374,45 @@ __global__ void __launch_bounds__(1024) k_es_scan(const UpdateJob *__restrict__ 
     if (MODE >= ES_MERGE && job_dead(J)) return;
     const EsView e = es_view(J, MODE);
     const int32_t n = J.g.n;
-    const int32_t per = (n + blockDim.x - 1) / blockDim.x;
-    const int32_t i0 = min(n, (int32_t)threadIdx.x * per), i1 = min(n, i0 + per);
-    int32_t local = 0;
-    for (int32_t i = i0; i < i1; ++i) local += J.g.es_cnt[i];
-    int32_t total;
-    int32_t off = block_excl_scan(local, sh, total);
-    for (int32_t i = i0; i < i1; ++i) {
-        const int32_t c = J.g.es_cnt[i];
-        e.optr[i] = off;
-        off += c;
+    const int32_t *cnt = J.g.es_cnt;
+    // tiles of 8 consecutive counts per thread (two 16-byte loads), one block
+    // scan per tile, a running carry between tiles
+    int32_t carry = 0;
+    for (int32_t base = 0; base < n; base += 8 * (int32_t)blockDim.x) {
+        const int32_t i0 = base + 8 * (int32_t)threadIdx.x;
+        int32_t v[8];
+        const bool whole = i0 + 8 <= n;
+        if (whole) {
+            const int4 a = *(const int4 *)(cnt + i0), b = *(const int4 *)(cnt + i0 + 4);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = (i0 + k < n) ? cnt[i0 + k] : 0;
+        }
+        int32_t local = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) local += v[k];
+        int32_t total;
+        int32_t off = block_excl_scan(local, sh, total) + carry;
+        int32_t o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            o[k] = off;
+            off += v[k];
+        }
+        if (whole) {
+            *(int4 *)(e.optr + i0) = make_int4(o[0], o[1], o[2], o[3]);
+            *(int4 *)(e.optr + i0 + 4) = make_int4(o[4], o[5], o[6], o[7]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i0 + k < n) e.optr[i0 + k] = o[k];
+        }
+        carry += total;
     }
     if (threadIdx.x == 0) {
+        const int32_t total = carry;
         e.optr[n] = total;
         if (total > e.m_limit) {
             atomicOr(&J.g.ctl->status, ST_ESTAR_CAP);
@@ -482,7 +509,8 @@ struct USlot {
     int32_t *outdeg, *sub, *q1, *q2, *bl_t, *bl_d;
     double *acc;
     uint64_t *bl_s;
-    int32_t *kcnt, *kend, *ka, *kb, *kr;
+    int32_t *kcnt, *kend, *ka, *kb, *kr, *dnew;
+    uint64_t *snew;
     int64_t kcap;
 };
 
@@ -496,7 +524,8 @@ __device__ __forceinline__ USlot uslot_at(char *base, int32_t n) {
     u.q2 = (int32_t *)(base + L.q2);
     u.bl_t = u.bl_d = nullptr;
     u.bl_s = nullptr;
-    u.kcnt = u.kend = u.ka = u.kb = u.kr = nullptr;
+    u.kcnt = u.kend = u.ka = u.kb = u.kr = u.dnew = nullptr;
+    u.snew = nullptr;
     u.kcap = 0;
     return u;
 }
@@ -517,6 +546,8 @@ __device__ __forceinline__ USlot wslot_at(char *base, int32_t n) {
     u.ka = (int32_t *)(base + L.ka);
     u.kb = (int32_t *)(base + L.kb);
     u.kr = (int32_t *)(base + L.kr);
+    u.dnew = (int32_t *)(base + L.dnew);
+    u.snew = (uint64_t *)(base + L.snew);
     u.kcap = L.kcap;
     return u;
 }
@@ -1221,6 +1252,8 @@ __device__ __forceinline__ uint32_t quad_mask(const int4 d, const int4 f, const 
 // Keeping the second phase out of the streaming loop keeps that loop small
 // and spreads the flagged pairs over the workgroup.  The caller zeroes sh.nf
 // and sh.nb before; if sh.nf > fcap after the call, the B list is incomplete.
+// QU quads per lane are in flight in the streaming loop.
+template <int QU>
 __device__ __forceinline__ void scan_row(const UpdateJob &J, const RowV &R, const SrcScal &sc, const bool same,
                                          const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Sg,
                                          const bool use_tlist, const int32_t t_count, int32_t *F, const int32_t fcap,
@@ -1241,22 +1274,22 @@ __device__ __forceinline__ void scan_row(const UpdateJob &J, const RowV &R, cons
     } else if (sc.dv == INF32) {
         // v unreachable from s: no pair of the row can change
     } else if ((n & 3) == 0) {
-        // eight quads (32 pairs) per lane in flight, tested against one
+        // QU quads (4 QU pairs) per lane in flight, tested against one
         // filter row
         const int32_t nq = n >> 2;
         const int4 *D4 = (const int4 *)Drow;
         const int4 *F4 = (const int4 *)(in_on ? J.g.f_any : J.g.f_out);
-        for (int32_t q0 = tid; q0 < nq; q0 += 8 * bs) {
-            int4 dq[8], fq[8];
+        for (int32_t q0 = tid; q0 < nq; q0 += QU * bs) {
+            int4 dq[QU], fq[QU];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < QU; ++k) {
                 const int32_t q = q0 + k * bs;
                 dq[k] = (q < nq) ? D4[q] : make_int4(0, 0, 0, 0);
                 fq[k] = (q < nq) ? F4[q] : make_int4(INF32, INF32, INF32, INF32);
             }
             uint32_t m = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) m |= quad_mask(dq[k], fq[k], sc.dv) << (4 * k);
+            for (int k = 0; k < QU; ++k) m |= quad_mask(dq[k], fq[k], sc.dv) << (4 * k);
             while (m) {
                 const int b = __ffs(m) - 1;
                 m &= m - 1;
@@ -1336,7 +1369,7 @@ __global__ void __launch_bounds__(256) k_rows(const UpdateJob *__restrict__ jobs
             const SrcScal sc = J.g.scal[s];
             const int32_t *Drow = J.g.D + (size_t)s * n;
             const uint64_t *Sg = J.g.S + (size_t)s * n;
-            scan_row(J, R, sc, (sc.flags & 1) != 0, Drow, Sg, use_tlist, t_count, lf, LCAP, L, sh, ovf_s, ovf_d);
+            scan_row<8>(J, R, sc, (sc.flags & 1) != 0, Drow, Sg, use_tlist, t_count, lf, LCAP, L, sh, ovf_s, ovf_d);
             __syncthreads();
             const int32_t nb = sh.nb;
             if (nb == 0 && sh.nf <= LCAP) continue;
@@ -1452,20 +1485,27 @@ __global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jo
 }
 
 // Wide kernel (persistent, runs after the DAG kernel): the deferred sources,
-// one workgroup of up to 1024 threads each.  Each scans its row again into the
-// slot's full-length B list, then runs update_source with the sub-DAGs in
-// global memory.
+// one workgroup of up to 1024 threads per unit of work.  The first
+// item_regions deferred sources (over the jobs in order) run as two units on
+// two workgroups at once: the old pass (it also stores the changed pairs in
+// the source's item region) and the new pass (it forms the new row and path
+// counts in its slot from the old ones and the changed pairs).  Neither
+// writes D or sigma; k_wide_apply does afterwards.  Further deferred sources
+// run as one unit each: scan, old pass, write the changed pairs, new pass.
+// Every unit scans its row again into the slot's full-length list.
 __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restrict__ jobs,
-                                                     const int32_t *__restrict__ njobs_p, char *__restrict__ scratch,
-                                                     size_t slot_bytes, int32_t lds_cap, int32_t n_layout) {
+                                                      const int32_t *__restrict__ njobs_p, char *__restrict__ scratch,
+                                                      size_t slot_bytes, int32_t lds_cap, int32_t n_layout,
+                                                      char *__restrict__ items, int32_t item_regions) {
     extern __shared__ __align__(16) char dyn_lds[];
     int32_t *const lds_row = (int32_t *)dyn_lds;
     const ExpandShared es = expand_at(dyn_lds, lds_cap);
-    const SmallDag sd = small_dag_at(dyn_lds + align256((size_t)lds_cap * 4) + align256(XB * (size_t)blockDim.x));
     __shared__ BlockShared sh;
     const int tid = threadIdx.x, bs = blockDim.x;
     const int njobs = *njobs_p;
     const USlot u = wslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
+    const size_t region_bytes = item_region_bytes(n_layout);
+    int32_t region0 = 0;  // first item region of the job
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
         if (job_dead(J)) continue;
@@ -1473,6 +1513,8 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
         const int32_t n = J.g.n;
         const bool lds = n <= lds_cap;
         const int32_t count = *(volatile int32_t *)&ctl->big_count;
+        const int32_t paired = min(count, item_regions - region0);
+        const int32_t units = 2 * paired + (count - paired);
         const RowV R = row_v_of(J);
         const int32_t t_count = *(volatile int32_t *)&ctl->t_count;
         const bool use_tlist = (int64_t)t_count * 8 <= (int64_t)n;
@@ -1487,27 +1529,106 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                 sh.nf = 0;
             }
             __syncthreads();
-            const int32_t item = sh.item;
-            if (item >= count) break;
+            const int32_t unit = sh.item;
+            if (unit >= units) break;
+            // role 0: old pass, 1: new pass, 2: the whole update of the source
+            const int32_t item = unit < 2 * paired ? unit >> 1 : paired + (unit - 2 * paired);
+            const int role = unit < 2 * paired ? (unit & 1) : 2;
             const int32_t s = J.g.biglist[item];
             const SrcScal sc = J.g.scal[s];
             const int32_t *Dg = J.g.D + (size_t)s * n;
+            const uint64_t *Sg = J.g.S + (size_t)s * n;
             if (lds) {
                 for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
                 __syncthreads();
             }
-            scan_row(J, R, sc, (sc.flags & 1) != 0, lds ? lds_row : Dg, J.g.S + (size_t)s * n, use_tlist, t_count,
-                     u.q1, n, L, sh, ovf_s, ovf_d);
+            scan_row<4>(J, R, sc, (sc.flags & 1) != 0, lds ? lds_row : Dg, Sg, use_tlist, t_count, u.q1, n, L, sh,
+                        ovf_s, ovf_d);
             __syncthreads();
             const int32_t nb = sh.nb;
+            if (role == 0) {
+                const ItemRegion ir = item_region_at(items + (size_t)(region0 + item) * region_bytes, n_layout);
+                for (int32_t i = tid; i < nb; i += bs) {
+                    ir.t[i] = u.bl_t[i];
+                    ir.d[i] = u.bl_d[i];
+                    ir.s[i] = u.bl_s[i];
+                }
+                if (tid == 0) *ir.nb = nb;
+            }
             if (nb == 0) continue;
-            update_source(J, s, u.bl_t, u.bl_d, u.bl_s, nb, lds, lds_row, u, sh, es, sd, false);
-            if (tid == 0) sh.counter += (unsigned long long)nb;
+            if (role != 1 && tid == 0) sh.counter += (unsigned long long)nb;
+            const bool full = (int64_t)nb * 16 >= (int64_t)n;
+            // phase 0: old pass (roles 0 and 2); phase 1: new pass (roles 1 and 2)
+            for (int ph = role == 1 ? 1 : 0; ph <= (role == 0 ? 0 : 1); ++ph) {
+                const int32_t *Dr = lds ? lds_row : Dg;
+                const uint64_t *Sr = Sg;
+                if (ph == 1) {
+                    if (role == 1) {
+                        // the new row and counts: the old ones with the changed pairs in
+                        int32_t *Dn = lds ? lds_row : u.dnew;
+                        if (!lds)
+                            for (int32_t t = tid; t < n; t += bs) u.dnew[t] = Dg[t];
+                        for (int32_t t = tid; t < n; t += bs) u.snew[t] = Sg[t];
+                        __syncthreads();
+                        for (int32_t i = tid; i < nb; i += bs) {
+                            Dn[u.bl_t[i]] = u.bl_d[i];
+                            u.snew[u.bl_t[i]] = u.bl_s[i];
+                        }
+                        Dr = Dn;
+                        Sr = u.snew;
+                    } else {
+                        int32_t *Dw = J.g.D + (size_t)s * n;
+                        uint64_t *Sw = J.g.S + (size_t)s * n;
+                        for (int32_t i = tid; i < nb; i += bs) {
+                            const int32_t t = u.bl_t[i];
+                            const int32_t d = u.bl_d[i];
+                            Sw[t] = u.bl_s[i];
+                            Dw[t] = d;
+                            if (lds) lds_row[t] = d;
+                        }
+                    }
+                    __syncthreads();
+                }
+                restricted_pass<false>(s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
+                                       ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u,
+                                       ph ? 1.0 : -1.0, J.g.bc_delta, sh, es);
+            }
         }
         if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
         if (ovf_d) atomicOr(&ctl->status, ST_DIST_OVF);
         __syncthreads();
         if (tid == 0 && sh.counter) atomicAdd(&ctl->changed_pairs, sh.counter);
+        region0 += paired;
+    }
+}
+
+// Writes the changed pairs of the deferred sources whose two passes ran
+// apart (same item-region assignment as k_source_wide).
+__global__ void __launch_bounds__(256) k_wide_apply(const UpdateJob *__restrict__ jobs,
+                                                    const int32_t *__restrict__ njobs_p, char *__restrict__ items,
+                                                    int32_t item_regions, int32_t n_layout) {
+    const int njobs = *njobs_p;
+    const size_t region_bytes = item_region_bytes(n_layout);
+    int32_t region0 = 0;
+    for (int j = 0; j < njobs; ++j) {
+        const UpdateJob &J = jobs[j];
+        if (job_dead(J)) continue;
+        const int32_t n = J.g.n;
+        const int32_t count = *(volatile int32_t *)&J.g.ctl->big_count;
+        const int32_t paired = min(count, item_regions - region0);
+        for (int32_t item = blockIdx.x; item < paired; item += gridDim.x) {
+            const ItemRegion ir = item_region_at(items + (size_t)(region0 + item) * region_bytes, n_layout);
+            const int32_t s = J.g.biglist[item];
+            const int32_t nb = *ir.nb;
+            int32_t *Dg = J.g.D + (size_t)s * n;
+            uint64_t *Sg = J.g.S + (size_t)s * n;
+            for (int32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+                const int32_t t = ir.t[i];
+                Dg[t] = ir.d[i];
+                Sg[t] = ir.s[i];
+            }
+        }
+        region0 += paired;
     }
 }
 

@@ -235,6 +235,9 @@ bc_status bc_reset_timing(bc_ctx *ctx);
  *   wide_block: threads per workgroup of the wide kernel: 256, 512 or 1024
  *   wide_stage: 1 = stage rows in LDS when they fit, 2 = never stage
  *   wide_slots: persistent workgroups of the wide kernel (at most slots)
+ *   table:      slots of the DAG kernel's LDS sub-DAG tables: 128 or 256
+ *               (smaller tables fit more workgroups per CU, larger ones
+ *               send fewer sub-DAGs to global memory)
  * bc_set_schedule synchronises the context's stream before it switches.
  * Errors: BC_ERR_INVALID_ARG for a value out of range (nothing changes). */
 typedef struct {
@@ -244,14 +247,16 @@ typedef struct {
     int32_t wide_block;
     int32_t wide_stage;
     int32_t wide_slots;
+    int32_t table;
 } bc_schedule;
 bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s);
 bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out);
 
 /* Autotuner of the launch schedule.  reqs[0..cnt) is a sample of requests
  * in bc_submit form on resident graphs (typically updates like the expected
- * stream, drawn for tuning).  For each candidate schedule (block 64, 128 or
- * 256; wide_block 512 or 1024; big_b 512 or 1024; the other fields as set)
+ * stream, drawn for tuning).  For each candidate schedule (table 128 or 256;
+ * block 128 or 256; wide_block 512 or 1024; big_b 512 or 1024; the other
+ * fields as set)
  * the sample runs on fresh device clones of its graphs, twice (the first run
  * also captures the step graphs), and the summed device time of the second
  * run's steps ranks the candidate.  The fastest is set on the context and

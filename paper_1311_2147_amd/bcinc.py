@@ -75,7 +75,8 @@ class bc_timing(ctypes.Structure):
 
 class bc_schedule(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("slots", ctypes.c_int32), ("big_b", ctypes.c_int32),
-                ("wide_block", ctypes.c_int32), ("wide_stage", ctypes.c_int32), ("wide_slots", ctypes.c_int32)]
+                ("wide_block", ctypes.c_int32), ("wide_stage", ctypes.c_int32), ("wide_slots", ctypes.c_int32),
+                ("table", ctypes.c_int32)]
 
 
 SCHEDULE_FIELDS = tuple(f for f, _ in bc_schedule._fields_)

@@ -52,8 +52,10 @@ struct GraphCtl {
     int32_t big_count;  // deferred (large) sources of the update in flight
     int32_t big_next;   // next deferred source to process
     int32_t big_last;   // deferred sources of the last update (statistic)
-    int32_t dag_count;  // listed sources of the update in flight (row kernel output)
+    int32_t dag_count;  // listed sources with many changed targets: dlist[0 .. dag_count)
     int32_t dag_next;   // next listed source of the DAG kernel
+    int32_t dag_back;   // listed sources with few: dlist[n - dag_back .. n)
+    int32_t pad2;
     unsigned long long changed_pairs;  // statistic of the last update
     unsigned long long affected_last;  // |A| of the last update
     unsigned long long updates;        // updates applied since load
@@ -93,6 +95,9 @@ struct StepPool {
 
 // Most changed targets the row kernel lists for one source (in LDS).
 constexpr int32_t LCAP = 1024;
+// Listed sources with at least this many changed targets go first to the DAG
+// kernel (their sub-DAGs take longest; starting them first shortens the tail).
+constexpr int32_t HEAVY_NB = 32;
 
 // Device pointers and sizes of one graph.  A copy rides in every job.
 struct GraphPtrs {

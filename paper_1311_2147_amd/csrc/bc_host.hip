@@ -137,6 +137,7 @@ struct bc_ctx {
     int wide_block = DEFAULT_WIDE_BLOCK;
     int wide_stage = 1;
     int wide_slots = 0;  // 0: one workgroup per CU when staging, else two
+    int table = 256;     // LDS sub-DAG table slots of the DAG kernel
     size_t wide_lds_limit = 0;  // dynamic LDS the wide kernel may use
     int rows_grid = 1024;       // workgroups of the row kernel (all resident)
     int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
@@ -243,10 +244,15 @@ ScratchPlan plan_scratch(bc_ctx *ctx, int32_t n) {
 int lds_cap_for(int32_t n_max) { return std::min<int32_t>(n_max, LDS_ROW_MAX); }
 
 // Dynamic LDS of the per-source kernels: staged row, XB bytes per thread of
-// expansion arrays, and the small sub-DAG table (which the wide kernel does
-// not use: its workgroups stop before it).
-size_t source_lds_bytes(int lds_cap, int block, bool small = true) {
-    return align256((size_t)lds_cap * 4) + align256(XB * (size_t)block) + (small ? small_dag_bytes() : 0);
+// expansion arrays, and the LDS sub-DAG tables of `table` slots (0: none; the
+// wide kernel and the dependency-row kernel use none).
+size_t table_bytes(int table) {
+    if (table == 256) return std::max(small_dag_bytes<256>(), dual_dag_bytes<256>());
+    if (table == 128) return std::max(small_dag_bytes<128>(), dual_dag_bytes<128>());
+    return 0;
+}
+size_t source_lds_bytes(int lds_cap, int block, int table) {
+    return align256((size_t)lds_cap * 4) + align256(XB * (size_t)block) + table_bytes(table);
 }
 
 // Arena layout of one graph (every piece 256-byte aligned).
@@ -423,10 +429,15 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
     } else if (part == 1) {
         hipLaunchKernelGGL(k_rows, dim3(ctx->rows_grid), dim3(256), 0, st, jobs, nj, ctx->big_b, pool);
     } else if (part == 2) {
-        hipLaunchKernelGGL(k_source, dim3(L.slots), dim3(ctx->block), source_lds_bytes(L.src_lds_cap, ctx->block), st,
-                           jobs, nj, L.src_base, L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
+        const size_t lds = source_lds_bytes(L.src_lds_cap, ctx->block, ctx->table);
+        if (ctx->table == 128)
+            hipLaunchKernelGGL(k_source<128>, dim3(L.slots), dim3(ctx->block), lds, st, jobs, nj, L.src_base,
+                               L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
+        else
+            hipLaunchKernelGGL(k_source<256>, dim3(L.slots), dim3(ctx->block), lds, st, jobs, nj, L.src_base,
+                               L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
         hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(ctx->wide_block),
-                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block, false), st, jobs, nj, L.wide_base,
+                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block, 0), st, jobs, nj, L.wide_base,
                            L.wide_bytes, L.wide_lds_cap, L.n_layout, L.items_base, L.item_regions);
         hipLaunchKernelGGL(k_wide_apply, dim3(256), dim3(256), 0, st, jobs, nj, L.items_base, L.item_regions,
                            L.n_layout);
@@ -478,7 +489,7 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     L->src_lds_cap = L->n_max <= ctx->src_lds_max ? L->n_max : 0;
     // wide kernel: the row is staged when it fits beside the expansion arrays
     // and the small-DAG table; one workgroup per CU then, else two
-    const size_t wide_lds = source_lds_bytes(L->n_max, ctx->wide_block, false);
+    const size_t wide_lds = source_lds_bytes(L->n_max, ctx->wide_block, 0);
     const bool stage = ctx->wide_stage == 1 && wide_lds <= ctx->wide_lds_limit;
     L->wide_lds_cap = stage ? L->n_max : 0;
     const int per_cu = (stage && wide_lds * 2 > ctx->wide_lds_limit) || ctx->wide_block > 512 ? 1 : 2;
@@ -731,7 +742,8 @@ bc_status set_lds_limit(bc_ctx *ctx, const void *fn, size_t *limit = nullptr) {
 
 bc_status set_lds_limits(bc_ctx *ctx) {
     bc_status st;
-    if ((st = set_lds_limit(ctx, (const void *)k_source))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_source<256>))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_source<128>))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_source_wide, &ctx->wide_lds_limit))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_sssp))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_static))) return st;
@@ -871,8 +883,9 @@ bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s) {
     const int wide_block = s->wide_block ? s->wide_block : ctx->wide_block;
     const int wide_stage = s->wide_stage ? s->wide_stage : ctx->wide_stage;
     const int wide_slots = s->wide_slots ? s->wide_slots : ctx->wide_slots;
+    const int table = s->table ? s->table : ctx->table;
     if (block < 64 || block > 256 || block % 64 != 0 || slots < 0 || slots > ctx->slots || big_b < 1 || big_b > LCAP ||
-        (wide_block != 256 && wide_block != 512 && wide_block != 1024) || (wide_stage != 1 && wide_stage != 2) || wide_slots < 0 ||
+        (wide_block != 256 && wide_block != 512 && wide_block != 1024) || (table != 128 && table != 256) || (wide_stage != 1 && wide_stage != 2) || wide_slots < 0 ||
         wide_slots > ctx->slots)
         return fail(ctx, BC_ERR_INVALID_ARG, "schedule value out of range");
     HIPCHK(hipSetDevice(ctx->device));
@@ -889,6 +902,7 @@ bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s) {
     ctx->wide_block = wide_block;
     ctx->wide_stage = wide_stage;
     ctx->wide_slots = wide_slots;
+    ctx->table = table;
     return BC_OK;
 }
 
@@ -964,23 +978,25 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
     bc_schedule best = start;
     double best_ms = 1e300;
     ctx->timing = true;
-    for (int block : {256, 128, 64})
-        for (int wide_block : {512, 1024})
-            for (int big_b : {512, 1024}) {
-                bc_schedule c = start;
-                c.block = block;
-                c.wide_block = wide_block;
-                c.big_b = big_b;
-                c.slots = start.slots ? start.slots : 0;
-                if ((st = bc_set_schedule(ctx, &c))) break;
-                double ms = 0;
-                if ((st = run(&ms))) break;
-                if ((st = run(&ms))) break;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    bc_get_schedule(ctx, &best);
+    for (int table : {256, 128})
+        for (int block : {256, 128})
+            for (int wide_block : {512, 1024})
+                for (int big_b : {512, 1024}) {
+                    if (st) break;
+                    bc_schedule c = start;
+                    c.block = block;
+                    c.wide_block = wide_block;
+                    c.big_b = big_b;
+                    c.table = table;
+                    if ((st = bc_set_schedule(ctx, &c))) break;
+                    double ms = 0;
+                    if ((st = run(&ms))) break;
+                    if ((st = run(&ms))) break;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        bc_get_schedule(ctx, &best);
+                    }
                 }
-            }
     ctx->timing = timing0;
     ctx->step_ms = step0;
     ctx->source_ms = src0;
@@ -1002,6 +1018,7 @@ bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out) {
     out->wide_block = ctx->wide_block;
     out->wide_stage = ctx->wide_stage;
     out->wide_slots = ctx->wide_slots;
+    out->table = ctx->table;
     return BC_OK;
 }
 
@@ -1360,7 +1377,7 @@ bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
     // the pass runs in wide slot 0; the row lands in its B-list value area,
     // which the pass does not use
     double *row = (double *)(sp.wide_base + wide_layout(ctx->n_layout).bl_s);
-    hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), source_lds_bytes(lds, 1024), ctx->stream,
+    hipLaunchKernelGGL(k_delta_row, dim3(1), dim3(1024), source_lds_bytes(lds, 1024, 0), ctx->stream,
                        ring_jobs_dev(ctx, r), s, sp.wide_base, lds, ctx->n_layout, row);
     HIPCHK(hipGetLastError());
     if ((st = ring_release(ctx, r))) return st;

@@ -969,9 +969,14 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
 // predecessors' distances are read from global memory.  A sub-DAG that
 // outgrows the table is redone by restricted_pass (nothing global has been
 // written by then).
-constexpr int SD_SLOTS = 256;     // hash slots (power of two)
-constexpr int SD_CAP = 192;       // most vertices admitted (load factor 3/4)
-constexpr int SD_ARCS = 512;      // most sub-DAG arcs
+// Table sizes of the LDS passes are a template parameter TS (a power of two
+// of at most 256, so a slot fits a byte): TS hash slots, 3/4 of them admitted
+// as vertices (load factor 3/4), 2 TS sub-DAG arcs.  Smaller tables let more
+// workgroups share a CU; larger ones fall back to global memory less often.
+#define SD_CONSTS                          \
+    constexpr int SD_SLOTS = TS;           \
+    constexpr int SD_CAP = TS * 3 / 4;     \
+    constexpr int SD_ARCS = 2 * TS;
 
 struct SmallDag {
     int32_t *key, *flags, *outdeg, *dval, *round;
@@ -980,11 +985,15 @@ struct SmallDag {
     int16_t *sub, *arc_a, *arc_x;
 };
 
+template <int TS>
 __host__ __device__ constexpr size_t small_dag_bytes() {
+    SD_CONSTS
     return (size_t)SD_SLOTS * (5 * 4 + 3 * 8 + 2) + (size_t)SD_ARCS * 4 + 256;
 }
 
+template <int TS>
 __device__ __forceinline__ SmallDag small_dag_at(char *p) {
+    SD_CONSTS
     SmallDag d;
     d.acc = (double *)p;             p += 8 * SD_SLOTS;
     d.coef = (double *)p;            p += 8 * SD_SLOTS;
@@ -1001,7 +1010,9 @@ __device__ __forceinline__ SmallDag small_dag_at(char *p) {
 }
 
 // Slot of vertex x, inserting it if absent; -1 if the table is full.
+template <int TS>
 __device__ __forceinline__ int32_t sd_slot(const SmallDag &d, int32_t x, bool &inserted) {
+    SD_CONSTS
     uint32_t h = ((uint32_t)x * 2654435761u) >> 24;
     inserted = false;
     for (int p = 0; p < SD_SLOTS; ++p) {
@@ -1019,11 +1030,13 @@ __device__ __forceinline__ int32_t sd_slot(const SmallDag &d, int32_t x, bool &i
 // The partial dependency of restricted_pass with all per-vertex state in
 // LDS.  Returns false (and leaves global memory untouched) if the sub-DAG
 // does not fit.
+template <int TS>
 __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Srow,
                            const int32_t *__restrict__ cptr, const int32_t *__restrict__ csrc,
                            const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
                            const double sign, double *out, BlockShared &sh, const ExpandShared &es,
                            const SmallDag &d) {
+    SD_CONSTS
     const int tid = threadIdx.x, bs = blockDim.x;
     for (int32_t i = tid; i < SD_SLOTS; i += bs) {
         d.key[i] = -1;
@@ -1043,7 +1056,7 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
         const int32_t dt = Drow[t];
         if (t == s || dt == INF32) continue;
         bool ins;
-        const int32_t slot = sd_slot(d, t, ins);
+        const int32_t slot = sd_slot<TS>(d, t, ins);
         const int32_t pos = atomicAdd(&sh.next, 1);
         if (slot < 0 || pos >= SD_CAP) {
             sh.ovf = 1;
@@ -1083,7 +1096,7 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
                 const int32_t da = Drow[a];
                 if (da != INF32 && (int64_t)da + cw[e] == (int64_t)d.dval[sxv]) {
                     bool ins;
-                    const int32_t sa = sd_slot(d, a, ins);
+                    const int32_t sa = sd_slot<TS>(d, a, ins);
                     const int32_t k = atomicAdd(&sh.tail, 1);
                     if (sa < 0 || k >= SD_ARCS) {
                         sh.ovf = 1;
@@ -1142,6 +1155,248 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
         }
         __syncthreads();
     }
+    return true;
+}
+
+// Old and new partial dependency of one source in one traversal (LDS only).
+// The vertices to visit are the union of the old sub-DAG (ancestors of B in
+// DAG(s)) and the new one (ancestors of B in DAG'(s)); both are walked back
+// from B level by level at once, so the dependent gathers of a level serve
+// both.  The new distances and path counts are those of the B list for
+// targets in B and the old ones elsewhere, so D and sigma are not written
+// before the new pass.  Over the merged E* segment of a head x (E* by head,
+// with the update's arcs appended), the first |E*(x)| arcs are the old E*
+// arcs with their old weights: the old Eq.1 test looks at those only, the new
+// test at all of them (an old-weight copy of a lowered arc cannot pass it).
+// The two Kahn accumulations then run over the recorded arcs, and BC gets the
+// difference delta'_B - delta_B once per vertex.  Returns false, before
+// anything global is written, when the union does not fit.
+#define DD_CONSTS                          \
+    constexpr int DD_SLOTS = TS;           \
+    constexpr int DD_CAP = TS * 3 / 4;     \
+    constexpr int DD_ARCS = 2 * TS;        \
+    constexpr int DD_FRONT = 2 * DD_CAP;
+enum : int32_t { DF_O = 1, DF_N = 2, DF_B = 4 };
+
+struct DualDag {
+    int32_t *key, *flags, *cnt, *dold, *dnew, *round, *front, *arcs;
+    double *acc_o, *acc_n, *coef;
+    uint64_t *sold, *snew;
+};
+
+template <int TS>
+__host__ __device__ constexpr size_t dual_dag_bytes() {
+    DD_CONSTS
+    return (size_t)DD_SLOTS * (6 * 4 + 5 * 8) + (size_t)DD_FRONT * 4 + (size_t)DD_ARCS * 4 + 256;
+}
+
+template <int TS>
+__device__ __forceinline__ DualDag dual_dag_at(char *p) {
+    DD_CONSTS
+    DualDag d;
+    d.acc_o = (double *)p;    p += 8 * DD_SLOTS;
+    d.acc_n = (double *)p;    p += 8 * DD_SLOTS;
+    d.coef = (double *)p;     p += 8 * DD_SLOTS;
+    d.sold = (uint64_t *)p;   p += 8 * DD_SLOTS;
+    d.snew = (uint64_t *)p;   p += 8 * DD_SLOTS;
+    d.key = (int32_t *)p;     p += 4 * DD_SLOTS;
+    d.flags = (int32_t *)p;   p += 4 * DD_SLOTS;
+    d.cnt = (int32_t *)p;     p += 4 * DD_SLOTS;  // successors: old in bits 0-15, new in 16-31
+    d.dold = (int32_t *)p;    p += 4 * DD_SLOTS;
+    d.dnew = (int32_t *)p;    p += 4 * DD_SLOTS;
+    d.round = (int32_t *)p;   p += 4 * DD_SLOTS;
+    d.front = (int32_t *)p;   p += 4 * DD_FRONT;  // slot | memberships to expand << 16
+    d.arcs = (int32_t *)p;                        // tail slot | head slot << 8 | kinds << 16
+    return d;
+}
+
+template <int TS>
+__device__ __forceinline__ int32_t dd_find(const DualDag &d, int32_t x) {
+    DD_CONSTS
+    uint32_t h = ((uint32_t)x * 2654435761u) >> 24;
+    for (int p = 0; p < DD_SLOTS; ++p) {
+        const int32_t slot = (int32_t)((h + (uint32_t)p) & (DD_SLOTS - 1));
+        const int32_t k = d.key[slot];
+        if (k == x) return slot;
+        if (k == -1) return -1;
+    }
+    return -1;
+}
+
+template <int TS>
+__device__ __forceinline__ int32_t dd_slot(const DualDag &d, int32_t x) {
+    DD_CONSTS
+    uint32_t h = ((uint32_t)x * 2654435761u) >> 24;
+    for (int p = 0; p < DD_SLOTS; ++p) {
+        const int32_t slot = (int32_t)((h + (uint32_t)p) & (DD_SLOTS - 1));
+        const int32_t prev = atomicCAS(&d.key[slot], -1, x);
+        if (prev == -1 || prev == x) return slot;
+    }
+    return -1;
+}
+
+// Kahn rounds over the recorded arcs of one of the two sub-DAGs (kind 1: old,
+// 2: new), from its sinks; acc gets delta_B of every member.
+template <int TS>
+__device__ __forceinline__ void dual_kahn(const DualDag &d, const int kind, const int32_t narcs, BlockShared &sh) {
+    DD_CONSTS
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int shift = kind == DF_O ? 0 : 16;
+    double *const acc = kind == DF_O ? d.acc_o : d.acc_n;
+    const uint64_t *const sv = kind == DF_O ? d.sold : d.snew;
+    for (int32_t i = tid; i < DD_SLOTS; i += bs)
+        d.round[i] = (d.key[i] >= 0 && (d.flags[i] & kind) && ((d.cnt[i] >> shift) & 0xffff) == 0) ? 0 : -1;
+    __syncthreads();
+    for (int32_t r = 0;; ++r) {
+        if (tid == 0) sh.progress = 0;
+        __syncthreads();
+        for (int32_t i = tid; i < DD_SLOTS; i += bs) {
+            if (d.round[i] != r) continue;
+            d.coef[i] = (((d.flags[i] & DF_B) ? 1.0 : 0.0) + acc[i]) / (double)sv[i];
+            sh.progress = 1;
+        }
+        __syncthreads();
+        if (sh.progress == 0) break;
+        for (int32_t k = tid; k < narcs; k += bs) {
+            const int32_t e = d.arcs[k];
+            if (!((e >> 16) & kind)) continue;
+            const int32_t sx = (e >> 8) & 0xff;
+            if (d.round[sx] != r) continue;
+            const int32_t sa = e & 0xff;
+            atomicAdd(&acc[sa], (double)sv[sa] * d.coef[sx]);
+            if (((atomicSub(&d.cnt[sa], 1 << shift) >> shift) & 0xffff) == 1) d.round[sa] = r + 1;
+        }
+        __syncthreads();
+    }
+}
+
+template <int TS>
+__device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, const uint64_t *__restrict__ Sold,
+                          const int32_t *__restrict__ xcp, const int32_t *__restrict__ ycp,
+                          const int32_t *__restrict__ ycs, const int32_t *__restrict__ ycw,
+                          const int32_t *__restrict__ Bt, const int32_t *__restrict__ Bd,
+                          const uint64_t *__restrict__ Bs, const int32_t nb, double *out, BlockShared &sh,
+                          const ExpandShared &es, const DualDag &d) {
+    DD_CONSTS
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int32_t i = tid; i < DD_SLOTS; i += bs) {
+        d.key[i] = -1;
+        d.flags[i] = 0;
+        d.cnt[i] = 0;
+        d.acc_o[i] = 0.0;
+        d.acc_n[i] = 0.0;
+    }
+    if (tid == 0) {
+        sh.next = 0;   // frontier entries
+        sh.tail = 0;   // recorded arcs
+        sh.nk = 0;     // vertices
+        sh.ovf = 0;
+    }
+    __syncthreads();
+    // B: roots of both sub-DAGs (of the old one only if t was reachable)
+    for (int32_t i = tid; i < nb; i += bs) {
+        const int32_t t = Bt[i];
+        if (t == s) continue;
+        const int32_t slot = dd_slot<TS>(d, t);
+        const int32_t v = atomicAdd(&sh.nk, 1);
+        const int32_t pos = atomicAdd(&sh.next, 1);
+        if (slot < 0 || v >= DD_CAP || pos >= DD_FRONT) {
+            sh.ovf = 1;
+            continue;
+        }
+        const int32_t dt = Dold[t];
+        const int32_t mem = DF_N | (dt != INF32 ? DF_O : 0);
+        d.flags[slot] = DF_B | mem;
+        d.dold[slot] = dt;
+        d.dnew[slot] = Bd[i];
+        d.sold[slot] = dt != INF32 ? Sold[t] : 0;
+        d.snew[slot] = Bs[i];
+        d.front[pos] = slot | (mem << 16);
+    }
+    __syncthreads();
+    if (sh.ovf) return false;
+    int32_t lo = 0, hi = sh.next;
+    __syncthreads();
+    while (lo < hi) {
+        for (int32_t c = lo; c < hi; c += bs) {
+            const int32_t idx = c + tid;
+            int32_t entry = 0, b0 = 0, deg = 0, olen = 0;
+            if (idx < hi) {
+                entry = d.front[idx];
+                const int32_t x = d.key[entry & 0xffff];
+                b0 = ycp[x];
+                deg = ycp[x + 1] - b0;
+                olen = (entry >> 16) & DF_O ? xcp[x + 1] - xcp[x] : 0;
+            }
+            int32_t total;
+            const int32_t off = block_excl_scan(deg, sh.scan, total);
+            es.off[tid] = off;
+            es.vtx[tid] = entry;
+            es.beg[tid] = b0;
+            es.dx[tid] = olen;
+            __syncthreads();
+            const int32_t nv = min(bs, hi - c);
+            for (int32_t j = tid; j < total; j += bs) {
+                const int32_t i = find_owner(es, nv, j);
+                const int32_t ent = es.vtx[i];
+                const int32_t sx = ent & 0xffff, mem = ent >> 16;
+                const int32_t rel = j - es.off[i];
+                const int32_t e = es.beg[i] + rel;
+                const int32_t a = ycs[e];
+                const int32_t w = ycw[e];
+                const int32_t da_o = Dold[a];
+                int32_t sa = dd_find<TS>(d, a);
+                const int32_t da_n = (sa >= 0 && (d.flags[sa] & DF_B)) ? d.dnew[sa] : da_o;
+                const bool po = (mem & DF_O) && rel < es.dx[i] && da_o != INF32 &&
+                                (int64_t)da_o + w == (int64_t)d.dold[sx];
+                const bool pn = (mem & DF_N) && da_n != INF32 && (int64_t)da_n + w == (int64_t)d.dnew[sx];
+                if (!po && !pn) continue;
+                if (sa < 0) sa = dd_slot<TS>(d, a);
+                const int32_t k = atomicAdd(&sh.tail, 1);
+                if (sa < 0 || k >= DD_ARCS) {
+                    sh.ovf = 1;
+                    continue;
+                }
+                const int32_t kinds = (po ? DF_O : 0) | (pn ? DF_N : 0);
+                d.arcs[k] = sa | (sx << 8) | (kinds << 16);
+                atomicAdd(&d.cnt[sa], (po ? 1 : 0) + (pn ? 1 << 16 : 0));
+                const int32_t old = atomicOr(&d.flags[sa], kinds);
+                const int32_t gained = kinds & ~old;
+                if (!gained) continue;
+                if (!(old & (DF_O | DF_N | DF_B))) {
+                    // first sight of a (not in B): its new values are its old ones
+                    if (atomicAdd(&sh.nk, 1) >= DD_CAP) {
+                        sh.ovf = 1;
+                        continue;
+                    }
+                    d.dold[sa] = da_o;
+                    d.dnew[sa] = da_o;
+                    const uint64_t sg = Sold[a];
+                    d.sold[sa] = sg;
+                    d.snew[sa] = sg;
+                }
+                const int32_t pos = atomicAdd(&sh.next, 1);
+                if (pos >= DD_FRONT) sh.ovf = 1;
+                else d.front[pos] = sa | (gained << 16);
+            }
+            __syncthreads();
+        }
+        const bool ovf = sh.ovf != 0;
+        lo = hi;
+        hi = sh.next;
+        __syncthreads();
+        if (ovf) return false;
+    }
+    const int32_t narcs = sh.tail;
+    dual_kahn<TS>(d, DF_O, narcs, sh);
+    dual_kahn<TS>(d, DF_N, narcs, sh);
+    for (int32_t i = tid; i < DD_SLOTS; i += bs) {
+        const int32_t x = d.key[i];
+        if (x < 0 || x == s) continue;
+        const double diff = d.acc_n[i] - d.acc_o[i];
+        if (diff != 0.0) atomicAdd(&out[x], diff);
+    }
+    __syncthreads();
     return true;
 }
 
@@ -1384,7 +1639,8 @@ __global__ void __launch_bounds__(256) k_rows(const UpdateJob *__restrict__ jobs
                     it.s = s;
                     it.nb = nb;
                     it.off = off;
-                    J.g.dlist[atomicAdd(&ctl->dag_count, 1)] = it;
+                    if (nb >= HEAVY_NB) J.g.dlist[atomicAdd(&ctl->dag_count, 1)] = it;
+                    else J.g.dlist[n - 1 - atomicAdd(&ctl->dag_back, 1)] = it;
                     sh.counter += (unsigned long long)nb;
                 } else {
                     J.g.biglist[atomicAdd(&ctl->big_count, 1)] = s;
@@ -1409,25 +1665,41 @@ __global__ void __launch_bounds__(256) k_rows(const UpdateJob *__restrict__ jobs
 }
 
 // One listed source with its changed targets B (Bt, Bd, Bs; nb of them):
+// both partial dependencies in one traversal in LDS (dual_pass) and then the
+// changed pairs written to D and sigma; or, when the two sub-DAGs do not fit
+// together:
 //   1. old partial dependency over B (E* by head, old row), sign -1,
 //   2. write the changed pairs (only those) to D and sigma,
-//   3. new partial dependency over B (merged E*, new row), sign +1.
-// Small sub-DAGs run in LDS (small_pass), larger ones in the workgroup's slot.
+//   3. new partial dependency over B (merged E*, new row), sign +1,
+// each in LDS (small_pass) when it fits, else in the workgroup's slot.
+template <int TS>
 __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t s, const int32_t *__restrict__ Bt,
                                               const int32_t *__restrict__ Bd, const uint64_t *__restrict__ Bs,
                                               const int32_t nb, const bool lds, int32_t *lds_row, const USlot &u,
                                               BlockShared &sh, const ExpandShared &es, const SmallDag &sd,
-                                              const bool try_small) {
+                                              const DualDag &dd, const bool try_small) {
     const int tid = threadIdx.x, bs = blockDim.x;
     const int32_t n = J.g.n;
     int32_t *const Dg = J.g.D + (size_t)s * n;
     uint64_t *const Sg = J.g.S + (size_t)s * n;
     const int32_t *Drow = lds ? lds_row : Dg;
     double *const bc_delta = J.g.bc_delta;
+    if (try_small &&
+        dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs, nb, bc_delta, sh, es, dd)) {
+        for (int32_t i = tid; i < nb; i += bs) {
+            const int32_t t = Bt[i];
+            const int32_t d = Bd[i];
+            Sg[t] = Bs[i];
+            Dg[t] = d;
+            if (lds) lds_row[t] = d;
+        }
+        __syncthreads();
+        return;
+    }
     // a large B (here 1/16 of the row or more) makes the sub-DAG most of
     // DAG(s): sweep all of E* instead of walking back from B
     const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
-    if (!try_small || !small_pass(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd))
+    if (!try_small || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd))
         restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u, -1.0,
                                bc_delta, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {
@@ -1438,7 +1710,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
         if (lds) lds_row[t] = d;
     }
     __syncthreads();
-    if (!try_small || !small_pass(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
+    if (!try_small || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
         restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb, full, u, 1.0,
                                bc_delta, sh, es);
 }
@@ -1448,13 +1720,16 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
 // (dynamic LDS of 4*lds_cap bytes).  Every workgroup's slot is laid out for
 // the context-wide n_layout (the largest graph), so the zero-kept arrays sit
 // at the same place for every job.
+template <int TS>
 __global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
                                                 char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
                                                 int32_t n_layout, StepPool pool) {
     extern __shared__ __align__(16) char dyn_lds[];
     int32_t *const lds_row = (int32_t *)dyn_lds;
     const ExpandShared es = expand_at(dyn_lds, lds_cap);
-    const SmallDag sd = small_dag_at(dyn_lds + align256((size_t)lds_cap * 4) + align256(XB * (size_t)blockDim.x));
+    char *const table = dyn_lds + align256((size_t)lds_cap * 4) + align256(XB * (size_t)blockDim.x);
+    const SmallDag sd = small_dag_at<TS>(table);
+    const DualDag dd = dual_dag_at<TS>(table);
     __shared__ BlockShared sh;
     const int tid = threadIdx.x, bs = blockDim.x;
     const int njobs = *njobs_p;
@@ -1465,21 +1740,23 @@ __global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jo
         GraphCtl *ctl = J.g.ctl;
         const int32_t n = J.g.n;
         const bool lds = n <= lds_cap;
-        const int32_t count = *(volatile int32_t *)&ctl->dag_count;
+        // heavy sources (front of the list) first, then the others (back)
+        const int32_t front = *(volatile int32_t *)&ctl->dag_count;
+        const int32_t count = front + *(volatile int32_t *)&ctl->dag_back;
         for (;;) {
             __syncthreads();
             if (tid == 0) sh.item = atomicAdd(&ctl->dag_next, 1);
             __syncthreads();
             const int32_t item = sh.item;
             if (item >= count) break;
-            const DItem it = J.g.dlist[item];
+            const DItem it = J.g.dlist[item < front ? item : n - 1 - (item - front)];
             if (lds) {
                 const int32_t *Dg = J.g.D + (size_t)it.s * n;
                 for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
                 __syncthreads();
             }
-            update_source(J, it.s, pool.t + it.off, pool.d + it.off, pool.s + it.off, it.nb, lds, lds_row, u, sh, es,
-                          sd, true);
+            update_source<TS>(J, it.s, pool.t + it.off, pool.d + it.off, pool.s + it.off, it.nb, lds, lds_row, u, sh, es,
+                          sd, dd, true);
         }
     }
 }
@@ -1681,6 +1958,7 @@ __global__ void __launch_bounds__(256) k_commit(const UpdateJob *__restrict__ jo
             c->big_next = 0;
             c->dag_count = 0;
             c->dag_next = 0;
+            c->dag_back = 0;
         }
     }
 }
@@ -1699,6 +1977,7 @@ __global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__res
         c->big_next = 0;
         c->dag_count = 0;
         c->dag_next = 0;
+        c->dag_back = 0;
     }
 }
 

@@ -18,11 +18,12 @@ from paper_1311_2147_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 SCHEDULES = [
-    {"block": 256, "wide_block": 512, "big_b": 512, "wide_stage": 1},
-    {"block": 64, "wide_block": 256, "big_b": 1, "wide_stage": 1},
-    {"block": 128, "wide_block": 1024, "big_b": 1, "wide_stage": 2},
-    {"block": 192, "wide_block": 512, "big_b": 4, "wide_stage": 1},
-    {"block": 256, "wide_block": 1024, "big_b": 1024, "wide_stage": 1},
+    {"block": 256, "wide_block": 512, "big_b": 512, "wide_stage": 1, "table": 256},
+    {"block": 64, "wide_block": 256, "big_b": 1, "wide_stage": 1, "table": 256},
+    {"block": 128, "wide_block": 1024, "big_b": 1, "wide_stage": 2, "table": 128},
+    {"block": 192, "wide_block": 512, "big_b": 4, "wide_stage": 1, "table": 128},
+    {"block": 128, "wide_block": 1024, "big_b": 1024, "wide_stage": 1, "table": 128},
+    {"block": 256, "wide_block": 1024, "big_b": 1024, "wide_stage": 1, "table": 256},
 ]
 
 
@@ -107,7 +108,7 @@ def test_schedule_rejects_out_of_range_values():
     ctx = make_ctx(64, slots=8)
     before = ctx.schedule()
     for bad in ({"block": 96}, {"block": 512}, {"big_b": 2000}, {"wide_block": 128}, {"wide_stage": 3},
-                {"slots": 9}):
+                {"slots": 9}, {"table": 64}, {"table": 512}):
         with pytest.raises(bcinc.BcError) as e:
             ctx.set_schedule(**bad)
         assert e.value.name == "BC_ERR_INVALID_ARG"
@@ -128,7 +129,7 @@ def test_autotune_keeps_graphs_and_sets_a_candidate():
     assert (a.state_hash(), b.state_hash()) == h0
     assert ctx.schedule() == chosen
     assert chosen["block"] in (64, 128, 256) and chosen["wide_block"] in (512, 1024)
-    assert chosen["big_b"] in (512, 1024)
+    assert chosen["big_b"] in (512, 1024) and chosen["table"] in (128, 256)
     # the stream itself, under the chosen schedule
     ups = W.mixed_stream(g1, 10, 30, 43, 0.35, 0.35, 8)
     cur = g1

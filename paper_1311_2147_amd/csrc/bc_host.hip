@@ -124,6 +124,10 @@ struct bc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // second stream (default priority): the wide kernel runs on it beside the
+    // DAG kernel, forked after the row kernel and joined before the E* filter
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     char *scratch = nullptr;
     uint64_t scratch_bytes = 0;
     uint64_t budget = 0;
@@ -429,6 +433,18 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
     } else if (part == 1) {
         hipLaunchKernelGGL(k_rows, dim3(ctx->rows_grid), dim3(256), 0, st, jobs, nj, ctx->big_b, pool);
     } else if (part == 2) {
+        // the wide kernel (deferred sources) and the DAG kernel (listed
+        // sources) touch disjoint rows: the wide one goes first on the side
+        // stream so its few long workgroups start early, the DAG kernel fills
+        // the remaining CUs
+        HIPCHK(hipEventRecord(ctx->fork_ev, st));
+        HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+        hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(ctx->wide_block),
+                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block, 0), ctx->side, jobs, nj, L.wide_base,
+                           L.wide_bytes, L.wide_lds_cap, L.n_layout, L.items_base, L.item_regions);
+        hipLaunchKernelGGL(k_wide_apply, dim3(256), dim3(256), 0, ctx->side, jobs, nj, L.items_base,
+                           L.item_regions, L.n_layout);
+        HIPCHK(hipEventRecord(ctx->join_ev, ctx->side));
         const size_t lds = source_lds_bytes(L.src_lds_cap, ctx->block, ctx->table);
         if (ctx->table == 128)
             hipLaunchKernelGGL(k_source<128>, dim3(L.slots), dim3(ctx->block), lds, st, jobs, nj, L.src_base,
@@ -436,11 +452,7 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
         else
             hipLaunchKernelGGL(k_source<256>, dim3(L.slots), dim3(ctx->block), lds, st, jobs, nj, L.src_base,
                                L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
-        hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(ctx->wide_block),
-                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block, 0), st, jobs, nj, L.wide_base,
-                           L.wide_bytes, L.wide_lds_cap, L.n_layout, L.items_base, L.item_regions);
-        hipLaunchKernelGGL(k_wide_apply, dim3(256), dim3(256), 0, st, jobs, nj, L.items_base, L.item_regions,
-                           L.n_layout);
+        HIPCHK(hipStreamWaitEvent(st, ctx->join_ev, 0));
     } else {
         hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
@@ -842,6 +854,12 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
         if (e != hipSuccess) return bail(e, "hipStreamCreate");
         ctx->own_stream = true;
     }
+    e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(e, "hipStreamCreate");
+    e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(e, "hipEventCreate");
+    e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(e, "hipEventCreate");
     for (int r = 0; r < RING; ++r) {
         e = hipHostMalloc((void **)&ctx->h_jobs[r], sizeof(UpdateJob) * JCAP, hipHostMallocDefault);
         if (e != hipSuccess) return bail(e, "hipHostMalloc");
@@ -981,7 +999,7 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
     for (int table : {256, 128})
         for (int block : {256, 128})
             for (int wide_block : {512, 1024})
-                for (int big_b : {512, 1024}) {
+                for (int big_b : {64, 512}) {
                     if (st) break;
                     bc_schedule c = start;
                     c.block = block;
@@ -1039,6 +1057,9 @@ bc_status bc_destroy(bc_ctx *ctx) {
             if (ctx->tev[r][q]) (void)hipEventDestroy(ctx->tev[r][q]);
     }
     for (auto *g : ctx->graphs) delete g;
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return BC_OK;

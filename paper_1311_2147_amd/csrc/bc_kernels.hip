@@ -1684,7 +1684,10 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     uint64_t *const Sg = J.g.S + (size_t)s * n;
     const int32_t *Drow = lds ? lds_row : Dg;
     double *const bc_delta = J.g.bc_delta;
-    if (try_small &&
+    // an LDS table cannot hold more vertices than 3/4 of its slots: larger B
+    // sets go straight to the slot passes
+    const bool fits = try_small && nb < TS * 3 / 4;
+    if (fits &&
         dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs, nb, bc_delta, sh, es, dd)) {
         for (int32_t i = tid; i < nb; i += bs) {
             const int32_t t = Bt[i];
@@ -1699,7 +1702,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // a large B (here 1/16 of the row or more) makes the sub-DAG most of
     // DAG(s): sweep all of E* instead of walking back from B
     const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
-    if (!try_small || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd))
+    if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd))
         restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u, -1.0,
                                bc_delta, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {
@@ -1710,7 +1713,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
         if (lds) lds_row[t] = d;
     }
     __syncthreads();
-    if (!try_small || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
+    if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
         restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb, full, u, 1.0,
                                bc_delta, sh, es);
 }

@@ -434,24 +434,25 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
         hipLaunchKernelGGL(k_rows, dim3(ctx->rows_grid), dim3(256), 0, st, jobs, nj, ctx->big_b, pool);
     } else if (part == 2) {
         // the wide kernel (deferred sources) and the DAG kernel (listed
-        // sources) touch disjoint rows: the wide one goes first on the side
-        // stream so its few long workgroups start early, the DAG kernel fills
-        // the remaining CUs
+        // sources) touch disjoint rows and run side by side: the wide one
+        // directly behind the row kernel on the main stream, so its few long
+        // workgroups (a whole CU each) start first, the DAG kernel on the
+        // side stream, filling the remaining CUs
         HIPCHK(hipEventRecord(ctx->fork_ev, st));
         HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
         hipLaunchKernelGGL(k_source_wide, dim3(L.wide_slots), dim3(ctx->wide_block),
-                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block, 0), ctx->side, jobs, nj, L.wide_base,
+                           source_lds_bytes(L.wide_lds_cap, ctx->wide_block, 0), st, jobs, nj, L.wide_base,
                            L.wide_bytes, L.wide_lds_cap, L.n_layout, L.items_base, L.item_regions);
-        hipLaunchKernelGGL(k_wide_apply, dim3(256), dim3(256), 0, ctx->side, jobs, nj, L.items_base,
-                           L.item_regions, L.n_layout);
-        HIPCHK(hipEventRecord(ctx->join_ev, ctx->side));
         const size_t lds = source_lds_bytes(L.src_lds_cap, ctx->block, ctx->table);
         if (ctx->table == 128)
-            hipLaunchKernelGGL(k_source<128>, dim3(L.slots), dim3(ctx->block), lds, st, jobs, nj, L.src_base,
+            hipLaunchKernelGGL(k_source<128>, dim3(L.slots), dim3(ctx->block), lds, ctx->side, jobs, nj, L.src_base,
                                L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
         else
-            hipLaunchKernelGGL(k_source<256>, dim3(L.slots), dim3(ctx->block), lds, st, jobs, nj, L.src_base,
+            hipLaunchKernelGGL(k_source<256>, dim3(L.slots), dim3(ctx->block), lds, ctx->side, jobs, nj, L.src_base,
                                L.slot_bytes, L.src_lds_cap, L.n_layout, pool);
+        HIPCHK(hipEventRecord(ctx->join_ev, ctx->side));
+        hipLaunchKernelGGL(k_wide_apply, dim3(256), dim3(256), 0, st, jobs, nj, L.items_base, L.item_regions,
+                           L.n_layout);
         HIPCHK(hipStreamWaitEvent(st, ctx->join_ev, 0));
     } else {
         hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);

@@ -172,21 +172,30 @@ __host__ __device__ inline StaticLayout static_layout(int32_t n) {
     return L;
 }
 
-// Per-workgroup scratch of the DAG kernel's global sub-DAG pass.  outdeg /
-// acc are kept all-zero between sources (each pass clears exactly the
-// entries it used).
+// Per-workgroup scratch of the DAG kernel's global sub-DAG pass: outdeg /
+// acc / kcnt are kept all-zero between sources (each pass clears exactly the
+// entries it used); a record of up to n sub-DAG arcs (ka = tail, kb = head,
+// kr = tails grouped by head, kend = range ends) spares the Kahn rounds the
+// Eq.1 tests.
 struct UpdateLayout {
-    size_t outdeg, acc, sub, q1, q2, total;
+    size_t outdeg, acc, sub, q1, q2, kcnt, kend, ka, kb, kr, total;
+    int64_t kcap;
 };
 
 __host__ __device__ inline UpdateLayout update_layout(int32_t n) {
     UpdateLayout L;
     size_t off = 0;
+    L.kcap = n;
     L.outdeg = off; off += align256(sizeof(int32_t) * (size_t)n);
     L.acc = off;    off += align256(sizeof(double) * (size_t)n);
     L.sub = off;    off += align256(sizeof(int32_t) * (size_t)n);
     L.q1 = off;     off += align256(sizeof(int32_t) * (size_t)n);
     L.q2 = off;     off += align256(sizeof(int32_t) * (size_t)n);
+    L.kcnt = off;   off += align256(sizeof(int32_t) * (size_t)n);
+    L.kend = off;   off += align256(sizeof(int32_t) * (size_t)n);
+    L.ka = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
+    L.kb = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
+    L.kr = off;     off += align256(sizeof(int32_t) * (size_t)L.kcap);
     L.total = off;
     return L;
 }

@@ -524,9 +524,14 @@ __device__ __forceinline__ USlot uslot_at(char *base, int32_t n) {
     u.q2 = (int32_t *)(base + L.q2);
     u.bl_t = u.bl_d = nullptr;
     u.bl_s = nullptr;
-    u.kcnt = u.kend = u.ka = u.kb = u.kr = u.dnew = nullptr;
+    u.kcnt = (int32_t *)(base + L.kcnt);
+    u.kend = (int32_t *)(base + L.kend);
+    u.ka = (int32_t *)(base + L.ka);
+    u.kb = (int32_t *)(base + L.kb);
+    u.kr = (int32_t *)(base + L.kr);
+    u.dnew = nullptr;
     u.snew = nullptr;
-    u.kcap = 0;
+    u.kcap = L.kcap;
     return u;
 }
 
@@ -735,9 +740,12 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
                                 const bool full, const USlot &u, const double sign, double *out, BlockShared &sh,
                                 const ExpandShared &es) {
     const int tid = threadIdx.x, bs = blockDim.x;
+    const int32_t kcap = (int32_t)u.kcap;
     if (tid == 0) {
         sh.next = 0;
         sh.tail = 0;
+        sh.nk = 0;
+        sh.kpos = 0;
     }
     __syncthreads();
     for (int32_t i = tid; i < nB; i += bs) {
@@ -756,13 +764,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
     if (full) {
         // 1. every DAG(s) arc: one more successor of its tail, and (with an
         //    arc record) the arc itself with one more arc into its head
-        if (tid == 0) {
-            sh.nk = 0;
-            sh.kpos = 0;
-        }
-        __syncthreads();
         const int32_t m = cptr[n];
-        const int32_t kcap = (int32_t)u.kcap;
         for (int32_t e0 = tid; e0 < m; e0 += XU * bs) {
             int32_t av[XU], bv[XU], wv[XU];
 #pragma unroll
@@ -852,8 +854,18 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
                         const int32_t da = Drow[a];
                         // one more successor inside the sub-DAG; the first arc
                         // found into a vertex not yet seen adds it to the list
-                        if (da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]])
+                        if (da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]]) {
                             if ((atomicAdd(&u.outdeg[a], 1) & (W_COUNT | W_VIS)) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
+                            if (kcap > 0) {
+                                const int32_t p = atomicAdd(&sh.nk, 1);
+                                if (p < kcap) {
+                                    const int32_t x = es.vtx[iv[k]];
+                                    u.ka[p] = a;
+                                    u.kb[p] = x;
+                                    atomicAdd(&u.kcnt[x], 1);
+                                }
+                            }
+                        }
                     }
                 }
                 __syncthreads();
@@ -863,6 +875,21 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
             __syncthreads();
         }
         nsub = hi;
+        const int32_t nk = sh.nk;
+        rec = kcap > 0 && nk <= kcap;
+        if (rec) {
+            // group the recorded arcs by head (the sub-DAG vertices)
+            for (int32_t i = tid; i < nsub; i += bs) {
+                const int32_t x = u.sub[i];
+                const int32_t c = u.kcnt[x];
+                if (c) u.kend[x] = atomicAdd(&sh.kpos, c);
+            }
+            __syncthreads();
+            for (int32_t p = tid; p < nk; p += bs) u.kr[atomicAdd(&u.kend[u.kb[p]], 1)] = u.ka[p];
+        } else if (kcap > 0) {
+            for (int32_t p = tid; p < kcap; p += bs) u.kcnt[u.kb[p]] = 0;
+        }
+        __syncthreads();
         for (int32_t i = tid; i < nsub; i += bs) {
             const int32_t x = u.sub[i];
             if ((u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
@@ -956,6 +983,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
             const int32_t x = u.sub[i];
             u.outdeg[x] = 0;
             u.acc[x] = 0.0;
+            if (rec) u.kcnt[x] = 0;
         }
     }
     __syncthreads();

@@ -76,7 +76,7 @@ typedef struct {
     void *scratch;          /* device buffer for per-workgroup work areas (caller owns it) */
     uint64_t scratch_bytes; /* its size; see bc_scratch_bytes */
     uint64_t memory_budget; /* admission limit for the sum of graph arenas, 0 = none */
-    int32_t slots;          /* workgroup slots of the DAG kernel and the static pass, 0 = 2048 */
+    int32_t slots;          /* workgroup slots of the DAG kernel and the static pass, 0 = 2560 */
     int32_t block;          /* threads per workgroup of the DAG kernel (64, 128, 192 or 256), 0 = 256 */
 } bc_config;
 
@@ -255,7 +255,7 @@ bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out);
 /* Autotuner of the launch schedule.  reqs[0..cnt) is a sample of requests
  * in bc_submit form on resident graphs (typically updates like the expected
  * stream, drawn for tuning).  For each candidate schedule (table 128 or 256;
- * block 128 or 256; wide_block 512 or 1024; big_b 64 or 512; the other
+ * block 128 or 256; wide_block 512 or 1024; big_b 256 or 768; the other
  * fields as set)
  * the sample runs on fresh device clones of its graphs, twice (the first run
  * also captures the step graphs), and the summed device time of the second

@@ -28,7 +28,7 @@ namespace {
 constexpr int RING = 4;            // job staging slots in flight
 constexpr int JCAP = 256;          // jobs per staging slot
 constexpr size_t MISC_BYTES = 4096;
-constexpr int DEFAULT_SLOTS = 2048; // 8 persistent workgroups per CU of an MI355X
+constexpr int DEFAULT_SLOTS = 2560; // 10 persistent 128-thread workgroups per CU of an MI355X (5 waves per SIMD)
 constexpr int WIDE_SLOTS_MAX = 256; // wide-kernel slots: one per CU
 constexpr int DEFAULT_BLOCK = 256;  // 4 waves per affected source
 constexpr int DEFAULT_WIDE_BLOCK = 512;
@@ -1000,7 +1000,7 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
     for (int table : {256, 128})
         for (int block : {256, 128})
             for (int wide_block : {512, 1024})
-                for (int big_b : {64, 512}) {
+                for (int big_b : {256, 768}) {
                     if (st) break;
                     bc_schedule c = start;
                     c.block = block;

@@ -1750,9 +1750,11 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
 // and run update_source on each.  The row is staged in LDS when n <= lds_cap
 // (dynamic LDS of 4*lds_cap bytes).  Every workgroup's slot is laid out for
 // the context-wide n_layout (the largest graph), so the zero-kept arrays sit
-// at the same place for every job.
+// at the same place for every job.  The work is bound by dependent gathers, so
+// the register budget is held to five waves per SIMD (ten 128-thread
+// workgroups per CU) at the price of a couple of spilled registers.
 template <int TS>
-__global__ void __launch_bounds__(256) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
                                                 char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,
                                                 int32_t n_layout, StepPool pool) {
     extern __shared__ __align__(16) char dyn_lds[];

@@ -39,30 +39,32 @@ constexpr int32_t BIG_B = 512;
 // Sticky status bits of a graph.
 enum : int32_t { ST_SIGMA_OVF = 1, ST_DIST_OVF = 2, ST_ESTAR_CAP = 4 };
 
-// Control words of one graph, resident in device memory.
+// Control words of one graph, resident in device memory.  The counters that
+// many workgroups bump with atomics during a step sit on 256-byte lines of
+// their own: atomics on one line are serialized where the line lives, so
+// counters sharing a line would queue behind each other.
 struct GraphCtl {
     int32_t status;     // sticky ST_* bits
     int32_t a_count;    // |A| of the update in flight (written by the scan)
-    int32_t work_next;  // next item of the persistent per-source kernel
     int32_t max_levels; // deepest Kahn level count seen (statistic)
     int32_t es_m;       // arcs in X (E* by tail, built by the static pass)
     int32_t esc_m;      // arcs in XC (E* by head, kept current)
     int32_t esc_m_tmp;  // arcs in YC (E* by head plus the updated arcs)
     int32_t t_count;    // candidate targets of the update in flight
-    int32_t big_count;  // deferred (large) sources of the update in flight
-    int32_t big_next;   // next deferred source to process
     int32_t big_last;   // deferred sources of the last update (statistic)
-    int32_t dag_count;  // listed sources with many changed targets: dlist[0 .. dag_count)
-    int32_t dag_next;   // next listed source of the DAG kernel
-    int32_t dag_back;   // listed sources with few: dlist[n - dag_back .. n)
-    int32_t pad2;
-    unsigned long long changed_pairs;  // statistic of the last update
     unsigned long long affected_last;  // |A| of the last update
     unsigned long long updates;        // updates applied since load
     unsigned long long affected_total; // sums over all updates since load
     unsigned long long changed_total;
     unsigned long long scan_bytes_last;  // row-scan bytes of the last update (see k_commit)
     unsigned long long scan_bytes_total;
+    alignas(256) int32_t work_next;    // next item of the persistent per-source kernel
+    alignas(256) int32_t dag_count;    // listed sources with many changed targets: dlist[0 .. dag_count)
+    alignas(256) int32_t dag_back;     // listed sources with few: dlist[n - dag_back .. n)
+    alignas(256) int32_t dag_next;     // next listed source of the DAG kernel
+    alignas(256) int32_t big_count;    // deferred (large) sources of the update in flight
+    alignas(256) int32_t big_next;     // next deferred source to process
+    alignas(256) unsigned long long changed_pairs;  // statistic of the last update
 };
 
 // Per-source scalars of the update in flight (Alg 4 output).

@@ -1612,6 +1612,119 @@ __device__ __forceinline__ RowV row_v_of(const UpdateJob &J) {
     return R;
 }
 
+// Rows of an update with at most 64 candidate targets (the candidate list is
+// scanned instead of the rows): each wave takes 64 / g rows at once, a group
+// of g lanes per row (g = the candidate count rounded up to a power of two),
+// one candidate per lane, with no workgroup barriers.  The changed pairs of a
+// row are compacted with a ballot and written to the step's target pool
+// straight from the lanes; the listing rules are those of k_rows, with the
+// pool and list reservations of a wave's rows taken in one atomic each.
+__device__ void rows_few_targets(const UpdateJob &J, const RowV &R, const int32_t count, const int32_t t_count,
+                                 const int32_t cap, const StepPool &pool) {
+    GraphCtl *ctl = J.g.ctl;
+    const int32_t n = J.g.n;
+    const int lane = lane_id();
+    int lpr = 1;
+    while (lpr < t_count) lpr <<= 1;
+    const int rpw = 64 / lpr;
+    const int g = lane / lpr, r = lane - g * lpr;
+    const uint64_t gmask = lpr == 64 ? ~0ull : ((1ull << lpr) - 1);
+    // this lane's candidate and its row-v data, the same for every row
+    const bool has_t = r < t_count;
+    const int32_t t = has_t ? J.g.tlist[r] : 0;
+    const int32_t f_rvd = has_t ? J.g.tl_rvD[r] : INF32;
+    const int32_t f_rvvd = has_t && R.has_out ? J.g.tl_rvvD[r] : INF32;
+    const int32_t rvd = has_t ? R.rvD[t] : INF32;
+    const int32_t rvvd = has_t && R.has_out ? R.rvvD[t] : INF32;
+    bool ovf_s = false, ovf_d = false;
+    int32_t listed_pairs = 0;
+    for (;;) {
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(&ctl->work_next, rpw);
+        base = __shfl(base, 0, 64);
+        if (base >= count) break;
+        const int32_t item = base + g;
+        const bool row_ok = item < count;
+        int32_t s = 0, d = 0;
+        uint64_t sg = 0;
+        bool chg = false;
+        if (row_ok && has_t) {
+            s = J.g.alist[item];
+            const SrcScal sc = J.g.scal[s];
+            const bool same = (sc.flags & 1) != 0;
+            const int32_t *Drow = J.g.D + (size_t)s * n;
+            const int32_t d0 = Drow[t];
+            if (may_change(d0, sc.dv, f_rvd, f_rvvd, !same || sc.hv != 0))
+                chg = pair_update(R, sc, same, t, d0, rvd, rvvd, J.g.S + (size_t)s * n, d, sg, ovf_s, ovf_d);
+        }
+        const uint64_t gm = (__ballot(chg) >> (g * lpr)) & gmask;
+        const int32_t nb = (int32_t)__popcll(gm);
+        // the groups' first lanes (each holds a candidate, so it read s) list
+        // their sources, with one reservation per wave in the pool and in
+        // each end of the list: a wave prefix sum of the pool entries wanted
+        const bool lead = row_ok && r == 0 && nb > 0;
+        const int32_t want = lead && nb <= cap ? nb : 0;
+        int32_t incl = want;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int32_t total = __shfl(incl, 63, 64);
+        int32_t pb_lo = 0, pb_hi = 0;
+        if (lane == 0 && total > 0) {
+            const unsigned long long o = atomicAdd(pool.next, (unsigned long long)total);
+            pb_lo = (int32_t)(o & 0xffffffffull);
+            pb_hi = (int32_t)(o >> 32);
+        }
+        pb_lo = __shfl(pb_lo, 0, 64);
+        pb_hi = __shfl(pb_hi, 0, 64);
+        const unsigned long long pbase = ((unsigned long long)(uint32_t)pb_hi << 32) | (uint32_t)pb_lo;
+        const unsigned long long mine = pbase + (unsigned long long)(incl - want);
+        const bool listed = want > 0 && mine + (unsigned long long)nb <= (unsigned long long)pool.cap;
+        const uint64_t hm = __ballot(listed && nb >= HEAVY_NB), lm = __ballot(listed && nb < HEAVY_NB);
+        const uint64_t dm = __ballot(lead && !listed);
+        int32_t hb = 0, lb = 0, db = 0;
+        if (lane == 0) {
+            if (hm) hb = atomicAdd(&ctl->dag_count, (int32_t)__popcll(hm));
+            if (lm) lb = atomicAdd(&ctl->dag_back, (int32_t)__popcll(lm));
+            if (dm) db = atomicAdd(&ctl->big_count, (int32_t)__popcll(dm));
+        }
+        hb = __shfl(hb, 0, 64);
+        lb = __shfl(lb, 0, 64);
+        db = __shfl(db, 0, 64);
+        if (listed) {
+            DItem it;
+            it.s = s;
+            it.nb = nb;
+            it.off = (int64_t)mine;
+            if (nb >= HEAVY_NB) J.g.dlist[hb + (int32_t)popc_below(hm, lane)] = it;
+            else J.g.dlist[n - 1 - (lb + (int32_t)popc_below(lm, lane))] = it;
+            listed_pairs += nb;
+        } else if (lead) {
+            J.g.biglist[db + (int32_t)popc_below(dm, lane)] = s;
+        }
+        // the group's changed pairs go to its pool entries
+        const int src_lane = g * lpr;
+        const bool g_listed = __shfl((int32_t)listed, src_lane, 64) != 0;
+        const int32_t off_lo = __shfl((int32_t)(mine & 0xffffffffull), src_lane, 64);
+        const int32_t off_hi = __shfl((int32_t)(mine >> 32), src_lane, 64);
+        if (chg && g_listed) {
+            const unsigned long long p = (((unsigned long long)(uint32_t)off_hi << 32) | (uint32_t)off_lo) +
+                                         (unsigned long long)__popcll(gm & ((1ull << r) - 1));
+            pool.t[p] = t;
+            pool.d[p] = d;
+            pool.s[p] = sg;
+        }
+    }
+    if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
+    if (ovf_d) atomicOr(&ctl->status, ST_DIST_OVF);
+    // one statistic update per wave
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) listed_pairs += __shfl_xor(listed_pairs, o, 64);
+    if (lane == 0 && listed_pairs) atomicAdd(&ctl->changed_pairs, (unsigned long long)listed_pairs);
+}
+
 // Row kernel (persistent): workgroups pull affected sources from a device
 // counter and scan their rows (scan_row).  A source's changed targets are
 // collected in LDS; up to big_b of them are copied to the step's target pool
@@ -1636,6 +1749,11 @@ __global__ void __launch_bounds__(256) k_rows(const UpdateJob *__restrict__ jobs
         const RowV R = row_v_of(J);
         const int32_t t_count = *(volatile int32_t *)&ctl->t_count;
         const bool use_tlist = (int64_t)t_count * 8 <= (int64_t)n;
+        if (use_tlist && t_count <= 64) {
+            // a row without candidates cannot change
+            if (t_count > 0) rows_few_targets(J, R, count, t_count, L.cap, pool);
+            continue;
+        }
         if (tid == 0) sh.counter = 0;
         bool ovf_s = false, ovf_d = false;
         for (;;) {

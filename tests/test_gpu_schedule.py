@@ -1,9 +1,9 @@
 """Launch schedules, graph clones and the schedule autotuner on the GPU.
 
 A schedule only maps affected sources onto workgroups, so every schedule must
-reach the same state: D, sigma and the DAGs bit-exact (the state hash covers
-D, sigma and E*), BC within the parity tolerance, and both equal to the
-oracle.  Small deferral thresholds push sources through the wide kernel and
+reach the same state: D and sigma bit-exact (the state hash covers both), BC
+within the parity tolerance, and the first schedule's whole state (D, sigma,
+E*, BC) equal to the oracle's.  Small deferral thresholds push sources through the wide kernel and
 its whole-DAG passes, including the fallback for DAGs with more arcs than
 the pass can record.
 """

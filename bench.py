@@ -230,6 +230,16 @@ def main():
         comparators["full_gpu_recompute_updates_per_s"] = 1.0 / rec_s
         comparators["batched_over_recompute"] = value * rec_s
         log(f"full GPU recompute: {rec_s:.3f}s -> {1 / rec_s:.3f} updates/s")
+        # the same static pass with the distance search over the maintained E*
+        # only (Section 6); the state it reaches is the same
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        grs[0].recompute_estar()
+        ctx.sync()
+        est_s = time.perf_counter() - t0
+        comparators["estar_gpu_recompute_s"] = est_s
+        comparators["batched_over_estar_recompute"] = value * est_s
+        log(f"GPU recompute over E*: {est_s:.3f}s")
 
     # ------------------------------------------------------------------ copy
     # A plain device-to-device copy of 1 GiB: the achievable HBM bandwidth on

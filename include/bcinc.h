@@ -174,6 +174,15 @@ bc_status bc_scores(bc_ctx *ctx, bc_graph_id g, double *out);
  * baseline, Alg 7, and the recovery path after a sticky error). */
 bc_status bc_recompute(bc_ctx *ctx, bc_graph_id g);
 
+/* Static recomputation whose distance search relaxes only the maintained E*
+ * (Section 6, Static-BC, with E* already known: every shortest path lies in
+ * E*, so searching E* instead of E gives the same distances, and the DAGs,
+ * path counts and dependencies over E* follow as in bc_recompute).  The
+ * result equals bc_recompute's.  Synchronises.  A graph that carries a sticky
+ * error (its E* may be incomplete) is left unchanged and its sticky status
+ * returned: recover it with bc_recompute. */
+bc_status bc_recompute_estar(bc_ctx *ctx, bc_graph_id g);
+
 /* Introspection (tests).  All synchronise and write host memory.
  * bc_get_rows: rows s0..s0+cnt-1 of d (int64, INT64_MAX unreachable) and
  *   sigma (uint64); either pointer may be NULL.

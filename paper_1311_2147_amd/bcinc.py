@@ -102,6 +102,7 @@ _SIGS = {
     "bc_sync": (_i32, [_P]),
     "bc_scores": (_i32, [_P, _i32, _P]),
     "bc_recompute": (_i32, [_P, _i32]),
+    "bc_recompute_estar": (_i32, [_P, _i32]),
     "bc_get_rows": (_i32, [_P, _i32, _i32, _i32, _P, _P]),
     "bc_get_dag": (_i32, [_P, _i32, _i32, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_estar": (_i32, [_P, _i32, _P, _P, _P, _i64, ctypes.POINTER(_i64)]),
@@ -311,6 +312,9 @@ class Graph:
 
     def recompute(self):
         self.ctx._check(_lib.bc_recompute(self.ctx.h, self.gid), "bc_recompute")
+
+    def recompute_estar(self):
+        self.ctx._check(_lib.bc_recompute_estar(self.ctx.h, self.gid), "bc_recompute_estar")
 
     def rows(self, s0: int = 0, cnt: int | None = None):
         cnt = self.n - s0 if cnt is None else cnt

@@ -670,11 +670,59 @@ bc_status sticky_to_status(int32_t st) {
 
 // Static pass on the GPU from the mirror's arcs: distances, E*, counts,
 // dependencies and BC (Alg 7 with the DAG taken from E*, Alg 6 steps 2-8).
-bc_status static_pass(bc_ctx *ctx, GraphRec *g) {
-    g->mirror.compact();
+// The maintained E* as an arc list grouped by tail (heads ascending within a
+// tail), read from its by-head copy XC.  Refuses a graph with a sticky error:
+// its E* may be incomplete then.
+bc_status estar_by_tail(bc_ctx *ctx, GraphRec *g, std::vector<int32_t> &hp, std::vector<int32_t> &hd,
+                        std::vector<int32_t> &hw) {
     const int32_t n = g->n;
-    std::vector<int32_t> hp(n + 1), hd(g->mirror.dst), hw(g->mirror.w);
-    for (int32_t i = 0; i <= n; ++i) hp[i] = (int32_t)g->mirror.ptr[i];
+    int32_t status = 0;
+    bc_status st = read_status(ctx, g, &status);
+    if (st) return st;
+    if (status) return fail(ctx, sticky_to_status(status), "the graph carries a sticky error: use bc_recompute");
+    int32_t m = 0;
+    HIPCHK(hipMemcpyAsync(&m, &g->P.ctl->esc_m, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<int32_t> a((size_t)m), b((size_t)m), w((size_t)m);
+    if (m) {
+        HIPCHK(hipMemcpyAsync(a.data(), g->P.xc_src, 4 * (size_t)m, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(b.data(), g->P.xc_dst, 4 * (size_t)m, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(w.data(), g->P.xc_w, 4 * (size_t)m, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    // counting sort by tail; XC is grouped by ascending head, so heads stay
+    // ascending within each tail
+    hp.assign(n + 1, 0);
+    for (int32_t e = 0; e < m; ++e) hp[a[e] + 1]++;
+    for (int32_t i = 0; i < n; ++i) hp[i + 1] += hp[i];
+    hd.resize((size_t)m);
+    hw.resize((size_t)m);
+    std::vector<int32_t> fill(hp.begin(), hp.end() - 1);
+    for (int32_t e = 0; e < m; ++e) {
+        const int32_t q = fill[a[e]]++;
+        hd[q] = b[e];
+        hw[q] = w[e];
+    }
+    return BC_OK;
+}
+
+// Static pass: all-pairs distances, path counts, E* and BC from scratch.
+// over_estar: the distance search relaxes only the maintained E* instead of
+// every arc (Section 6: every shortest path lies in E*, so any arc set
+// containing E* gives the same distances, DAGs, counts and BC).
+bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
+    const int32_t n = g->n;
+    std::vector<int32_t> hp, hd, hw;
+    if (over_estar) {
+        bc_status st = estar_by_tail(ctx, g, hp, hd, hw);
+        if (st) return st;
+    } else {
+        g->mirror.compact();
+        hp.resize(n + 1);
+        hd = g->mirror.dst;
+        hw = g->mirror.w;
+        for (int32_t i = 0; i <= n; ++i) hp[i] = (int32_t)g->mirror.ptr[i];
+    }
     const int64_t m = (int64_t)hd.size();
     if (m > g->arc_cap) return fail(ctx, BC_ERR_CAPACITY, "arc capacity exceeded");
     g->P.arc_m = m;
@@ -1322,6 +1370,12 @@ bc_status bc_recompute(bc_ctx *ctx, bc_graph_id gid) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
     return static_pass(ctx, g);
+}
+
+bc_status bc_recompute_estar(bc_ctx *ctx, bc_graph_id gid) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    return static_pass(ctx, g, true);
 }
 
 bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id gid, int32_t s0, int32_t cnt, int64_t *D, uint64_t *sigma) {

@@ -173,6 +173,62 @@ def test_recompute_equals_incremental_state():
     ctx.close()
 
 
+@pytest.mark.parametrize("kind", ["directed", "complete"])
+def test_estar_recompute_equals_incremental_and_full_recompute(kind):
+    """The static pass restricted to the maintained E* reaches the state of the
+    incremental updates and of the full recompute, and the oracle's."""
+    if kind == "directed":
+        g = W.random_small(300, 0.03, 20, seed=23, directed=True)
+        ups = W.mixed_stream(g, 16, 20, 31, 0.35, 0.35, 8)
+    else:
+        g, ups = W.config3(n=256, n_updates=6, k=16)
+    ctx = make_ctx(g.n, slots=32)
+    gr = ctx.load_graph(g)
+    cur = g
+    for up in ups:
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+    h, bc = gr.state_hash(), gr.scores()
+    a, b, w = gr.estar()
+    before = set(zip(a.tolist(), b.tolist(), w.tolist()))
+    say(f"[{kind}] recompute over E* ({len(before)} arcs of {cur.m if cur.directed else 2 * cur.m})")
+    gr.recompute_estar()
+    assert gr.state_hash() == h
+    assert np.abs(gr.scores() - bc).max() <= 1e-10 * max(1.0, np.abs(bc).max())
+    a, b, w = gr.estar()
+    assert set(zip(a.tolist(), b.tolist(), w.tolist())) == before
+    check_full(gr, cur, f"{kind} after E* recompute")
+    gr.recompute()
+    assert gr.state_hash() == h
+    # and once more over E* right after a full recompute
+    gr.recompute_estar()
+    check_full(gr, cur, f"{kind} after a second E* recompute", estar=False)
+    ctx.close()
+
+
+def test_estar_recompute_refuses_a_graph_with_a_sticky_error():
+    bcinc = _bc()
+    g = W.random_small(64, 0.1, 9, seed=2, directed=True)
+    ctx = make_ctx(64, slots=4)
+    probe = ctx.load_graph(g)
+    mstar = probe.stats()["estar_arcs"]
+    probe.free()
+    gr = ctx.load_graph(g, estar_capacity=mstar)
+    st = W.ArcStore(g)
+    a, b = next((a, b) for a in range(64) for b in range(64) if a != b and st.get(a, b) is None)
+    # an inserted arc of weight 1 is its own shortest path, so E* outgrows
+    # the capacity it was loaded with
+    with pytest.raises(bcinc.BcError) as e:
+        gr.update_edge(a, b, 1)
+        ctx.sync()
+        gr.scores()
+    assert e.value.name == "BC_ERR_ESTAR_CAPACITY"
+    with pytest.raises(bcinc.BcError) as e:
+        gr.recompute_estar()
+    assert e.value.name == "BC_ERR_ESTAR_CAPACITY"
+    ctx.close()
+
+
 def test_sigma_overflow_is_detected_and_recoverable():
     bcinc = _bc()
     ctx = make_ctx(35 * 35, slots=8)

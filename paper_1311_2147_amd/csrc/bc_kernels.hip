@@ -1613,9 +1613,9 @@ __device__ __forceinline__ RowV row_v_of(const UpdateJob &J) {
 }
 
 // Rows of an update with at most 64 candidate targets (the candidate list is
-// scanned instead of the rows): each wave takes 64 / g rows at once, a group
-// of g lanes per row (g = the candidate count rounded up to a power of two),
-// one candidate per lane, with no workgroup barriers.  The changed pairs of a
+// scanned instead of the rows): each wave takes 64 / lpr rows at once, a
+// group of lpr lanes per row (lpr = the candidate count rounded up to a power
+// of two), one candidate per lane, with no workgroup barriers.  The changed pairs of a
 // row are compacted with a ballot and written to the step's target pool
 // straight from the lanes; the listing rules are those of k_rows, with the
 // pool and list reservations of a wave's rows taken in one atomic each.

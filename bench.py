@@ -73,7 +73,8 @@ def main():
     ap.add_argument("--plain", type=int, default=None, help="updates on the plain path (default steps*graphs)")
     ap.add_argument("--latency-requests", type=int, default=160)
     ap.add_argument("--cpu-sources", type=int, default=4096)
-    ap.add_argument("--legs", default="batched,plain,recompute,latency,cpu,copy")
+    ap.add_argument("--legs", default="batched,plain,recompute,latency,single,cpu,copy")
+    ap.add_argument("--single", type=int, default=1000, help="updates of the dedicated single-graph stream")
     ap.add_argument("--tune-sample", type=int, default=8, help="updates per graph in the autotuner's sample (0: no tuning)")
     args = ap.parse_args()
 
@@ -240,6 +241,41 @@ def main():
         comparators["estar_gpu_recompute_s"] = est_s
         comparators["batched_over_estar_recompute"] = value * est_s
         log(f"GPU recompute over E*: {est_s:.3f}s")
+
+    # ---------------------------------------------------------------- single
+    # A dedicated stream of the same mix on one freshly loaded n-vertex graph:
+    # the whole stream in one submit (one job per step, captured steps, tuned
+    # schedule), and the same stream one update at a time on a device clone
+    # taken before it (default schedule, synchronised).  Both must reach the
+    # same D and sigma.
+    if "single" in legs and args.single > 0:
+        S = args.single
+        sstream = W.mixed_stream(graphs[0], S, 1000, W.derive_seed(5, 6000 + gidx[0]), 0.35, 0.35, 16)
+        fresh = ctx.load_graph(graphs[0])
+        twin = fresh.clone()
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.wait(ctx.submit([(fresh, up) for up in sstream]))
+        ctx.sync()
+        s_batched = time.perf_counter() - t0
+        ctx.set_schedule(**default_sched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for up in sstream:
+            twin.update(up)
+            ctx.sync()
+        s_plain = time.perf_counter() - t0
+        ctx.set_schedule(**tuned)
+        same = fresh.state_hash() == twin.state_hash()
+        comparators["single_graph_stream"] = {
+            "updates": S, "batched_updates_per_s": S / s_batched, "plain_updates_per_s": S / s_plain,
+            "batched_over_plain": s_plain / s_batched, "same_state": same}
+        log(f"single-graph stream of {S} updates: batched {S / s_batched:.1f} updates/s, plain {S / s_plain:.1f} "
+            f"updates/s, same state {same}")
+        twin.free()
+        fresh.free()
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------------ copy
     # A plain device-to-device copy of 1 GiB: the achievable HBM bandwidth on

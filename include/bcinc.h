@@ -191,12 +191,17 @@ bc_status bc_recompute_estar(bc_ctx *ctx, bc_graph_id g);
  * bc_get_estar: E* arcs (a, b, w); same capacity rule.
  * bc_get_delta: the dependency row delta_s.(.) of Eq.4 computed by the GPU's
  *   level-ordered accumulation (0 at s itself and at unreachable vertices).
+ * bc_get_preds: the stored DAG(s) predecessor of every vertex x into out[0..n):
+ *   the tail of x's only DAG(s) in-arc (Eq.1 over E*), -2 if x has two or
+ *   more, -1 at x == s and at vertices unreachable from s.  The walks use it
+ *   in place of Eq.1 tests where it names one tail.
  * bc_state_hash: 128-bit hash of D and sigma (order-fixed, bit-exact).
  * bc_get_stats: counters of the last update (see bc_update_stats). */
 bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id g, int32_t s0, int32_t cnt, int64_t *D, uint64_t *sigma);
 bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *a, int32_t *b, int64_t cap, int64_t *cnt);
 bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id g, int32_t *a, int32_t *b, int64_t *w, int64_t cap, int64_t *cnt);
 bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id g, int32_t s, double *out);
+bc_status bc_get_preds(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *out);
 bc_status bc_state_hash(bc_ctx *ctx, bc_graph_id g, uint64_t out[2]);
 
 typedef struct {

@@ -107,6 +107,7 @@ _SIGS = {
     "bc_get_dag": (_i32, [_P, _i32, _i32, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_estar": (_i32, [_P, _i32, _P, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_delta": (_i32, [_P, _i32, _i32, _P]),
+    "bc_get_preds": (_i32, [_P, _i32, _i32, _P]),
     "bc_state_hash": (_i32, [_P, _i32, _P]),
     "bc_get_stats": (_i32, [_P, _i32, ctypes.POINTER(bc_update_stats)]),
     "bc_get_timing": (_i32, [_P, ctypes.POINTER(bc_timing)]),
@@ -347,6 +348,12 @@ class Graph:
     def delta(self, s: int) -> np.ndarray:
         out = np.empty(self.n, dtype=np.float64)
         self.ctx._check(_lib.bc_get_delta(self.ctx.h, self.gid, s, _np_ptr(out)), "bc_get_delta")
+        return out
+
+    def preds(self, s: int) -> np.ndarray:
+        """bc_get_preds: stored DAG(s) predecessor per vertex (-1 none, -2 several)."""
+        out = np.empty(self.n, dtype=np.int32)
+        self.ctx._check(_lib.bc_get_preds(self.ctx.h, self.gid, s, _np_ptr(out)), "bc_get_preds")
         return out
 
     def state_hash(self) -> tuple[int, int]:

@@ -10,6 +10,10 @@ namespace bcinc {
 // Unreachable marker of the int32 distance matrix.  Finite distances stay
 // strictly below it; a finite result that would reach it is an overflow.
 constexpr int32_t INF32 = 0x7fffffff;
+// Stored DAG predecessor of a pair (s, x): the tail of its only DAG(s) in-arc,
+// or one of these.
+constexpr int32_t PRED_NONE = -1;   // x == s or x unreachable from s
+constexpr int32_t PRED_MULTI = -2;  // two or more DAG(s) in-arcs
 
 // Arcs per direction carried inline by one update job (E_i and E_o of
 // Section 4).  Larger vertex updates are split on the host into consecutive
@@ -107,6 +111,7 @@ struct GraphPtrs {
     int32_t directed;
     int64_t es_cap;  // capacity of each E* buffer (arcs)
     int32_t *D;      // n x n distances, INF32 = unreachable
+    int32_t *pred;   // n x n: pred[s*n + x] = the DAG(s) predecessor of x, PRED_NONE or PRED_MULTI
     uint64_t *S;     // n x n path counts
     double *bc_hi, *bc_lo;  // BC as an unevaluated sum hi + lo
     double *bc_delta;       // per-update difference, folded into (hi, lo) at commit

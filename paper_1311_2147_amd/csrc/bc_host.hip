@@ -272,7 +272,7 @@ struct Carve {
 GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *total) {
     Carve c;
     const size_t nn = (size_t)n * (size_t)n;
-    size_t oD = c.take(4 * nn), oS = c.take(8 * nn);
+    size_t oD = c.take(4 * nn), oS = c.take(8 * nn), oPr = c.take(4 * nn);
     size_t ohi = c.take(8 * (size_t)n), olo = c.take(8 * (size_t)n), odl = c.take(8 * (size_t)n);
     size_t oxp = c.take(4 * ((size_t)n + 1)), oxs = c.take(4 * (size_t)es_cap), oxd = c.take(4 * (size_t)es_cap),
            oxw = c.take(4 * (size_t)es_cap);
@@ -296,6 +296,7 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     P.n = n;
     P.es_cap = es_cap;
     P.D = (int32_t *)(base + oD);
+    P.pred = (int32_t *)(base + oPr);
     P.S = (uint64_t *)(base + oS);
     P.bc_hi = (double *)(base + ohi);
     P.bc_lo = (double *)(base + olo);
@@ -1436,6 +1437,14 @@ bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id gid, int32_t s, int32_t *a, int32_
         if (b) HIPCHK(hipMemcpyAsync(b, g->P.yc_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
+    return BC_OK;
+}
+
+bc_status bc_get_preds(bc_ctx *ctx, bc_graph_id gid, int32_t s, int32_t *out) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || s < 0 || s >= g->n || !out) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    HIPCHK(hipMemcpyAsync(out, g->P.pred + (size_t)s * g->n, 4 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return BC_OK;
 }
 

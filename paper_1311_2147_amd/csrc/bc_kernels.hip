@@ -570,21 +570,28 @@ __device__ __forceinline__ USlot wslot_at(char *base, int32_t n) {
 //      delta(a) = sigma_sa * sum_b (1 + delta(b)) / sigma_sb, and BC(a) gets
 //      delta(a) for a != s (Alg 1).
 __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t *Drow, uint64_t *Srow,
-                                const int32_t *ptr, const int32_t *src, const int32_t *dst, const int32_t *wt,
-                                const int32_t m, const SSlot &sl, double *bc_delta, GraphCtl *ctl, BlockShared &sh) {
+                                int32_t *pred, const int32_t *ptr, const int32_t *src, const int32_t *dst,
+                                const int32_t *wt, const int32_t m, const SSlot &sl, double *bc_delta, GraphCtl *ctl,
+                                BlockShared &sh) {
     const int tid = threadIdx.x, bs = blockDim.x;
     for (int32_t i = tid; i < n; i += bs) {
         sl.indeg[i] = 0;
         Srow[i] = (i == s) ? 1ull : 0ull;
+        pred[i] = PRED_NONE;
     }
     __syncthreads();
+    // DAG(s) in-arcs of every vertex (Eq.1 over E*): their count, and the
+    // stored predecessor (the first tail to claim the pair, MULTI after that)
     for (int32_t i = tid; i < m; i += bs) {
         const int32_t a = src[i];
         const int32_t da = Drow[a];
         if (da == INF32) continue;
         const int32_t b = dst[i];
         const int32_t db = Drow[b];
-        if (db != INF32 && (int64_t)da + wt[i] == (int64_t)db) atomicAdd(&sl.indeg[b], 1);
+        if (db != INF32 && (int64_t)da + wt[i] == (int64_t)db) {
+            atomicAdd(&sl.indeg[b], 1);
+            if (atomicCAS(&pred[b], PRED_NONE, a) != PRED_NONE) pred[b] = PRED_MULTI;
+        }
     }
     if (tid == 0) {
         sl.order[0] = s;
@@ -706,6 +713,64 @@ __device__ __forceinline__ void chunk_arcs(const ExpandShared &es, const int32_t
             iv[k] = i;
             ev[k] = es.beg[i] + (j - es.off[i]);
         }
+    }
+}
+
+// Stored predecessors of the changed pairs (s, t), t in Bt[0..nb), from the
+// new row Dnew and the merged E* by head (cptr/csrc/cw): the tail of t's only
+// DAG'(s) in-arc, else PRED_MULTI.  A pair whose distance and count did not
+// change keeps its DAG in-arcs (a new in-arc, or a tail whose own distance or
+// count changed, would change the pair), so these are the only stored
+// predecessors an update changes.  One workgroup; arc-parallel, RU arcs per
+// lane in flight.
+template <int RU>
+__device__ void refresh_preds(const int32_t *__restrict__ Dnew, const int32_t *__restrict__ cptr,
+                              const int32_t *__restrict__ csrc, const int32_t *__restrict__ cw,
+                              const int32_t *__restrict__ Bt, const int32_t nb, int32_t *pred, BlockShared &sh,
+                              const ExpandShared &es) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int32_t i = tid; i < nb; i += bs) pred[Bt[i]] = PRED_NONE;
+    __syncthreads();
+    for (int32_t c = 0; c < nb; c += bs) {
+        const int32_t idx = c + tid;
+        int32_t t = 0, b0 = 0, deg = 0, dt = INF32;
+        if (idx < nb) {
+            t = Bt[idx];
+            b0 = cptr[t];
+            deg = cptr[t + 1] - b0;
+            dt = Dnew[t];
+        }
+        int32_t total;
+        const int32_t off = block_excl_scan(deg, sh.scan, total);
+        es.off[tid] = off;
+        es.vtx[tid] = t;
+        es.beg[tid] = b0;
+        es.dx[tid] = dt;
+        __syncthreads();
+        const int32_t nv = min(bs, nb - c);
+        for (int32_t j0 = tid; j0 < total; j0 += bs * RU) {
+            int32_t iv[RU], av[RU], wv[RU];
+            bool ok[RU];
+#pragma unroll
+            for (int k = 0; k < RU; ++k) {
+                const int32_t j = j0 + k * bs;
+                ok[k] = j < total;
+                iv[k] = ok[k] ? find_owner(es, nv, j) : 0;
+                const int32_t e = es.beg[iv[k]] + (j - es.off[iv[k]]);
+                av[k] = ok[k] ? csrc[e] : 0;
+                wv[k] = ok[k] ? cw[e] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < RU; ++k) {
+                if (!ok[k]) continue;
+                const int32_t da = Dnew[av[k]];
+                if (da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]]) {
+                    int32_t *const p = &pred[es.vtx[iv[k]]];
+                    if (atomicCAS(p, PRED_NONE, av[k]) != PRED_NONE) *p = PRED_MULTI;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1833,22 +1898,14 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // an LDS table cannot hold more vertices than 3/4 of its slots: larger B
     // sets go straight to the slot passes
     const bool fits = try_small && nb < TS * 3 / 4;
-    if (fits &&
-        dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs, nb, bc_delta, sh, es, dd)) {
-        for (int32_t i = tid; i < nb; i += bs) {
-            const int32_t t = Bt[i];
-            const int32_t d = Bd[i];
-            Sg[t] = Bs[i];
-            Dg[t] = d;
-            if (lds) lds_row[t] = d;
-        }
-        __syncthreads();
-        return;
-    }
+    const bool dual =
+        fits && dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs, nb, bc_delta, sh, es,
+                              dd);
     // a large B (here 1/16 of the row or more) makes the sub-DAG most of
     // DAG(s): sweep all of E* instead of walking back from B
     const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
-    if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd))
+    if (!dual &&
+        (!fits || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd)))
         restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u, -1.0,
                                bc_delta, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {
@@ -1859,9 +1916,11 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
         if (lds) lds_row[t] = d;
     }
     __syncthreads();
-    if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
+    if (!dual &&
+        (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd)))
         restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb, full, u, 1.0,
                                bc_delta, sh, es);
+    refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, J.g.pred + (size_t)s * n, sh, es);
 }
 
 // DAG kernel (persistent): workgroups pull the sources the row kernel listed
@@ -2021,6 +2080,11 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                                        ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u,
                                        ph ? 1.0 : -1.0, J.g.bc_delta, sh, es);
             }
+            // the new row of the new pass: in LDS, in the slot (role 1 without
+            // staging) or written back to D (role 2)
+            if (role != 0)
+                refresh_preds<1>(lds ? lds_row : role == 1 ? u.dnew : Dg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, u.bl_t, nb,
+                                 J.g.pred + (size_t)s * n, sh, es);
         }
         if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
         if (ovf_d) atomicOr(&ctl->status, ST_DIST_OVF);
@@ -2233,8 +2297,8 @@ __global__ void __launch_bounds__(1024) k_static(const UpdateJob *__restrict__ j
             __syncthreads();
             Drow = lds_row;
         }
-        static_dag_pass(s, n, Drow, J.g.S + (size_t)s * n, J.g.x_ptr, J.g.x_src, J.g.x_dst, J.g.x_w, ctl->es_m, sl,
-                        J.g.bc_delta, ctl, sh);
+        static_dag_pass(s, n, Drow, J.g.S + (size_t)s * n, J.g.pred + (size_t)s * n, J.g.x_ptr, J.g.x_src, J.g.x_dst,
+                        J.g.x_w, ctl->es_m, sl, J.g.bc_delta, ctl, sh);
     }
 }
 

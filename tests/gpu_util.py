@@ -25,9 +25,34 @@ def dag_set(a, b):
     return set(zip(np.asarray(a).tolist(), np.asarray(b).tolist()))
 
 
+def expected_preds(n, dag_a, dag_b):
+    """Stored-predecessor row from the oracle's DAG(s) arcs: the only tail
+    into x, -2 for two or more, -1 for none."""
+    a = np.asarray(dag_a, dtype=np.int64)
+    b = np.asarray(dag_b, dtype=np.int64)
+    cnt = np.bincount(b, minlength=n)
+    out = np.full(n, -1, dtype=np.int32)
+    one = cnt[b] == 1
+    out[b[one]] = a[one]
+    out[cnt >= 2] = -2
+    return out
+
+
+def check_preds(gr, g, sources, label=""):
+    """Stored predecessors of the listed sources against the oracle's DAGs."""
+    for s in sources:
+        one = oracle.source(g, int(s))
+        want = expected_preds(g.n, one["dag_a"], one["dag_b"])
+        got = gr.preds(int(s))
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, (f"{label}: stored predecessors of source {s} differ at {bad.size} vertices, first "
+                               f"{[(int(x), int(got[x]), int(want[x])) for x in bad[:3]]}")
+
+
 def check_full(gr, g, label="", dags=(), deltas=(), estar=True):
     """Whole-state parity: D and sigma bit-exact, BC within BC_TOL, E* and
-    the DAGs of the listed sources as sets, delta rows within BC_TOL."""
+    the DAGs of the listed sources as sets (and their stored predecessors),
+    delta rows within BC_TOL."""
     ref = oracle.brandes(g, estar=estar)
     D, S = gr.rows()
     assert D.shape == ref["D"].shape
@@ -47,6 +72,7 @@ def check_full(gr, g, label="", dags=(), deltas=(), estar=True):
         one = oracle.source(g, s)
         a, b = gr.dag(s)
         assert dag_set(a, b) == dag_set(one["dag_a"], one["dag_b"]), f"{label}: DAG({s}) differs"
+    check_preds(gr, g, dags, label)
     for s in deltas:
         one = oracle.source(g, s)
         e = bc_err(gr.delta(s), one["delta"])
@@ -55,7 +81,8 @@ def check_full(gr, g, label="", dags=(), deltas=(), estar=True):
 
 
 def check_sampled(gr, g, sources, label=""):
-    """Sampled parity on large graphs: rows of the listed sources."""
+    """Sampled parity on large graphs: rows and stored predecessors of the
+    listed sources."""
     r = oracle.rows(g, sources)
     for i, s in enumerate(sources):
         D, S = gr.rows(int(s), 1)
@@ -63,6 +90,7 @@ def check_sampled(gr, g, sources, label=""):
         assert np.array_equal(S[0], r["sigma"][i]), f"{label}: sigma row {s} differs"
         e = bc_err(gr.delta(int(s)), r["delta"][i])
         assert e <= BC_TOL, f"{label}: delta row {s} error {e}"
+    check_preds(gr, g, sources, label)
 
 
 def make_ctx(n_max, slots=0, **kw):

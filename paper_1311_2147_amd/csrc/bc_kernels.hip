@@ -798,11 +798,12 @@ __device__ void refresh_preds(const int32_t *__restrict__ Dnew, const int32_t *_
 // OUT_ROW: delta_B goes to out[x] (introspection); otherwise
 // out[x] += sign * delta_B(x) for x != s (out = the BC difference).
 template <bool OUT_ROW>
-__device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t *__restrict__ Drow,
+__device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t *__restrict__ Drow,
                                 const uint64_t *__restrict__ Srow, const int32_t *__restrict__ cptr,
                                 const int32_t *__restrict__ csrc, const int32_t *__restrict__ cdst,
                                 const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
-                                const bool full, const USlot &u, const double sign, double *out, BlockShared &sh,
+                                const bool full, const USlot &u, const double sign, double *out,
+                                const int32_t *__restrict__ pred, int32_t *new_pred, BlockShared &sh,
                                 const ExpandShared &es) {
     const int tid = threadIdx.x, bs = blockDim.x;
     const int32_t kcap = (int32_t)u.kcap;
@@ -826,7 +827,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
     __syncthreads();
     int32_t nsub;
     bool rec = false;  // Kahn walks recorded arcs
-    if (full) {
+    if (full && !pred) {
         // 1. every DAG(s) arc: one more successor of its tail, and (with an
         //    arc record) the arc itself with one more arc into its head
         const int32_t m = cptr[n];
@@ -861,38 +862,51 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 }
             }
         }
-        __syncthreads();
-        const int32_t nk = sh.nk;
-        rec = kcap > 0 && nk <= kcap;
-        if (rec) {
-            // group the arcs by head: each head with arcs gets a range
-            // [kend - kcnt, kend); the scatter advances kend from its start
-            for (int32_t x = tid; x < n; x += bs) {
-                const int32_t c = u.kcnt[x];
-                if (c) u.kend[x] = atomicAdd(&sh.kpos, c);
+    } else if (full) {
+        // 1. every reachable vertex's DAG(s) in-arcs: its stored predecessor
+        //    (an unchanged pair keeps its DAG in-arcs), else (a changed target,
+        //    or two or more in-arcs) Eq.1 over its E* in-arcs, below
+        for (int32_t x = tid; x < n; x += bs) {
+            if (x == s || Drow[x] == INF32) continue;
+            const int32_t p = (u.outdeg[x] & W_B) ? PRED_MULTI : pred[x];
+            if (p >= 0) {
+                atomicAdd(&u.outdeg[p], 1);
+                if (kcap > 0) {
+                    const int32_t k = atomicAdd(&sh.nk, 1);
+                    if (k < kcap) {
+                        u.ka[k] = p;
+                        u.kb[k] = x;
+                        atomicAdd(&u.kcnt[x], 1);
+                    }
+                }
+            } else {
+                u.sub[atomicAdd(&sh.next, 1)] = x;
             }
-            __syncthreads();
-            for (int32_t p = tid; p < nk; p += bs) u.kr[atomicAdd(&u.kend[u.kb[p]], 1)] = u.ka[p];
-        } else if (kcap > 0) {
-            // too many arcs to record: Kahn tests E*; undo the counts
-            for (int32_t p = tid; p < kcap; p += bs) u.kcnt[u.kb[p]] = 0;
         }
-        __syncthreads();
-        for (int32_t x = tid; x < n; x += bs)
-            if (Drow[x] != INF32 && (u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
-        nsub = n;
-    } else {
+    }
+    __syncthreads();
+    if (!full || pred) {
+        // 1. backward BFS from B, one level per round, arc-parallel within a
+        //    round (or, for a full pass, one round over the vertices to test).
+        //    A vertex outside B with one stored predecessor contributes that
+        //    arc untested; B vertices (always) and vertices with two or more
+        //    DAG in-arcs test their E* in-arcs by Eq.1.
         int32_t lo = 0, hi = sh.next;
         __syncthreads();
-        // 1. backward BFS, one level per round, arc-parallel within a round
         while (lo < hi) {
             for (int32_t c = lo; c < hi; c += bs) {
                 const int32_t idx = c + tid;
                 int32_t x = 0, b0 = 0, deg = 0, dx = 0;
                 if (idx < hi) {
                     x = u.sub[idx];
-                    b0 = cptr[x];
-                    deg = cptr[x + 1] - b0;
+                    const int32_t p = (pred && !(u.outdeg[x] & W_B)) ? pred[x] : PRED_MULTI;
+                    if (p >= 0) {
+                        b0 = -1 - p;  // the stored arc, marked by a negative start
+                        deg = 1;
+                    } else {
+                        b0 = cptr[x];
+                        deg = cptr[x + 1] - b0;
+                    }
                     dx = Drow[x];
                 }
                 int32_t total;
@@ -909,26 +923,34 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
                     chunk_arcs(es, nv, total, jb, iv, ev, ok);
 #pragma unroll
                     for (int k = 0; k < XU; ++k) {
-                        av[k] = ok[k] ? csrc[ev[k]] : 0;
-                        wv[k] = ok[k] ? cw[ev[k]] : 0;
+                        // a stored arc: its tail from the marked start, weight
+                        // -1 as its mark (E* weights are positive)
+                        const bool one = ok[k] && es.beg[iv[k]] < 0;
+                        av[k] = ok[k] ? (one ? -1 - es.beg[iv[k]] : csrc[ev[k]]) : 0;
+                        wv[k] = one ? -1 : ok[k] ? cw[ev[k]] : 0;
                     }
 #pragma unroll
                     for (int k = 0; k < XU; ++k) {
                         if (!ok[k]) continue;
                         const int32_t a = av[k];
-                        const int32_t da = Drow[a];
+                        bool is_arc = wv[k] < 0;
+                        if (!is_arc) {
+                            const int32_t da = Drow[a];
+                            is_arc = da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]];
+                        }
+                        if (!is_arc) continue;
                         // one more successor inside the sub-DAG; the first arc
                         // found into a vertex not yet seen adds it to the list
-                        if (da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]]) {
-                            if ((atomicAdd(&u.outdeg[a], 1) & (W_COUNT | W_VIS)) == 0) u.sub[atomicAdd(&sh.next, 1)] = a;
-                            if (kcap > 0) {
-                                const int32_t p = atomicAdd(&sh.nk, 1);
-                                if (p < kcap) {
-                                    const int32_t x = es.vtx[iv[k]];
-                                    u.ka[p] = a;
-                                    u.kb[p] = x;
-                                    atomicAdd(&u.kcnt[x], 1);
-                                }
+                        // (a full pass has every vertex already)
+                        if ((atomicAdd(&u.outdeg[a], 1) & (W_COUNT | W_VIS)) == 0 && !full)
+                            u.sub[atomicAdd(&sh.next, 1)] = a;
+                        if (kcap > 0) {
+                            const int32_t p = atomicAdd(&sh.nk, 1);
+                            if (p < kcap) {
+                                const int32_t x = es.vtx[iv[k]];
+                                u.ka[p] = a;
+                                u.kb[p] = x;
+                                atomicAdd(&u.kcnt[x], 1);
                             }
                         }
                     }
@@ -936,10 +958,34 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 __syncthreads();
             }
             lo = hi;
-            hi = sh.next;
+            hi = full ? hi : sh.next;
             __syncthreads();
         }
-        nsub = hi;
+    }
+    if (full) {
+        const int32_t nk = sh.nk;
+        rec = kcap > 0 && nk <= kcap;
+        if (rec) {
+            // group the arcs by head: each head with arcs gets a range
+            // [kend - kcnt, kend); the scatter advances kend from its start
+            for (int32_t x = tid; x < n; x += bs) {
+                const int32_t c = u.kcnt[x];
+                if (c) u.kend[x] = atomicAdd(&sh.kpos, c);
+            }
+            __syncthreads();
+            for (int32_t p = tid; p < nk; p += bs) u.kr[atomicAdd(&u.kend[u.kb[p]], 1)] = u.ka[p];
+        } else if (kcap > 0) {
+            // too many arcs to record: Kahn tests E*; undo the counts
+            for (int32_t p = tid; p < kcap; p += bs) u.kcnt[u.kb[p]] = 0;
+        }
+        __syncthreads();
+        if (tid == 0) sh.tail = 0;
+        __syncthreads();
+        for (int32_t x = tid; x < n; x += bs)
+            if (Drow[x] != INF32 && (u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
+        nsub = n;
+    } else {
+        nsub = sh.next;
         const int32_t nk = sh.nk;
         rec = kcap > 0 && nk <= kcap;
         if (rec) {
@@ -954,6 +1000,8 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
         } else if (kcap > 0) {
             for (int32_t p = tid; p < kcap; p += bs) u.kcnt[u.kb[p]] = 0;
         }
+        __syncthreads();
+        if (tid == 0) sh.tail = 0;
         __syncthreads();
         for (int32_t i = tid; i < nsub; i += bs) {
             const int32_t x = u.sub[i];
@@ -1037,6 +1085,18 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
         qb = tmp;
         __syncthreads();
     }
+    // the new stored predecessors of the changed targets: every E* in-arc of
+    // a B vertex was tested, so its recorded in-arcs are all its DAG in-arcs
+    const bool preds_done = rec && new_pred != nullptr;
+    if (preds_done) {
+        for (int32_t i = tid; i < nB; i += bs) {
+            const int32_t t = Bt[i];
+            if (t == s || Drow[t] == INF32) continue;
+            const int32_t c = u.kcnt[t];
+            new_pred[t] = c == 1 ? u.kr[u.kend[t] - 1] : c == 0 ? PRED_NONE : PRED_MULTI;
+        }
+        __syncthreads();
+    }
     if (full) {
         for (int32_t x = tid; x < n; x += bs) {
             u.outdeg[x] = 0;
@@ -1052,6 +1112,7 @@ __device__ void restricted_pass(const int32_t s, const int32_t n, const int32_t 
         }
     }
     __syncthreads();
+    return preds_done;
 }
 
 // Small sub-DAGs in LDS.  Most sources' sub-DAGs hold a few dozen vertices,
@@ -1272,7 +1333,7 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
 enum : int32_t { DF_O = 1, DF_N = 2, DF_B = 4 };
 
 struct DualDag {
-    int32_t *key, *flags, *cnt, *dold, *dnew, *round, *front, *arcs;
+    int32_t *key, *flags, *cnt, *dold, *dnew, *round, *pr, *ybeg, *ydeg, *xdeg, *front, *arcs;
     double *acc_o, *acc_n, *coef;
     uint64_t *sold, *snew;
 };
@@ -1280,7 +1341,7 @@ struct DualDag {
 template <int TS>
 __host__ __device__ constexpr size_t dual_dag_bytes() {
     DD_CONSTS
-    return (size_t)DD_SLOTS * (6 * 4 + 5 * 8) + (size_t)DD_FRONT * 4 + (size_t)DD_ARCS * 4 + 256;
+    return (size_t)DD_SLOTS * (10 * 4 + 5 * 8) + (size_t)DD_FRONT * 4 + (size_t)DD_ARCS * 4 + 256;
 }
 
 template <int TS>
@@ -1298,7 +1359,12 @@ __device__ __forceinline__ DualDag dual_dag_at(char *p) {
     d.dold = (int32_t *)p;    p += 4 * DD_SLOTS;
     d.dnew = (int32_t *)p;    p += 4 * DD_SLOTS;
     d.round = (int32_t *)p;   p += 4 * DD_SLOTS;
-    d.front = (int32_t *)p;   p += 4 * DD_FRONT;  // slot | memberships to expand << 16
+    d.pr = (int32_t *)p;      p += 4 * DD_SLOTS;  // stored (old) predecessor
+    d.ybeg = (int32_t *)p;    p += 4 * DD_SLOTS;  // changed targets: merged E* in-arcs (start,
+    d.ydeg = (int32_t *)p;    p += 4 * DD_SLOTS;  // count,
+    d.xdeg = (int32_t *)p;    p += 4 * DD_SLOTS;  // and how many are old E* arcs)
+    d.front = (int32_t *)p;   p += 4 * DD_FRONT;  // slot | memberships to expand << 16; after the walk
+                                                  // the new stored predecessor of each changed target
     d.arcs = (int32_t *)p;                        // tail slot | head slot << 8 | kinds << 16
     return d;
 }
@@ -1368,8 +1434,8 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
                           const int32_t *__restrict__ xcp, const int32_t *__restrict__ ycp,
                           const int32_t *__restrict__ ycs, const int32_t *__restrict__ ycw,
                           const int32_t *__restrict__ Bt, const int32_t *__restrict__ Bd,
-                          const uint64_t *__restrict__ Bs, const int32_t nb, double *out, BlockShared &sh,
-                          const ExpandShared &es, const DualDag &d) {
+                          const uint64_t *__restrict__ Bs, const int32_t *__restrict__ pred, const int32_t nb,
+                          double *out, BlockShared &sh, const ExpandShared &es, const DualDag &d) {
     DD_CONSTS
     const int tid = threadIdx.x, bs = blockDim.x;
     for (int32_t i = tid; i < DD_SLOTS; i += bs) {
@@ -1397,36 +1463,69 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
             sh.ovf = 1;
             continue;
         }
+        // everything the walk reads of t, in one round trip
         const int32_t dt = Dold[t];
+        const uint64_t st = Sold[t];
+        const int32_t pt = pred[t];
+        const int32_t yb = ycp[t], ye = ycp[t + 1], xb = xcp[t], xe = xcp[t + 1];
         const int32_t mem = DF_N | (dt != INF32 ? DF_O : 0);
         d.flags[slot] = DF_B | mem;
         d.dold[slot] = dt;
         d.dnew[slot] = Bd[i];
-        d.sold[slot] = dt != INF32 ? Sold[t] : 0;
+        d.sold[slot] = dt != INF32 ? st : 0;
         d.snew[slot] = Bs[i];
+        d.pr[slot] = pt;
+        d.ybeg[slot] = yb;
+        d.ydeg[slot] = ye - yb;
+        d.xdeg[slot] = xe - xb;
         d.front[pos] = slot | (mem << 16);
     }
     __syncthreads();
     if (sh.ovf) return false;
     int32_t lo = 0, hi = sh.next;
     __syncthreads();
+    // per frontier entry: its stored old predecessor and how many of its
+    // merged in-arcs are tested (the rest of its work items: the stored arc)
+    int32_t *const ex_pred = (int32_t *)es.val, *const ex_test = ex_pred + bs;
     while (lo < hi) {
         for (int32_t c = lo; c < hi; c += bs) {
             const int32_t idx = c + tid;
-            int32_t entry = 0, b0 = 0, deg = 0, olen = 0;
+            int32_t entry = 0, b0 = 0, cnt = 0, ntest = 0, olen = 0, pr = PRED_NONE;
             if (idx < hi) {
                 entry = d.front[idx];
-                const int32_t x = d.key[entry & 0xffff];
-                b0 = ycp[x];
-                deg = ycp[x + 1] - b0;
-                olen = (entry >> 16) & DF_O ? xcp[x + 1] - xcp[x] : 0;
+                const int32_t sl = entry & 0xffff, mem = entry >> 16;
+                const int32_t x = d.key[sl];
+                if (x != s) {
+                    pr = d.pr[sl];
+                    if (d.flags[sl] & DF_B) {
+                        // a changed target: its new DAG in-arcs by Eq.1 over the
+                        // merged E*; its old ones from the stored predecessor,
+                        // or by Eq.1 over the old E* arcs where two or more
+                        b0 = d.ybeg[sl];
+                        ntest = d.ydeg[sl];
+                        olen = ((mem & DF_O) && pr < 0) ? d.xdeg[sl] : 0;
+                        cnt = ntest + (((mem & DF_O) && pr >= 0) ? 1 : 0);
+                    } else if (pr >= 0) {
+                        // an unchanged pair keeps its DAG in-arcs: its one
+                        // stored predecessor serves both memberships
+                        cnt = 1;
+                    } else {
+                        // two or more DAG in-arcs: Eq.1 over E*
+                        b0 = ycp[x];
+                        ntest = ycp[x + 1] - b0;
+                        olen = (mem & DF_O) ? xcp[x + 1] - xcp[x] : 0;
+                        cnt = ntest;
+                    }
+                }
             }
             int32_t total;
-            const int32_t off = block_excl_scan(deg, sh.scan, total);
+            const int32_t off = block_excl_scan(cnt, sh.scan, total);
             es.off[tid] = off;
             es.vtx[tid] = entry;
             es.beg[tid] = b0;
             es.dx[tid] = olen;
+            ex_pred[tid] = pr;
+            ex_test[tid] = ntest;
             __syncthreads();
             const int32_t nv = min(bs, hi - c);
             for (int32_t j = tid; j < total; j += bs) {
@@ -1434,25 +1533,41 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
                 const int32_t ent = es.vtx[i];
                 const int32_t sx = ent & 0xffff, mem = ent >> 16;
                 const int32_t rel = j - es.off[i];
-                const int32_t e = es.beg[i] + rel;
-                const int32_t a = ycs[e];
-                const int32_t w = ycw[e];
-                const int32_t da_o = Dold[a];
-                int32_t sa = dd_find<TS>(d, a);
-                const int32_t da_n = (sa >= 0 && (d.flags[sa] & DF_B)) ? d.dnew[sa] : da_o;
-                const bool po = (mem & DF_O) && rel < es.dx[i] && da_o != INF32 &&
-                                (int64_t)da_o + w == (int64_t)d.dold[sx];
-                const bool pn = (mem & DF_N) && da_n != INF32 && (int64_t)da_n + w == (int64_t)d.dnew[sx];
-                if (!po && !pn) continue;
+                int32_t a, da_o, pa, sa, kinds;
+                uint64_t sg;
+                if (rel < ex_test[i]) {
+                    const int32_t e = es.beg[i] + rel;
+                    a = ycs[e];
+                    const int32_t w = ycw[e];
+                    // with the distance, what a first sight of a needs
+                    da_o = Dold[a];
+                    sg = Sold[a];
+                    pa = pred[a];
+                    sa = dd_find<TS>(d, a);
+                    const int32_t da_n = (sa >= 0 && (d.flags[sa] & DF_B)) ? d.dnew[sa] : da_o;
+                    const bool po = (mem & DF_O) && rel < es.dx[i] && da_o != INF32 &&
+                                    (int64_t)da_o + w == (int64_t)d.dold[sx];
+                    const bool pn = (mem & DF_N) && da_n != INF32 && (int64_t)da_n + w == (int64_t)d.dnew[sx];
+                    if (!po && !pn) continue;
+                    kinds = (po ? DF_O : 0) | (pn ? DF_N : 0);
+                } else {
+                    // the stored predecessor: old membership only for a
+                    // changed target, both of the unchanged one's otherwise
+                    a = ex_pred[i];
+                    da_o = Dold[a];
+                    sg = Sold[a];
+                    pa = pred[a];
+                    sa = dd_find<TS>(d, a);
+                    kinds = (d.flags[sx] & DF_B) ? DF_O : (mem & (DF_O | DF_N));
+                }
                 if (sa < 0) sa = dd_slot<TS>(d, a);
                 const int32_t k = atomicAdd(&sh.tail, 1);
                 if (sa < 0 || k >= DD_ARCS) {
                     sh.ovf = 1;
                     continue;
                 }
-                const int32_t kinds = (po ? DF_O : 0) | (pn ? DF_N : 0);
                 d.arcs[k] = sa | (sx << 8) | (kinds << 16);
-                atomicAdd(&d.cnt[sa], (po ? 1 : 0) + (pn ? 1 << 16 : 0));
+                atomicAdd(&d.cnt[sa], ((kinds & DF_O) ? 1 : 0) + ((kinds & DF_N) ? 1 << 16 : 0));
                 const int32_t old = atomicOr(&d.flags[sa], kinds);
                 const int32_t gained = kinds & ~old;
                 if (!gained) continue;
@@ -1464,9 +1579,9 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
                     }
                     d.dold[sa] = da_o;
                     d.dnew[sa] = da_o;
-                    const uint64_t sg = Sold[a];
                     d.sold[sa] = sg;
                     d.snew[sa] = sg;
+                    d.pr[sa] = pa;
                 }
                 const int32_t pos = atomicAdd(&sh.next, 1);
                 if (pos >= DD_FRONT) sh.ovf = 1;
@@ -1481,6 +1596,23 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
         if (ovf) return false;
     }
     const int32_t narcs = sh.tail;
+    // the new stored predecessor of each changed target: its only recorded
+    // new-DAG in-arc (every new in-arc of a changed target was tested and
+    // recorded when it was expanded), else MULTI
+    for (int32_t i = tid; i < DD_SLOTS; i += bs) d.round[i] = 0;
+    __syncthreads();
+    for (int32_t k = tid; k < narcs; k += bs) {
+        const int32_t e = d.arcs[k];
+        if (!((e >> 16) & DF_N)) continue;
+        const int32_t sx = (e >> 8) & 0xff;
+        if (!(d.flags[sx] & DF_B)) continue;
+        if (atomicAdd(&d.round[sx], 1) == 0) d.front[sx] = d.key[e & 0xff];
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < DD_SLOTS; i += bs)
+        if (d.key[i] >= 0 && (d.flags[i] & DF_B) && d.round[i] != 1)
+            d.front[i] = d.round[i] == 0 ? PRED_NONE : PRED_MULTI;
+    __syncthreads();
     dual_kahn<TS>(d, DF_O, narcs, sh);
     dual_kahn<TS>(d, DF_N, narcs, sh);
     for (int32_t i = tid; i < DD_SLOTS; i += bs) {
@@ -1898,29 +2030,37 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // an LDS table cannot hold more vertices than 3/4 of its slots: larger B
     // sets go straight to the slot passes
     const bool fits = try_small && nb < TS * 3 / 4;
-    const bool dual =
-        fits && dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs, nb, bc_delta, sh, es,
-                              dd);
+    int32_t *const pred_row = J.g.pred + (size_t)s * n;
+    const bool dual = fits && dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs,
+                                            pred_row, nb, bc_delta, sh, es, dd);
     // a large B (here 1/16 of the row or more) makes the sub-DAG most of
-    // DAG(s): sweep all of E* instead of walking back from B
+    // DAG(s): take every vertex's DAG in-arcs instead of walking back from B
     const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
     if (!dual &&
         (!fits || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd)))
         restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u, -1.0,
-                               bc_delta, sh, es);
+                               bc_delta, pred_row, nullptr, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {
         const int32_t t = Bt[i];
         const int32_t d = Bd[i];
         Sg[t] = Bs[i];
         Dg[t] = d;
         if (lds) lds_row[t] = d;
+        if (dual) {
+            // the union walk found the changed targets' new predecessors
+            const int32_t sl = dd_find<TS>(dd, t);
+            if (sl >= 0) pred_row[t] = dd.front[sl];
+        }
     }
     __syncthreads();
-    if (!dual &&
-        (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd)))
-        restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb, full, u, 1.0,
-                               bc_delta, sh, es);
-    refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, J.g.pred + (size_t)s * n, sh, es);
+    if (dual) return;
+    // the new pass reads the stored predecessors of unchanged pairs only, so
+    // it may write the changed targets' new ones from its arc record
+    bool preds_done = false;
+    if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
+        preds_done = restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb, full,
+                                            u, 1.0, bc_delta, pred_row, pred_row, sh, es);
+    if (!preds_done) refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, pred_row, sh, es);
 }
 
 // DAG kernel (persistent): workgroups pull the sources the row kernel listed
@@ -2045,6 +2185,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
             if (nb == 0) continue;
             if (role != 1 && tid == 0) sh.counter += (unsigned long long)nb;
             const bool full = (int64_t)nb * 16 >= (int64_t)n;
+            bool preds_done = false;
             // phase 0: old pass (roles 0 and 2); phase 1: new pass (roles 1 and 2)
             for (int ph = role == 1 ? 1 : 0; ph <= (role == 0 ? 0 : 1); ++ph) {
                 const int32_t *Dr = lds ? lds_row : Dg;
@@ -2076,13 +2217,17 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                     }
                     __syncthreads();
                 }
-                restricted_pass<false>(s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
-                                       ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u,
-                                       ph ? 1.0 : -1.0, J.g.bc_delta, sh, es);
+                // B vertices are always tested, so the old pass of a source never
+                // reads a stored predecessor that its new pass (another
+                // workgroup, at the same time) rewrites
+                preds_done = restricted_pass<false>(
+                    s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
+                    ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u, ph ? 1.0 : -1.0,
+                    J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr, sh, es);
             }
             // the new row of the new pass: in LDS, in the slot (role 1 without
             // staging) or written back to D (role 2)
-            if (role != 0)
+            if (role != 0 && !preds_done)
                 refresh_preds<1>(lds ? lds_row : role == 1 ? u.dnew : Dg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, u.bl_t, nb,
                                  J.g.pred + (size_t)s * n, sh, es);
         }
@@ -2335,8 +2480,7 @@ __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict_
     if (lds) Drow = lds_row;
     __syncthreads();
     restricted_pass<true>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, u.bl_t,
-                          sh.nb, true, u, 1.0,
-                          out_row, sh, es);
+                          sh.nb, true, u, 1.0, out_row, nullptr, nullptr, sh, es);
 }
 
 // Arcs of DAG(s): the predicate of Eq.1 over E*.

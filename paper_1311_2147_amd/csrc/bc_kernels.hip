@@ -699,11 +699,12 @@ __device__ __forceinline__ int32_t find_owner(const ExpandShared &es, int32_t nv
 // Arcs jb .. jb+XU-1 of an expansion chunk of nv vertices and total arcs:
 // for each, the owning chunk entry iv and the arc id ev (ok false past the
 // end).  One binary search, then a forward walk (the arcs are consecutive).
+template <int U>
 __device__ __forceinline__ void chunk_arcs(const ExpandShared &es, const int32_t nv, const int32_t total,
-                                           const int32_t jb, int32_t (&iv)[XU], int32_t (&ev)[XU], bool (&ok)[XU]) {
+                                           const int32_t jb, int32_t (&iv)[U], int32_t (&ev)[U], bool (&ok)[U]) {
     int32_t i = find_owner(es, nv, jb);
 #pragma unroll
-    for (int k = 0; k < XU; ++k) {
+    for (int k = 0; k < U; ++k) {
         const int32_t j = jb + k;
         ok[k] = j < total;
         iv[k] = 0;
@@ -797,7 +798,7 @@ __device__ void refresh_preds(const int32_t *__restrict__ Dnew, const int32_t *_
 // the whole accumulation; both give the same BC).
 // OUT_ROW: delta_B goes to out[x] (introspection); otherwise
 // out[x] += sign * delta_B(x) for x != s (out = the BC difference).
-template <bool OUT_ROW>
+template <bool OUT_ROW, int RU>
 __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t *__restrict__ Drow,
                                 const uint64_t *__restrict__ Srow, const int32_t *__restrict__ cptr,
                                 const int32_t *__restrict__ csrc, const int32_t *__restrict__ cdst,
@@ -831,10 +832,10 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         // 1. every DAG(s) arc: one more successor of its tail, and (with an
         //    arc record) the arc itself with one more arc into its head
         const int32_t m = cptr[n];
-        for (int32_t e0 = tid; e0 < m; e0 += XU * bs) {
-            int32_t av[XU], bv[XU], wv[XU];
+        for (int32_t e0 = tid; e0 < m; e0 += RU * bs) {
+            int32_t av[RU], bv[RU], wv[RU];
 #pragma unroll
-            for (int k = 0; k < XU; ++k) {
+            for (int k = 0; k < RU; ++k) {
                 const int32_t e = e0 + k * bs;
                 av[k] = 0;
                 bv[k] = 0;
@@ -846,7 +847,7 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 }
             }
 #pragma unroll
-            for (int k = 0; k < XU; ++k) {
+            for (int k = 0; k < RU; ++k) {
                 if (e0 + k * bs >= m) continue;
                 const int32_t da = Drow[av[k]];
                 if (da != INF32 && (int64_t)da + wv[k] == (int64_t)Drow[bv[k]]) {
@@ -917,12 +918,12 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 es.dx[tid] = dx;
                 __syncthreads();
                 const int32_t nv = min(bs, hi - c);
-                for (int32_t jb = tid * XU; jb < total; jb += bs * XU) {
-                    int32_t iv[XU], ev[XU], av[XU], wv[XU];
-                    bool ok[XU];
+                for (int32_t jb = tid * RU; jb < total; jb += bs * RU) {
+                    int32_t iv[RU], ev[RU], av[RU], wv[RU];
+                    bool ok[RU];
                     chunk_arcs(es, nv, total, jb, iv, ev, ok);
 #pragma unroll
-                    for (int k = 0; k < XU; ++k) {
+                    for (int k = 0; k < RU; ++k) {
                         // a stored arc: its tail from the marked start, weight
                         // -1 as its mark (E* weights are positive)
                         const bool one = ok[k] && es.beg[iv[k]] < 0;
@@ -930,7 +931,7 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                         wv[k] = one ? -1 : ok[k] ? cw[ev[k]] : 0;
                     }
 #pragma unroll
-                    for (int k = 0; k < XU; ++k) {
+                    for (int k = 0; k < RU; ++k) {
                         if (!ok[k]) continue;
                         const int32_t a = av[k];
                         bool is_arc = wv[k] < 0;
@@ -1046,18 +1047,18 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
             es.val[tid] = coef;
             __syncthreads();
             const int32_t nv = min(bs, qn - c);
-            for (int32_t jb = tid * XU; jb < total; jb += bs * XU) {
-                int32_t iv[XU], ev[XU], av[XU], wv[XU];
-                bool ok[XU];
+            for (int32_t jb = tid * RU; jb < total; jb += bs * RU) {
+                int32_t iv[RU], ev[RU], av[RU], wv[RU];
+                bool ok[RU];
                 chunk_arcs(es, nv, total, jb, iv, ev, ok);
 #pragma unroll
-                for (int k = 0; k < XU; ++k) {
+                for (int k = 0; k < RU; ++k) {
                     av[k] = ok[k] ? (rec ? u.kr[ev[k]] : csrc[ev[k]]) : 0;
                     wv[k] = (ok[k] && !rec) ? cw[ev[k]] : 0;
                 }
-                double cf[XU];
+                double cf[RU];
 #pragma unroll
-                for (int k = 0; k < XU; ++k) {
+                for (int k = 0; k < RU; ++k) {
                     cf[k] = 0.0;
                     if (!ok[k]) continue;
                     if (!rec) {
@@ -1066,11 +1067,11 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                     }
                     if (ok[k]) cf[k] = es.val[iv[k]];
                 }
-                uint64_t sa[XU];
+                uint64_t sa[RU];
 #pragma unroll
-                for (int k = 0; k < XU; ++k) sa[k] = (ok[k] && cf[k] != 0.0) ? Srow[av[k]] : 0;
+                for (int k = 0; k < RU; ++k) sa[k] = (ok[k] && cf[k] != 0.0) ? Srow[av[k]] : 0;
 #pragma unroll
-                for (int k = 0; k < XU; ++k) {
+                for (int k = 0; k < RU; ++k) {
                     if (!ok[k]) continue;
                     const int32_t a = av[k];
                     if (cf[k] != 0.0) atomicAdd(&u.acc[a], (double)sa[k] * cf[k]);
@@ -2038,8 +2039,8 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
     if (!dual &&
         (!fits || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd)))
-        restricted_pass<false>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u, -1.0,
-                               bc_delta, pred_row, nullptr, sh, es);
+        restricted_pass<false, XU>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u,
+                                   -1.0, bc_delta, pred_row, nullptr, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {
         const int32_t t = Bt[i];
         const int32_t d = Bd[i];
@@ -2058,8 +2059,8 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // it may write the changed targets' new ones from its arc record
     bool preds_done = false;
     if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
-        preds_done = restricted_pass<false>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb, full,
-                                            u, 1.0, bc_delta, pred_row, pred_row, sh, es);
+        preds_done = restricted_pass<false, XU>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb,
+                                                full, u, 1.0, bc_delta, pred_row, pred_row, sh, es);
     if (!preds_done) refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, pred_row, sh, es);
 }
 
@@ -2220,7 +2221,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                 // B vertices are always tested, so the old pass of a source never
                 // reads a stored predecessor that its new pass (another
                 // workgroup, at the same time) rewrites
-                preds_done = restricted_pass<false>(
+                preds_done = restricted_pass<false, 2>(
                     s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
                     ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u, ph ? 1.0 : -1.0,
                     J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr, sh, es);
@@ -2479,7 +2480,7 @@ __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict_
     }
     if (lds) Drow = lds_row;
     __syncthreads();
-    restricted_pass<true>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, u.bl_t,
+    restricted_pass<true, XU>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, u.bl_t,
                           sh.nb, true, u, 1.0, out_row, nullptr, nullptr, sh, es);
 }
 

@@ -269,7 +269,7 @@ bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out);
 /* Autotuner of the launch schedule.  reqs[0..cnt) is a sample of requests
  * in bc_submit form on resident graphs (typically updates like the expected
  * stream, drawn for tuning).  For each candidate schedule (table 128 or 256;
- * block 128 or 256; wide_block 512 or 1024; big_b 256 or 768; the other
+ * block 128 or 256; wide_block 512 or 1024; big_b 512 or 1024; the other
  * fields as set)
  * the sample runs on fresh device clones of its graphs, twice (the first run
  * also captures the step graphs), and the summed device time of the second

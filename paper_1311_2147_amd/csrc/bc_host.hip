@@ -1049,7 +1049,7 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
     for (int table : {256, 128})
         for (int block : {256, 128})
             for (int wide_block : {512, 1024})
-                for (int big_b : {256, 768}) {
+                for (int big_b : {512, 1024}) {
                     if (st) break;
                     bc_schedule c = start;
                     c.block = block;

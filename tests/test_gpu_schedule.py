@@ -129,7 +129,7 @@ def test_autotune_keeps_graphs_and_sets_a_candidate():
     assert (a.state_hash(), b.state_hash()) == h0
     assert ctx.schedule() == chosen
     assert chosen["block"] in (64, 128, 256) and chosen["wide_block"] in (512, 1024)
-    assert chosen["big_b"] in (256, 768) and chosen["table"] in (128, 256)
+    assert chosen["big_b"] in (512, 1024) and chosen["table"] in (128, 256)
     # the stream itself, under the chosen schedule
     ups = W.mixed_stream(g1, 10, 30, 43, 0.35, 0.35, 8)
     cur = g1

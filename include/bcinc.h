@@ -25,8 +25,9 @@
  *     graphs), so BC counts ordered pairs (twice the unordered convention).
  *   - Unreachable pairs have distance INT64_MAX and sigma 0 at this boundary;
  *     they contribute nothing to BC.
- *   - Device state per graph is D (int32, n x n, row-major) and sigma (uint64,
- *     n x n): 12 bytes per pair.  A finite distance that would reach 2^31-1
+ *   - Device state per graph is D (int32, n x n, row-major), sigma (uint64,
+ *     n x n) and the stored DAG predecessor of every pair (int32, n x n; see
+ *     bc_get_preds): 16 bytes per pair.  A finite distance that would reach 2^31-1
  *     raises BC_ERR_DIST_OVERFLOW; a path count above 2^64-1 raises
  *     BC_ERR_SIGMA_OVERFLOW.  Both are sticky: the graph answers with that
  *     error until bc_recompute or bc_free_graph.

@@ -1015,13 +1015,44 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
     int32_t *qa = u.q1, *qb = u.q2;
     __syncthreads();
     while (qn > 0) {
-        if (tid == 0) sh.tail = 0;
-        for (int32_t c = 0; c < qn; c += bs) {
+        if (tid == 0) {
+            sh.tail = 0;
+            sh.kpos = 0;
+        }
+        __syncthreads();
+        int32_t nslow = qn;
+        const int32_t *slow = qa;
+        if (pred) {
+            // a vertex outside B whose only DAG in-arc comes from its stored
+            // predecessor p: sigma_sx = sigma_sp, so p receives acc(x) itself
+            // (no counts, no arc list, no scan).  The others go to the back
+            // of the next round's queue (the two never meet: a vertex queued
+            // for the next round is not in this one) for the general step.
+            for (int32_t idx = tid; idx < qn; idx += bs) {
+                const int32_t x = qa[idx];
+                const int32_t p = (u.outdeg[x] & W_B) ? PRED_MULTI : pred[x];
+                if (p < 0) {
+                    qb[n - 1 - atomicAdd(&sh.kpos, 1)] = x;
+                    continue;
+                }
+                const double ax = u.acc[x];
+                if (ax != 0.0) {
+                    if (OUT_ROW) out[x] = ax;
+                    else atomicAdd(&out[x], sign * ax);
+                    atomicAdd(&u.acc[p], ax);
+                }
+                if ((atomicSub(&u.outdeg[p], 1) & W_COUNT) == 1) qb[atomicAdd(&sh.tail, 1)] = p;
+            }
+            __syncthreads();
+            nslow = sh.kpos;
+            slow = qb + n - nslow;
+        }
+        for (int32_t c = 0; c < nslow; c += bs) {
             const int32_t idx = c + tid;
             int32_t x = 0, b0 = 0, deg = 0, dx = 0;
             double coef = 0.0;
-            if (idx < qn) {
-                x = qa[idx];
+            if (idx < nslow) {
+                x = slow[idx];
                 const double ax = u.acc[x];
                 if (x != s && ax != 0.0) {
                     if (OUT_ROW) out[x] = ax;
@@ -1046,7 +1077,7 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
             es.dx[tid] = dx;
             es.val[tid] = coef;
             __syncthreads();
-            const int32_t nv = min(bs, qn - c);
+            const int32_t nv = min(bs, nslow - c);
             for (int32_t jb = tid * RU; jb < total; jb += bs * RU) {
                 int32_t iv[RU], ev[RU], av[RU], wv[RU];
                 bool ok[RU];

@@ -828,7 +828,10 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
     __syncthreads();
     int32_t nsub;
     bool rec = false;  // Kahn walks recorded arcs
-    if (full && !pred) {
+    // a full pass over a B that covers much of the row tests most in-arcs
+    // anyway: one coalesced sweep over E* serves it better than the list
+    const bool sweep = full && (!pred || (int64_t)nB * 4 >= (int64_t)n);
+    if (sweep) {
         // 1. every DAG(s) arc: one more successor of its tail, and (with an
         //    arc record) the arc itself with one more arc into its head
         const int32_t m = cptr[n];
@@ -886,7 +889,7 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         }
     }
     __syncthreads();
-    if (!full || pred) {
+    if (!sweep) {
         // 1. backward BFS from B, one level per round, arc-parallel within a
         //    round (or, for a full pass, one round over the vertices to test).
         //    A vertex outside B with one stored predecessor contributes that
@@ -1022,25 +1025,29 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         __syncthreads();
         int32_t nslow = qn;
         const int32_t *slow = qa;
-        if (pred) {
-            // a vertex outside B whose only DAG in-arc comes from its stored
-            // predecessor p: sigma_sx = sigma_sp, so p receives acc(x) itself
-            // (no counts, no arc list, no scan).  The others go to the back
-            // of the next round's queue (the two never meet: a vertex queued
-            // for the next round is not in this one) for the general step.
+        if (pred || rec) {
+            // a vertex with one DAG in-arc (a, x): sigma_sx = sigma_sa, so a
+            // receives [x in B] + acc(x) itself (no count, no scan).  Its
+            // tail is the stored predecessor for a vertex outside B, else
+            // the one recorded arc.  The others go to the back of the next
+            // round's queue (the two never meet: a vertex queued for the
+            // next round is not in this one) for the general step.
             for (int32_t idx = tid; idx < qn; idx += bs) {
                 const int32_t x = qa[idx];
-                const int32_t p = (u.outdeg[x] & W_B) ? PRED_MULTI : pred[x];
+                const bool in_b = (u.outdeg[x] & W_B) != 0;
+                int32_t p = (pred && !in_b) ? pred[x] : PRED_MULTI;
+                if (p < 0 && rec && u.kcnt[x] == 1) p = u.kr[u.kend[x] - 1];
                 if (p < 0) {
                     qb[n - 1 - atomicAdd(&sh.kpos, 1)] = x;
                     continue;
                 }
                 const double ax = u.acc[x];
-                if (ax != 0.0) {
+                if (x != s && ax != 0.0) {
                     if (OUT_ROW) out[x] = ax;
                     else atomicAdd(&out[x], sign * ax);
-                    atomicAdd(&u.acc[p], ax);
                 }
+                const double push = (in_b ? 1.0 : 0.0) + ax;
+                if (push != 0.0) atomicAdd(&u.acc[p], push);
                 if ((atomicSub(&u.outdeg[p], 1) & W_COUNT) == 1) qb[atomicAdd(&sh.tail, 1)] = p;
             }
             __syncthreads();

@@ -1372,7 +1372,7 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
 enum : int32_t { DF_O = 1, DF_N = 2, DF_B = 4 };
 
 struct DualDag {
-    int32_t *key, *flags, *cnt, *dold, *dnew, *round, *pr, *ybeg, *ydeg, *xdeg, *front, *arcs;
+    int32_t *key, *flags, *cnt, *dold, *dnew, *round, *pr, *ybeg, *ydeg, *xdeg, *front, *slow, *arcs;
     double *acc_o, *acc_n, *coef;
     uint64_t *sold, *snew;
 };
@@ -1380,7 +1380,7 @@ struct DualDag {
 template <int TS>
 __host__ __device__ constexpr size_t dual_dag_bytes() {
     DD_CONSTS
-    return (size_t)DD_SLOTS * (10 * 4 + 5 * 8) + (size_t)DD_FRONT * 4 + (size_t)DD_ARCS * 4 + 256;
+    return (size_t)DD_SLOTS * (10 * 4 + 5 * 8) + (size_t)DD_FRONT * 8 + (size_t)DD_ARCS * 4 + 256;
 }
 
 template <int TS>
@@ -1404,6 +1404,7 @@ __device__ __forceinline__ DualDag dual_dag_at(char *p) {
     d.xdeg = (int32_t *)p;    p += 4 * DD_SLOTS;  // and how many are old E* arcs)
     d.front = (int32_t *)p;   p += 4 * DD_FRONT;  // slot | memberships to expand << 16; after the walk
                                                   // the new stored predecessor of each changed target
+    d.slow = (int32_t *)p;    p += 4 * DD_FRONT;  // a level's entries for the general expansion
     d.arcs = (int32_t *)p;                        // tail slot | head slot << 8 | kinds << 16
     return d;
 }
@@ -1431,6 +1432,43 @@ __device__ __forceinline__ int32_t dd_slot(const DualDag &d, int32_t x) {
         if (prev == -1 || prev == x) return slot;
     }
     return -1;
+}
+
+// One arc (a, x) of the union walk (x in slot sx; kinds: the sub-DAGs it is
+// in; sa: a's slot or -1): recorded, a's successor counts and memberships
+// raised, and a queued for the next level with any membership it gains.
+// da_o, sg, pa: d(s,a), sigma_sa and a's stored predecessor, kept at a's
+// first sight (a not in B: its new values are its old ones).
+template <int TS>
+__device__ __forceinline__ void dd_add_arc(const DualDag &d, BlockShared &sh, const int32_t a, int32_t sa,
+                                           const int32_t sx, const int32_t kinds, const int32_t da_o, const uint64_t sg,
+                                           const int32_t pa) {
+    DD_CONSTS
+    if (sa < 0) sa = dd_slot<TS>(d, a);
+    const int32_t k = atomicAdd(&sh.tail, 1);
+    if (sa < 0 || k >= DD_ARCS) {
+        sh.ovf = 1;
+        return;
+    }
+    d.arcs[k] = sa | (sx << 8) | (kinds << 16);
+    atomicAdd(&d.cnt[sa], ((kinds & DF_O) ? 1 : 0) + ((kinds & DF_N) ? 1 << 16 : 0));
+    const int32_t old = atomicOr(&d.flags[sa], kinds);
+    const int32_t gained = kinds & ~old;
+    if (!gained) return;
+    if (!(old & (DF_O | DF_N | DF_B))) {
+        if (atomicAdd(&sh.nk, 1) >= DD_CAP) {
+            sh.ovf = 1;
+            return;
+        }
+        d.dold[sa] = da_o;
+        d.dnew[sa] = da_o;
+        d.sold[sa] = sg;
+        d.snew[sa] = sg;
+        d.pr[sa] = pa;
+    }
+    const int32_t pos = atomicAdd(&sh.next, 1);
+    if (pos >= DD_FRONT) sh.ovf = 1;
+    else d.front[pos] = sa | (gained << 16);
 }
 
 // Kahn rounds over the recorded arcs of one of the two sub-DAGs (kind 1: old,
@@ -1523,38 +1561,54 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
     if (sh.ovf) return false;
     int32_t lo = 0, hi = sh.next;
     __syncthreads();
-    // per frontier entry: its stored old predecessor and how many of its
+    // per general entry: its stored old predecessor and how many of its
     // merged in-arcs are tested (the rest of its work items: the stored arc)
     int32_t *const ex_pred = (int32_t *)es.val, *const ex_test = ex_pred + bs;
     while (lo < hi) {
-        for (int32_t c = lo; c < hi; c += bs) {
+        if (tid == 0) sh.kpos = 0;
+        __syncthreads();
+        // an unchanged vertex with one stored predecessor: that arc, at
+        // once, for both memberships (an unchanged pair keeps its DAG
+        // in-arcs); the others to the level's general list
+        for (int32_t idx = lo + tid; idx < hi; idx += bs) {
+            const int32_t entry = d.front[idx];
+            const int32_t sl = entry & 0xffff;
+            if (d.key[sl] == s) continue;
+            const int32_t pr = d.pr[sl];
+            if ((d.flags[sl] & DF_B) || pr < 0) {
+                d.slow[atomicAdd(&sh.kpos, 1)] = entry;
+                continue;
+            }
+            // with the distance, what a first sight of the tail needs
+            const int32_t da_o = Dold[pr];
+            const uint64_t sg = Sold[pr];
+            const int32_t pa = pred[pr];
+            dd_add_arc<TS>(d, sh, pr, dd_find<TS>(d, pr), sl, (entry >> 16) & (DF_O | DF_N), da_o, sg, pa);
+        }
+        __syncthreads();
+        const int32_t nslow = sh.kpos;
+        for (int32_t c = 0; c < nslow; c += bs) {
             const int32_t idx = c + tid;
             int32_t entry = 0, b0 = 0, cnt = 0, ntest = 0, olen = 0, pr = PRED_NONE;
-            if (idx < hi) {
-                entry = d.front[idx];
+            if (idx < nslow) {
+                entry = d.slow[idx];
                 const int32_t sl = entry & 0xffff, mem = entry >> 16;
                 const int32_t x = d.key[sl];
-                if (x != s) {
-                    pr = d.pr[sl];
-                    if (d.flags[sl] & DF_B) {
-                        // a changed target: its new DAG in-arcs by Eq.1 over the
-                        // merged E*; its old ones from the stored predecessor,
-                        // or by Eq.1 over the old E* arcs where two or more
-                        b0 = d.ybeg[sl];
-                        ntest = d.ydeg[sl];
-                        olen = ((mem & DF_O) && pr < 0) ? d.xdeg[sl] : 0;
-                        cnt = ntest + (((mem & DF_O) && pr >= 0) ? 1 : 0);
-                    } else if (pr >= 0) {
-                        // an unchanged pair keeps its DAG in-arcs: its one
-                        // stored predecessor serves both memberships
-                        cnt = 1;
-                    } else {
-                        // two or more DAG in-arcs: Eq.1 over E*
-                        b0 = ycp[x];
-                        ntest = ycp[x + 1] - b0;
-                        olen = (mem & DF_O) ? xcp[x + 1] - xcp[x] : 0;
-                        cnt = ntest;
-                    }
+                pr = d.pr[sl];
+                if (d.flags[sl] & DF_B) {
+                    // a changed target: its new DAG in-arcs by Eq.1 over the
+                    // merged E*; its old ones from the stored predecessor, or
+                    // by Eq.1 over the old E* arcs where two or more
+                    b0 = d.ybeg[sl];
+                    ntest = d.ydeg[sl];
+                    olen = ((mem & DF_O) && pr < 0) ? d.xdeg[sl] : 0;
+                    cnt = ntest + (((mem & DF_O) && pr >= 0) ? 1 : 0);
+                } else {
+                    // two or more DAG in-arcs: Eq.1 over E*
+                    b0 = ycp[x];
+                    ntest = ycp[x + 1] - b0;
+                    olen = (mem & DF_O) ? xcp[x + 1] - xcp[x] : 0;
+                    cnt = ntest;
                 }
             }
             int32_t total;
@@ -1566,7 +1620,7 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
             ex_pred[tid] = pr;
             ex_test[tid] = ntest;
             __syncthreads();
-            const int32_t nv = min(bs, hi - c);
+            const int32_t nv = min(bs, nslow - c);
             for (int32_t j = tid; j < total; j += bs) {
                 const int32_t i = find_owner(es, nv, j);
                 const int32_t ent = es.vtx[i];
@@ -1590,41 +1644,16 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
                     if (!po && !pn) continue;
                     kinds = (po ? DF_O : 0) | (pn ? DF_N : 0);
                 } else {
-                    // the stored predecessor: old membership only for a
-                    // changed target, both of the unchanged one's otherwise
+                    // the stored predecessor of a changed target: old
+                    // membership only
                     a = ex_pred[i];
                     da_o = Dold[a];
                     sg = Sold[a];
                     pa = pred[a];
                     sa = dd_find<TS>(d, a);
-                    kinds = (d.flags[sx] & DF_B) ? DF_O : (mem & (DF_O | DF_N));
+                    kinds = DF_O;
                 }
-                if (sa < 0) sa = dd_slot<TS>(d, a);
-                const int32_t k = atomicAdd(&sh.tail, 1);
-                if (sa < 0 || k >= DD_ARCS) {
-                    sh.ovf = 1;
-                    continue;
-                }
-                d.arcs[k] = sa | (sx << 8) | (kinds << 16);
-                atomicAdd(&d.cnt[sa], ((kinds & DF_O) ? 1 : 0) + ((kinds & DF_N) ? 1 << 16 : 0));
-                const int32_t old = atomicOr(&d.flags[sa], kinds);
-                const int32_t gained = kinds & ~old;
-                if (!gained) continue;
-                if (!(old & (DF_O | DF_N | DF_B))) {
-                    // first sight of a (not in B): its new values are its old ones
-                    if (atomicAdd(&sh.nk, 1) >= DD_CAP) {
-                        sh.ovf = 1;
-                        continue;
-                    }
-                    d.dold[sa] = da_o;
-                    d.dnew[sa] = da_o;
-                    d.sold[sa] = sg;
-                    d.snew[sa] = sg;
-                    d.pr[sa] = pa;
-                }
-                const int32_t pos = atomicAdd(&sh.next, 1);
-                if (pos >= DD_FRONT) sh.ovf = 1;
-                else d.front[pos] = sa | (gained << 16);
+                dd_add_arc<TS>(d, sh, a, sa, sx, kinds, da_o, sg, pa);
             }
             __syncthreads();
         }

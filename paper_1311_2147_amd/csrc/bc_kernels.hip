@@ -898,19 +898,38 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         int32_t lo = 0, hi = sh.next;
         __syncthreads();
         while (lo < hi) {
-            for (int32_t c = lo; c < hi; c += bs) {
+            if (tid == 0) sh.head = 0;
+            __syncthreads();
+            // the stored arcs first, one lane per vertex; the vertices that
+            // test E* in-arcs go to the level's general list (the Kahn queue,
+            // idle until the walk ends)
+            for (int32_t idx = lo + tid; idx < hi; idx += bs) {
+                const int32_t x = u.sub[idx];
+                const int32_t p = (pred && !(u.outdeg[x] & W_B)) ? pred[x] : PRED_MULTI;
+                if (p < 0) {
+                    u.q1[atomicAdd(&sh.head, 1)] = x;
+                    continue;
+                }
+                if ((atomicAdd(&u.outdeg[p], 1) & (W_COUNT | W_VIS)) == 0 && !full)
+                    u.sub[atomicAdd(&sh.next, 1)] = p;
+                if (kcap > 0) {
+                    const int32_t k = atomicAdd(&sh.nk, 1);
+                    if (k < kcap) {
+                        u.ka[k] = p;
+                        u.kb[k] = x;
+                        atomicAdd(&u.kcnt[x], 1);
+                    }
+                }
+            }
+            __syncthreads();
+            const int32_t nslow = sh.head;
+            for (int32_t c = 0; c < nslow; c += bs) {
                 const int32_t idx = c + tid;
                 int32_t x = 0, b0 = 0, deg = 0, dx = 0;
-                if (idx < hi) {
-                    x = u.sub[idx];
-                    const int32_t p = (pred && !(u.outdeg[x] & W_B)) ? pred[x] : PRED_MULTI;
-                    if (p >= 0) {
-                        b0 = -1 - p;  // the stored arc, marked by a negative start
-                        deg = 1;
-                    } else {
-                        b0 = cptr[x];
-                        deg = cptr[x + 1] - b0;
-                    }
+                if (idx < nslow) {
+                    x = u.q1[idx];
+                    b0 = cptr[x];
+                    deg = cptr[x + 1] - b0;
                     dx = Drow[x];
                 }
                 int32_t total;
@@ -920,29 +939,22 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 es.beg[tid] = b0;
                 es.dx[tid] = dx;
                 __syncthreads();
-                const int32_t nv = min(bs, hi - c);
+                const int32_t nv = min(bs, nslow - c);
                 for (int32_t jb = tid * RU; jb < total; jb += bs * RU) {
                     int32_t iv[RU], ev[RU], av[RU], wv[RU];
                     bool ok[RU];
                     chunk_arcs(es, nv, total, jb, iv, ev, ok);
 #pragma unroll
                     for (int k = 0; k < RU; ++k) {
-                        // a stored arc: its tail from the marked start, weight
-                        // -1 as its mark (E* weights are positive)
-                        const bool one = ok[k] && es.beg[iv[k]] < 0;
-                        av[k] = ok[k] ? (one ? -1 - es.beg[iv[k]] : csrc[ev[k]]) : 0;
-                        wv[k] = one ? -1 : ok[k] ? cw[ev[k]] : 0;
+                        av[k] = ok[k] ? csrc[ev[k]] : 0;
+                        wv[k] = ok[k] ? cw[ev[k]] : 0;
                     }
 #pragma unroll
                     for (int k = 0; k < RU; ++k) {
                         if (!ok[k]) continue;
                         const int32_t a = av[k];
-                        bool is_arc = wv[k] < 0;
-                        if (!is_arc) {
-                            const int32_t da = Drow[a];
-                            is_arc = da != INF32 && (int64_t)da + wv[k] == (int64_t)es.dx[iv[k]];
-                        }
-                        if (!is_arc) continue;
+                        const int32_t da = Drow[a];
+                        if (da == INF32 || (int64_t)da + wv[k] != (int64_t)es.dx[iv[k]]) continue;
                         // one more successor inside the sub-DAG; the first arc
                         // found into a vertex not yet seen adds it to the list
                         // (a full pass has every vertex already)

@@ -2116,8 +2116,10 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // a large B (here 1/16 of the row or more) makes the sub-DAG most of
     // DAG(s): take every vertex's DAG in-arcs instead of walking back from B
     const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
-    if (!dual &&
-        (!fits || !small_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_w, Bt, nb, -1.0, bc_delta, sh, es, sd)))
+    // when the union outgrew the table it is mostly the old sub-DAG that did:
+    // the old pass goes straight to the slot (it follows stored
+    // predecessors), the new one tries the LDS table first
+    if (!dual)
         restricted_pass<false, XU>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u,
                                    -1.0, bc_delta, pred_row, nullptr, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {

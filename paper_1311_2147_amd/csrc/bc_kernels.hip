@@ -1235,12 +1235,37 @@ __device__ __forceinline__ int32_t sd_slot(const SmallDag &d, int32_t x, bool &i
 // The partial dependency of restricted_pass with all per-vertex state in
 // LDS.  Returns false (and leaves global memory untouched) if the sub-DAG
 // does not fit.
+// One arc (a, x) of the LDS walk (x in slot sxv, da = d(s,a)): recorded,
+// a's successor count raised, and a queued at its first sight.
+template <int TS>
+__device__ __forceinline__ void sd_add_arc(const SmallDag &d, BlockShared &sh, const int32_t a, const int32_t sxv,
+                                           const int32_t da, const uint64_t *__restrict__ Srow) {
+    SD_CONSTS
+    bool ins;
+    const int32_t sa = sd_slot<TS>(d, a, ins);
+    const int32_t k = atomicAdd(&sh.tail, 1);
+    if (sa < 0 || k >= SD_ARCS) {
+        sh.ovf = 1;
+        return;
+    }
+    d.arc_a[k] = (int16_t)sa;
+    d.arc_x[k] = (int16_t)sxv;
+    atomicAdd(&d.outdeg[sa], 1);
+    if ((atomicOr(&d.flags[sa], F_VIS) & F_VIS) == 0) {
+        d.dval[sa] = da;
+        d.sval[sa] = Srow[a];
+        const int32_t pos = atomicAdd(&sh.next, 1);
+        if (pos >= SD_CAP) sh.ovf = 1;
+        else d.sub[pos] = (int16_t)sa;
+    }
+}
+
 template <int TS>
 __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Srow,
                            const int32_t *__restrict__ cptr, const int32_t *__restrict__ csrc,
                            const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
-                           const double sign, double *out, BlockShared &sh, const ExpandShared &es,
-                           const SmallDag &d) {
+                           const double sign, double *out, const int32_t *__restrict__ pred, BlockShared &sh,
+                           const ExpandShared &es, const SmallDag &d) {
     SD_CONSTS
     const int tid = threadIdx.x, bs = blockDim.x;
     for (int32_t i = tid; i < SD_SLOTS; i += bs) {
@@ -1277,11 +1302,28 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
     int32_t lo = 0, hi = sh.next;
     __syncthreads();
     while (lo < hi) {
-        for (int32_t c = lo; c < hi; c += bs) {
+        if (tid == 0) sh.head = 0;
+        __syncthreads();
+        // a vertex outside B with one stored predecessor: that arc, at once;
+        // the others (their E* in-arcs tested) listed in d.round, idle
+        // until the accumulation
+        for (int32_t idx = lo + tid; idx < hi; idx += bs) {
+            const int32_t sx = d.sub[idx];
+            const int32_t x = d.key[sx];
+            const int32_t p = (pred && !(d.flags[sx] & F_B)) ? pred[x] : PRED_MULTI;
+            if (p < 0) {
+                d.round[atomicAdd(&sh.head, 1)] = sx;
+                continue;
+            }
+            sd_add_arc<TS>(d, sh, p, sx, Drow[p], Srow);
+        }
+        __syncthreads();
+        const int32_t nslow = sh.head;
+        for (int32_t c = 0; c < nslow; c += bs) {
             const int32_t idx = c + tid;
             int32_t sx = 0, b0 = 0, deg = 0;
-            if (idx < hi) {
-                sx = d.sub[idx];
+            if (idx < nslow) {
+                sx = d.round[idx];
                 const int32_t x = d.key[sx];
                 b0 = cptr[x];
                 deg = cptr[x + 1] - b0;
@@ -1292,32 +1334,14 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
             es.vtx[tid] = sx;
             es.beg[tid] = b0;
             __syncthreads();
-            const int32_t nv = min(bs, hi - c);
+            const int32_t nv = min(bs, nslow - c);
             for (int32_t j = tid; j < total; j += bs) {
                 const int32_t i = find_owner(es, nv, j);
                 const int32_t sxv = es.vtx[i];
                 const int32_t e = es.beg[i] + (j - es.off[i]);
                 const int32_t a = csrc[e];
                 const int32_t da = Drow[a];
-                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)d.dval[sxv]) {
-                    bool ins;
-                    const int32_t sa = sd_slot<TS>(d, a, ins);
-                    const int32_t k = atomicAdd(&sh.tail, 1);
-                    if (sa < 0 || k >= SD_ARCS) {
-                        sh.ovf = 1;
-                        continue;
-                    }
-                    d.arc_a[k] = (int16_t)sa;
-                    d.arc_x[k] = (int16_t)sxv;
-                    atomicAdd(&d.outdeg[sa], 1);
-                    if ((atomicOr(&d.flags[sa], F_VIS) & F_VIS) == 0) {
-                        d.dval[sa] = da;
-                        d.sval[sa] = Srow[a];
-                        const int32_t pos = atomicAdd(&sh.next, 1);
-                        if (pos >= SD_CAP) sh.ovf = 1;
-                        else d.sub[pos] = (int16_t)sa;
-                    }
-                }
+                if (da != INF32 && (int64_t)da + cw[e] == (int64_t)d.dval[sxv]) sd_add_arc<TS>(d, sh, a, sxv, da, Srow);
             }
             __syncthreads();
         }
@@ -1328,6 +1352,8 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
         if (ovf) return false;
     }
     const int32_t nsub = hi, narcs = sh.tail;
+    for (int32_t i = tid; i < SD_SLOTS; i += bs) d.round[i] = -1;
+    __syncthreads();
     // Kahn from the sinks over the recorded arcs, all in LDS.  Round r makes
     // final the vertices whose successors all became final before r.
     for (int32_t i = tid; i < nsub; i += bs) {
@@ -2139,7 +2165,8 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // the new pass reads the stored predecessors of unchanged pairs only, so
     // it may write the changed targets' new ones from its arc record
     bool preds_done = false;
-    if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, sh, es, sd))
+    if (!fits ||
+        !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, pred_row, sh, es, sd))
         preds_done = restricted_pass<false, XU>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb,
                                                 full, u, 1.0, bc_delta, pred_row, pred_row, sh, es);
     if (!preds_done) refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, pred_row, sh, es);

@@ -97,8 +97,8 @@ def test_clone_is_an_independent_copy():
         b.update(up)
         cur = W.apply_update(cur, up)
     assert a.state_hash() == h_a
-    check_full(b, cur, "clone after updates")
-    check_full(a, W.apply_update(g, ups[0]), "original after clone updates")
+    check_full(b, cur, "clone after updates", dags=(0, 7, 64))
+    check_full(a, W.apply_update(g, ups[0]), "original after clone updates", dags=(0, 7, 64))
     ctx.close()
 
 

@@ -804,8 +804,8 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                                 const int32_t *__restrict__ csrc, const int32_t *__restrict__ cdst,
                                 const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
                                 const bool full, const USlot &u, const double sign, double *out,
-                                const int32_t *__restrict__ pred, int32_t *new_pred, BlockShared &sh,
-                                const ExpandShared &es) {
+                                const int32_t *__restrict__ pred, int32_t *new_pred, const bool b_pred,
+                                BlockShared &sh, const ExpandShared &es) {
     const int tid = threadIdx.x, bs = blockDim.x;
     const int32_t kcap = (int32_t)u.kcap;
     if (tid == 0) {
@@ -889,12 +889,106 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         }
     }
     __syncthreads();
-    if (!sweep) {
-        // 1. backward BFS from B, one level per round, arc-parallel within a
-        //    round (or, for a full pass, one round over the vertices to test).
-        //    A vertex outside B with one stored predecessor contributes that
-        //    arc untested; B vertices (always) and vertices with two or more
-        //    DAG in-arcs test their E* in-arcs by Eq.1.
+    if (!sweep && !full) {
+        // 1. backward walk from B.  A lane follows a chain of stored
+        //    predecessors itself (a vertex's one DAG in-arc, then its tail's,
+        //    and so on) until it reaches a vertex already in the sub-DAG, or
+        //    s, or a vertex with two or more DAG in-arcs.  Those vertices (and
+        //    the B vertices whose stored predecessor may not be read) test
+        //    their E* in-arcs by Eq.1 in a round of their own, arc-parallel,
+        //    and the tails first found there start the next round's walks.
+        //    A round costs one barrier pair per such vertex on a path instead
+        //    of one per level.
+        int32_t wlo = 0, whi = sh.next;
+        bool first = true;
+        for (;;) {
+            if (tid == 0) sh.head = 0;
+            __syncthreads();
+            for (int32_t idx = wlo + tid; idx < whi; idx += bs) {
+                int32_t x = u.sub[idx];
+                int32_t p = PRED_MULTI;
+                if (pred && (b_pred || !first || !(u.outdeg[x] & W_B))) p = pred[x];
+                for (;;) {
+                    if (p < 0) {
+                        // s has no DAG in-arc; any other vertex tests E*
+                        if (p == PRED_MULTI || x != s) u.q1[atomicAdd(&sh.head, 1)] = x;
+                        break;
+                    }
+                    const int32_t pp = pred[p];  // issued before the count returns
+                    const int32_t old = atomicAdd(&u.outdeg[p], 1);
+                    if (kcap > 0) {
+                        const int32_t k = atomicAdd(&sh.nk, 1);
+                        if (k < kcap) {
+                            u.ka[k] = p;
+                            u.kb[k] = x;
+                            atomicAdd(&u.kcnt[x], 1);
+                        }
+                    }
+                    if (old & (W_COUNT | W_VIS)) break;
+                    u.sub[atomicAdd(&sh.next, 1)] = p;
+                    x = p;
+                    p = pp;
+                }
+            }
+            first = false;
+            __syncthreads();
+            const int32_t nslow = sh.head;
+            if (nslow == 0) break;
+            wlo = sh.next;
+            for (int32_t c = 0; c < nslow; c += bs) {
+                const int32_t idx = c + tid;
+                int32_t x = 0, b0 = 0, deg = 0, dx = 0;
+                if (idx < nslow) {
+                    x = u.q1[idx];
+                    b0 = cptr[x];
+                    deg = cptr[x + 1] - b0;
+                    dx = Drow[x];
+                }
+                int32_t total;
+                const int32_t off = block_excl_scan(deg, sh.scan, total);
+                es.off[tid] = off;
+                es.vtx[tid] = x;
+                es.beg[tid] = b0;
+                es.dx[tid] = dx;
+                __syncthreads();
+                const int32_t nv = min(bs, nslow - c);
+                for (int32_t jb = tid * RU; jb < total; jb += bs * RU) {
+                    int32_t iv[RU], ev[RU], av[RU], wv[RU];
+                    bool ok[RU];
+                    chunk_arcs(es, nv, total, jb, iv, ev, ok);
+#pragma unroll
+                    for (int k = 0; k < RU; ++k) {
+                        av[k] = ok[k] ? csrc[ev[k]] : 0;
+                        wv[k] = ok[k] ? cw[ev[k]] : 0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < RU; ++k) {
+                        if (!ok[k]) continue;
+                        const int32_t a = av[k];
+                        const int32_t da = Drow[a];
+                        if (da == INF32 || (int64_t)da + wv[k] != (int64_t)es.dx[iv[k]]) continue;
+                        if ((atomicAdd(&u.outdeg[a], 1) & (W_COUNT | W_VIS)) == 0)
+                            u.sub[atomicAdd(&sh.next, 1)] = a;
+                        if (kcap > 0) {
+                            const int32_t p = atomicAdd(&sh.nk, 1);
+                            if (p < kcap) {
+                                const int32_t x = es.vtx[iv[k]];
+                                u.ka[p] = a;
+                                u.kb[p] = x;
+                                atomicAdd(&u.kcnt[x], 1);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            whi = sh.next;
+        }
+    } else if (!sweep) {
+        // 1. one round over the vertices to test (a full pass: the others
+        //    took their stored predecessor above), arc-parallel.  B vertices
+        //    (always) and vertices with two or more DAG in-arcs test their E*
+        //    in-arcs by Eq.1.
         int32_t lo = 0, hi = sh.next;
         __syncthreads();
         while (lo < hi) {
@@ -1047,7 +1141,7 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
             for (int32_t idx = tid; idx < qn; idx += bs) {
                 const int32_t x = qa[idx];
                 const bool in_b = (u.outdeg[x] & W_B) != 0;
-                int32_t p = (pred && !in_b) ? pred[x] : PRED_MULTI;
+                int32_t p = (pred && (b_pred || !in_b)) ? pred[x] : PRED_MULTI;
                 if (p < 0 && rec && u.kcnt[x] == 1) p = u.kr[u.kend[x] - 1];
                 if (p < 0) {
                     qb[n - 1 - atomicAdd(&sh.kpos, 1)] = x;
@@ -2147,7 +2241,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // predecessors), the new one tries the LDS table first
     if (!dual)
         restricted_pass<false, XU>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u,
-                                   -1.0, bc_delta, pred_row, nullptr, sh, es);
+                                   -1.0, bc_delta, pred_row, nullptr, true, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {
         const int32_t t = Bt[i];
         const int32_t d = Bd[i];
@@ -2168,7 +2262,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     if (!fits ||
         !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, pred_row, sh, es, sd))
         preds_done = restricted_pass<false, XU>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb,
-                                                full, u, 1.0, bc_delta, pred_row, pred_row, sh, es);
+                                                full, u, 1.0, bc_delta, pred_row, pred_row, false, sh, es);
     if (!preds_done) refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, pred_row, sh, es);
 }
 
@@ -2332,7 +2426,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                 preds_done = restricted_pass<false, 2>(
                     s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
                     ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u, ph ? 1.0 : -1.0,
-                    J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr, sh, es);
+                    J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr, false, sh, es);
             }
             // the new row of the new pass: in LDS, in the slot (role 1 without
             // staging) or written back to D (role 2)
@@ -2589,7 +2683,7 @@ __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict_
     if (lds) Drow = lds_row;
     __syncthreads();
     restricted_pass<true, XU>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, u.bl_t,
-                          sh.nb, true, u, 1.0, out_row, nullptr, nullptr, sh, es);
+                          sh.nb, true, u, 1.0, out_row, nullptr, nullptr, false, sh, es);
 }
 
 // Arcs of DAG(s): the predicate of Eq.1 over E*.

@@ -1507,6 +1507,10 @@ struct DualDag {
     int32_t *key, *flags, *cnt, *dold, *dnew, *round, *pr, *ybeg, *ydeg, *xdeg, *front, *slow, *arcs;
     double *acc_o, *acc_n, *coef;
     uint64_t *sold, *snew;
+    // after the walk: the recorded arcs grouped by head (harc over ybeg and
+    // ydeg, 2 * TS entries), each head's range end (hend over slow) and
+    // in-arc count (hdeg over xdeg), and the Kahn work list (over coef)
+    int32_t *harc, *hend, *hdeg, *klist;
 };
 
 template <int TS>
@@ -1538,6 +1542,10 @@ __device__ __forceinline__ DualDag dual_dag_at(char *p) {
                                                   // the new stored predecessor of each changed target
     d.slow = (int32_t *)p;    p += 4 * DD_FRONT;  // a level's entries for the general expansion
     d.arcs = (int32_t *)p;                        // tail slot | head slot << 8 | kinds << 16
+    d.harc = d.ybeg;
+    d.hend = d.slow;
+    d.hdeg = d.xdeg;
+    d.klist = (int32_t *)d.coef;
     return d;
 }
 
@@ -1603,37 +1611,82 @@ __device__ __forceinline__ void dd_add_arc(const DualDag &d, BlockShared &sh, co
     else d.front[pos] = sa | (gained << 16);
 }
 
-// Kahn rounds over the recorded arcs of one of the two sub-DAGs (kind 1: old,
-// 2: new), from its sinks; acc gets delta_B of every member.
+// The recorded arcs grouped by head (a counting sort in LDS), for the Kahn
+// walks of both sub-DAGs.
 template <int TS>
-__device__ __forceinline__ void dual_kahn(const DualDag &d, const int kind, const int32_t narcs, BlockShared &sh) {
+__device__ __forceinline__ void dual_group_arcs(const DualDag &d, const int32_t narcs, BlockShared &sh) {
+    DD_CONSTS
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int32_t i = tid; i < DD_SLOTS; i += bs) d.hdeg[i] = 0;
+    __syncthreads();
+    for (int32_t k = tid; k < narcs; k += bs) atomicAdd(&d.hdeg[(d.arcs[k] >> 8) & 0xff], 1);
+    __syncthreads();
+    // exclusive scan over the slots, a run of consecutive slots per thread
+    const int32_t per = (DD_SLOTS + bs - 1) / bs, i0 = min(tid * per, DD_SLOTS), i1 = min(i0 + per, DD_SLOTS);
+    int32_t run = 0;
+    for (int32_t i = i0; i < i1; ++i) run += d.hdeg[i];
+    int32_t total;
+    int32_t off = block_excl_scan(run, sh.scan, total);
+    for (int32_t i = i0; i < i1; ++i) {
+        d.hend[i] = off;
+        off += d.hdeg[i];
+    }
+    __syncthreads();
+    // the scatter leaves hend[h] at the end of h's range
+    for (int32_t k = tid; k < narcs; k += bs) {
+        const int32_t e = d.arcs[k];
+        d.harc[atomicAdd(&d.hend[(e >> 8) & 0xff], 1)] = e;
+    }
+    __syncthreads();
+}
+
+// Dependency accumulation over one of the two sub-DAGs (kind 1: old, 2: new)
+// from its sinks: a member x, once every successor has pushed, gives each
+// DAG predecessor a the share sigma_sa * ([x in B] + acc(x)) / sigma_sx.  The
+// lane whose push completes a carries on with a at once, so a chain takes no
+// rounds; a vertex completing two or more waits for the next round.
+template <int TS>
+__device__ __forceinline__ void dual_kahn(const DualDag &d, const int kind, BlockShared &sh) {
     DD_CONSTS
     const int tid = threadIdx.x, bs = blockDim.x;
     const int shift = kind == DF_O ? 0 : 16;
     double *const acc = kind == DF_O ? d.acc_o : d.acc_n;
     const uint64_t *const sv = kind == DF_O ? d.sold : d.snew;
-    for (int32_t i = tid; i < DD_SLOTS; i += bs)
-        d.round[i] = (d.key[i] >= 0 && (d.flags[i] & kind) && ((d.cnt[i] >> shift) & 0xffff) == 0) ? 0 : -1;
+    if (tid == 0) sh.kpos = 0;
     __syncthreads();
-    for (int32_t r = 0;; ++r) {
-        if (tid == 0) sh.progress = 0;
-        __syncthreads();
-        for (int32_t i = tid; i < DD_SLOTS; i += bs) {
-            if (d.round[i] != r) continue;
-            d.coef[i] = (((d.flags[i] & DF_B) ? 1.0 : 0.0) + acc[i]) / (double)sv[i];
-            sh.progress = 1;
+    for (int32_t i = tid; i < DD_SLOTS; i += bs)
+        if (d.key[i] >= 0 && (d.flags[i] & kind) && ((d.cnt[i] >> shift) & 0xffff) == 0)
+            d.klist[atomicAdd(&sh.kpos, 1)] = i;
+    __syncthreads();
+    int32_t lo = 0, hi = sh.kpos;
+    while (lo < hi) {
+        for (int32_t idx = lo + tid; idx < hi; idx += bs) {
+            int32_t x = d.klist[idx];
+            for (;;) {
+                const double c = (((d.flags[x] & DF_B) ? 1.0 : 0.0) + acc[x]) / (double)sv[x];
+                int32_t next = -1;
+                const int32_t e1 = d.hend[x];
+                for (int32_t e = e1 - d.hdeg[x]; e < e1; ++e) {
+                    const int32_t arc = d.harc[e];
+                    if (!((arc >> 16) & kind)) continue;
+                    const int32_t a = arc & 0xff;
+                    if (c != 0.0) atomicAdd(&acc[a], (double)sv[a] * c);
+                    // release: the share lands before the count drops;
+                    // acquire: the last pusher sees every other share
+                    const int32_t left = __hip_atomic_fetch_sub(&d.cnt[a], 1 << shift, __ATOMIC_ACQ_REL,
+                                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (((left >> shift) & 0xffff) == 1) {
+                        if (next < 0) next = a;
+                        else d.klist[atomicAdd(&sh.kpos, 1)] = a;
+                    }
+                }
+                if (next < 0) break;
+                x = next;
+            }
         }
         __syncthreads();
-        if (sh.progress == 0) break;
-        for (int32_t k = tid; k < narcs; k += bs) {
-            const int32_t e = d.arcs[k];
-            if (!((e >> 16) & kind)) continue;
-            const int32_t sx = (e >> 8) & 0xff;
-            if (d.round[sx] != r) continue;
-            const int32_t sa = e & 0xff;
-            atomicAdd(&acc[sa], (double)sv[sa] * d.coef[sx]);
-            if (((atomicSub(&d.cnt[sa], 1 << shift) >> shift) & 0xffff) == 1) d.round[sa] = r + 1;
-        }
+        lo = hi;
+        hi = sh.kpos;
         __syncthreads();
     }
 }
@@ -1813,8 +1866,9 @@ __device__ bool dual_pass(const int32_t s, const int32_t *__restrict__ Dold, con
         if (d.key[i] >= 0 && (d.flags[i] & DF_B) && d.round[i] != 1)
             d.front[i] = d.round[i] == 0 ? PRED_NONE : PRED_MULTI;
     __syncthreads();
-    dual_kahn<TS>(d, DF_O, narcs, sh);
-    dual_kahn<TS>(d, DF_N, narcs, sh);
+    dual_group_arcs<TS>(d, narcs, sh);
+    dual_kahn<TS>(d, DF_O, sh);
+    dual_kahn<TS>(d, DF_N, sh);
     for (int32_t i = tid; i < DD_SLOTS; i += bs) {
         const int32_t x = d.key[i];
         if (x < 0 || x == s) continue;

@@ -798,7 +798,11 @@ __device__ void refresh_preds(const int32_t *__restrict__ Dnew, const int32_t *_
 // the whole accumulation; both give the same BC).
 // OUT_ROW: delta_B goes to out[x] (introspection); otherwise
 // out[x] += sign * delta_B(x) for x != s (out = the BC difference).
-template <bool OUT_ROW, int RU>
+// RU: arcs in flight per lane in the arc-parallel loops (the E* sweep
+// included); LU: vertices or recorded arcs in flight per lane in the loops
+// over the row, the changed targets and the arc record (each lane issues LU
+// independent loads or atomics before it uses any).
+template <bool OUT_ROW, int RU, int LU = 1>
 __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t *__restrict__ Drow,
                                 const uint64_t *__restrict__ Srow, const int32_t *__restrict__ cptr,
                                 const int32_t *__restrict__ csrc, const int32_t *__restrict__ cdst,
@@ -815,14 +819,22 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         sh.kpos = 0;
     }
     __syncthreads();
-    for (int32_t i = tid; i < nB; i += bs) {
-        const int32_t t = Bt[i];
-        if (t == s || Drow[t] == INF32) continue;
-        if (full) {
-            u.outdeg[t] = W_B;
-        } else {
-            u.outdeg[t] = W_VIS | W_B;
-            u.sub[atomicAdd(&sh.next, 1)] = t;
+    for (int32_t i0 = tid; i0 < nB; i0 += LU * bs) {
+        int32_t tv[LU];
+#pragma unroll
+        for (int k = 0; k < LU; ++k) tv[k] = i0 + k * bs < nB ? Bt[i0 + k * bs] : s;
+        bool live[LU];
+#pragma unroll
+        for (int k = 0; k < LU; ++k) live[k] = tv[k] != s && Drow[tv[k]] != INF32;
+#pragma unroll
+        for (int k = 0; k < LU; ++k) {
+            if (!live[k]) continue;
+            if (full) {
+                u.outdeg[tv[k]] = W_B;
+            } else {
+                u.outdeg[tv[k]] = W_VIS | W_B;
+                u.sub[atomicAdd(&sh.next, 1)] = tv[k];
+            }
         }
     }
     __syncthreads();
@@ -870,21 +882,37 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         // 1. every reachable vertex's DAG(s) in-arcs: its stored predecessor
         //    (an unchanged pair keeps its DAG in-arcs), else (a changed target,
         //    or two or more in-arcs) Eq.1 over its E* in-arcs, below
-        for (int32_t x = tid; x < n; x += bs) {
-            if (x == s || Drow[x] == INF32) continue;
-            const int32_t p = (u.outdeg[x] & W_B) ? PRED_MULTI : pred[x];
-            if (p >= 0) {
-                atomicAdd(&u.outdeg[p], 1);
-                if (kcap > 0) {
-                    const int32_t k = atomicAdd(&sh.nk, 1);
-                    if (k < kcap) {
-                        u.ka[k] = p;
-                        u.kb[k] = x;
-                        atomicAdd(&u.kcnt[x], 1);
-                    }
+        for (int32_t x0 = tid; x0 < n; x0 += LU * bs) {
+            int32_t pv[LU];
+            bool live[LU];
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                const int32_t x = x0 + k * bs;
+                live[k] = false;
+                pv[k] = PRED_MULTI;
+                if (x < n) {
+                    const int32_t dx = Drow[x], o = u.outdeg[x], pr = pred[x];
+                    live[k] = x != s && dx != INF32;
+                    pv[k] = (o & W_B) ? PRED_MULTI : pr;
                 }
-            } else {
-                u.sub[atomicAdd(&sh.next, 1)] = x;
+            }
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                if (!live[k]) continue;
+                const int32_t x = x0 + k * bs, p = pv[k];
+                if (p >= 0) {
+                    atomicAdd(&u.outdeg[p], 1);
+                    if (kcap > 0) {
+                        const int32_t q = atomicAdd(&sh.nk, 1);
+                        if (q < kcap) {
+                            u.ka[q] = p;
+                            u.kb[q] = x;
+                            atomicAdd(&u.kcnt[x], 1);
+                        }
+                    }
+                } else {
+                    u.sub[atomicAdd(&sh.next, 1)] = x;
+                }
             }
         }
     }
@@ -1078,12 +1106,29 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         if (rec) {
             // group the arcs by head: each head with arcs gets a range
             // [kend - kcnt, kend); the scatter advances kend from its start
-            for (int32_t x = tid; x < n; x += bs) {
-                const int32_t c = u.kcnt[x];
-                if (c) u.kend[x] = atomicAdd(&sh.kpos, c);
+            for (int32_t x0 = tid; x0 < n; x0 += LU * bs) {
+                int32_t cv[LU];
+#pragma unroll
+                for (int k = 0; k < LU; ++k) cv[k] = x0 + k * bs < n ? u.kcnt[x0 + k * bs] : 0;
+#pragma unroll
+                for (int k = 0; k < LU; ++k)
+                    if (cv[k]) u.kend[x0 + k * bs] = atomicAdd(&sh.kpos, cv[k]);
             }
             __syncthreads();
-            for (int32_t p = tid; p < nk; p += bs) u.kr[atomicAdd(&u.kend[u.kb[p]], 1)] = u.ka[p];
+            for (int32_t p0 = tid; p0 < nk; p0 += LU * bs) {
+                int32_t hv[LU], tv[LU], pos[LU];
+#pragma unroll
+                for (int k = 0; k < LU; ++k) {
+                    const int32_t q = p0 + k * bs;
+                    hv[k] = q < nk ? u.kb[q] : -1;
+                    tv[k] = q < nk ? u.ka[q] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < LU; ++k) pos[k] = hv[k] >= 0 ? atomicAdd(&u.kend[hv[k]], 1) : 0;
+#pragma unroll
+                for (int k = 0; k < LU; ++k)
+                    if (hv[k] >= 0) u.kr[pos[k]] = tv[k];
+            }
         } else if (kcap > 0) {
             // too many arcs to record: Kahn tests E*; undo the counts
             for (int32_t p = tid; p < kcap; p += bs) u.kcnt[u.kb[p]] = 0;
@@ -1091,8 +1136,21 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         __syncthreads();
         if (tid == 0) sh.tail = 0;
         __syncthreads();
-        for (int32_t x = tid; x < n; x += bs)
-            if (Drow[x] != INF32 && (u.outdeg[x] & W_COUNT) == 0) u.q1[atomicAdd(&sh.tail, 1)] = x;
+        for (int32_t x0 = tid; x0 < n; x0 += LU * bs) {
+            bool sink[LU];
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                const int32_t x = x0 + k * bs;
+                sink[k] = false;
+                if (x < n) {
+                    const int32_t dx = Drow[x], o = u.outdeg[x];
+                    sink[k] = dx != INF32 && (o & W_COUNT) == 0;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LU; ++k)
+                if (sink[k]) u.q1[atomicAdd(&sh.tail, 1)] = x0 + k * bs;
+        }
         nsub = n;
     } else {
         nsub = sh.next;
@@ -1234,11 +1292,28 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
     // a B vertex was tested, so its recorded in-arcs are all its DAG in-arcs
     const bool preds_done = rec && new_pred != nullptr;
     if (preds_done) {
-        for (int32_t i = tid; i < nB; i += bs) {
-            const int32_t t = Bt[i];
-            if (t == s || Drow[t] == INF32) continue;
-            const int32_t c = u.kcnt[t];
-            new_pred[t] = c == 1 ? u.kr[u.kend[t] - 1] : c == 0 ? PRED_NONE : PRED_MULTI;
+        for (int32_t i0 = tid; i0 < nB; i0 += LU * bs) {
+            int32_t tv[LU], cv[LU], ev[LU];
+            bool live[LU];
+#pragma unroll
+            for (int k = 0; k < LU; ++k) tv[k] = i0 + k * bs < nB ? Bt[i0 + k * bs] : s;
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                live[k] = false;
+                cv[k] = 0;
+                ev[k] = 0;
+                if (tv[k] != s) {
+                    const int32_t dt = Drow[tv[k]];
+                    cv[k] = u.kcnt[tv[k]];
+                    ev[k] = u.kend[tv[k]];
+                    live[k] = dt != INF32;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LU; ++k) {
+                if (!live[k]) continue;
+                new_pred[tv[k]] = cv[k] == 1 ? u.kr[ev[k] - 1] : cv[k] == 0 ? PRED_NONE : PRED_MULTI;
+            }
         }
         __syncthreads();
     }
@@ -2477,7 +2552,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                 // B vertices are always tested, so the old pass of a source never
                 // reads a stored predecessor that its new pass (another
                 // workgroup, at the same time) rewrites
-                preds_done = restricted_pass<false, 2>(
+                preds_done = restricted_pass<false, 2, 4>(
                     s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
                     ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u, ph ? 1.0 : -1.0,
                     J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr, false, sh, es);

@@ -2443,6 +2443,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     }
 }
 
+// A row copy with U loads in flight per lane (a plain loop waits for each
+// load before the next one).
+template <int U, typename T>
+__device__ __forceinline__ void copy_row(T *dst, const T *__restrict__ src, const int32_t n) {
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int32_t t0 = tid; t0 < n; t0 += U * bs) {
+        T v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = t0 + k * bs < n ? src[t0 + k * bs] : T(0);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (t0 + k * bs < n) dst[t0 + k * bs] = v[k];
+    }
+}
+
 // Wide kernel (persistent, runs after the DAG kernel): the deferred sources,
 // one workgroup of up to 1024 threads per unit of work.  The first
 // item_regions deferred sources (over the jobs in order) run as two units on
@@ -2498,7 +2513,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
             const int32_t *Dg = J.g.D + (size_t)s * n;
             const uint64_t *Sg = J.g.S + (size_t)s * n;
             if (lds) {
-                for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
+                copy_row<4>(lds_row, Dg, n);
                 __syncthreads();
             }
             scan_row<4>(J, R, sc, (sc.flags & 1) != 0, lds ? lds_row : Dg, Sg, use_tlist, t_count, u.q1, n, L, sh,

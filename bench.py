@@ -17,6 +17,9 @@ Besides the headline the run measures, on the same graphs and stream:
     after each, launched directly (no HIP graph, no batching);
   * a full GPU recompute (static Brandes on the GPU, the loader);
   * p50/p99 latency of a served Poisson stream at 0.8x the batched rate;
+  * a dedicated 1000-update stream on one freshly loaded graph;
+  * the multi-core CPU incremental comparator (the same update rules on CPU
+    threads) on a short sample, its state checked against the GPU's;
   * the CPU oracle (from-scratch Brandes) on a bounded sample of sources.
 Prints one JSON line.
 """
@@ -73,7 +76,8 @@ def main():
     ap.add_argument("--plain", type=int, default=None, help="updates on the plain path (default steps*graphs)")
     ap.add_argument("--latency-requests", type=int, default=160)
     ap.add_argument("--cpu-sources", type=int, default=4096)
-    ap.add_argument("--legs", default="batched,plain,recompute,latency,single,cpu,copy")
+    ap.add_argument("--legs", default="batched,plain,recompute,latency,single,cpuinc,cpu,copy")
+    ap.add_argument("--cpu-updates", type=int, default=12, help="updates of the CPU incremental comparator's sample")
     ap.add_argument("--single", type=int, default=1000, help="updates of the dedicated single-graph stream")
     ap.add_argument("--tune-sample", type=int, default=8, help="updates per graph in the autotuner's sample (0: no tuning)")
     args = ap.parse_args()
@@ -276,6 +280,69 @@ def main():
         twin.free()
         fresh.free()
         torch.cuda.empty_cache()
+
+    # ------------------------------------------------------- cpu incremental
+    # The multi-core CPU comparator (Lemma 2 per arc, the partial dependency
+    # over the changed pairs' ancestors; a vertex update arc by arc) on the
+    # same graph: its state is read back from a freshly loaded GPU copy, a
+    # short sample of the same mix is applied on CPU threads, and the same
+    # updates on the GPU copy must give the same rows (sampled) and BC.
+    if "cpuinc" in legs and args.cpu_updates > 0:
+        from paper_1311_2147_amd.cpu import CpuIncremental
+
+        C = args.cpu_updates
+        threads = min(16, os.cpu_count() or 1)
+        cstream = W.mixed_stream(graphs[0], C, 1000, W.derive_seed(5, 7000 + gidx[0]), 0.35, 0.35, 16)
+        base = ctx.load_graph(graphs[0])
+        ctx.sync()
+        t0 = time.perf_counter()
+        cpu_inc = CpuIncremental(graphs[0], threads=threads)
+        chunk = 1024
+        for s0 in range(0, n, chunk):
+            Dc, Sc = base.rows(s0, min(chunk, n - s0))
+            cpu_inc.set_rows(s0, Dc, Sc)
+        cpu_inc.set_scores(base.scores())
+        del Dc, Sc
+        fill_s = time.perf_counter() - t0
+        t_edge = t_vertex = 0.0
+        n_edge = n_vertex = 0
+        for up in cstream:
+            t0 = time.perf_counter()
+            cpu_inc.update(up)
+            dt = time.perf_counter() - t0
+            if up.kind == "edge":
+                t_edge += dt
+                n_edge += 1
+            else:
+                t_vertex += dt
+                n_vertex += 1
+        ctx.set_schedule(**default_sched)
+        for up in cstream:
+            base.update(up)
+        ctx.sync()
+        ctx.set_schedule(**tuned)
+        probe = np.linspace(0, n - 1, 64).astype(np.int64)
+        same = True
+        for s in probe:
+            Dg, Sg = base.rows(int(s), 1)
+            Dh, Sh = cpu_inc.rows(int(s), 1)
+            same = same and np.array_equal(Dg, Dh) and np.array_equal(Sg, Sh)
+        bg, bh = base.scores(), cpu_inc.scores()
+        same = same and float(np.max(np.abs(bg - bh) / np.maximum(np.abs(bg), 1.0))) <= 1e-10
+        cpu_inc.close()
+        base.free()
+        torch.cuda.empty_cache()
+        rate = C / (t_edge + t_vertex)
+        comparators["cpu_incremental"] = {
+            "updates": C, "threads": threads, "updates_per_s": rate,
+            "edge_updates_per_s": n_edge / t_edge if n_edge else None,
+            "vertex_updates_per_s": n_vertex / t_vertex if n_vertex else None,
+            "batched_over_cpu_incremental": value / rate, "same_state_sampled": bool(same),
+            "state_fill_s": fill_s,
+            "note": "C/OpenMP over the sources; a vertex update is applied as its arcs in turn"}
+        log(f"cpu incremental comparator: {C} updates ({n_edge} edge, {n_vertex} vertex) on {threads} threads -> "
+            f"{rate:.2f} updates/s (edge {n_edge / max(t_edge, 1e-9):.2f}/s, vertex {n_vertex / max(t_vertex, 1e-9):.2f}/s); "
+            f"same sampled state as the GPU: {same}; state read back in {fill_s:.1f}s")
 
     # ------------------------------------------------------------------ copy
     # A plain device-to-device copy of 1 GiB: the achievable HBM bandwidth on

@@ -1,4 +1,5 @@
-"""Builds libbcinc.so (HIP for gfx950) in-tree with hipcc."""
+"""Builds libbcinc.so (HIP for gfx950) in-tree with hipcc, and the CPU
+comparator's libcpu_incremental.so with gcc."""
 from __future__ import annotations
 
 import os
@@ -22,7 +23,24 @@ FLAGS = [
 ]
 
 
+CPU_SRC = os.path.join(HERE, "cpu", "cpu_incremental.c")
+CPU_LIB = os.path.join(HERE, "cpu", "libcpu_incremental.so")
+
+
+def build_cpu(verbose: bool = False) -> str:
+    cmd = [os.environ.get("CC", "gcc"), "-O3", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", CPU_SRC, "-o",
+           CPU_LIB + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("gcc failed:\n" + res.stdout + res.stderr)
+    if verbose and (res.stdout or res.stderr):
+        print(res.stdout + res.stderr)
+    os.replace(CPU_LIB + ".tmp", CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose: bool = False) -> str:
+    build_cpu(verbose)
     cmd = [HIPCC, *FLAGS, *SOURCES, "-o", LIB_PATH + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

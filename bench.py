@@ -282,8 +282,9 @@ def main():
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------- cpu incremental
-    # The multi-core CPU comparator (Lemma 2 per arc, the partial dependency
-    # over the changed pairs' ancestors; a vertex update arc by arc) on the
+    # The multi-core CPU comparator (Lemma 2 for an arc, the two-phase rule of
+    # Section 4 for a vertex update, the partial dependency over the changed
+    # pairs' ancestors) on the
     # same graph: its state is read back from a freshly loaded GPU copy, a
     # short sample of the same mix is applied on CPU threads, and the same
     # updates on the GPU copy must give the same rows (sampled) and BC.
@@ -339,7 +340,7 @@ def main():
             "vertex_updates_per_s": n_vertex / t_vertex if n_vertex else None,
             "batched_over_cpu_incremental": value / rate, "same_state_sampled": bool(same),
             "state_fill_s": fill_s,
-            "note": "C/OpenMP over the sources; a vertex update is applied as its arcs in turn"}
+            "note": "C/OpenMP over the sources, the same update rules (Lemma 2, Section 4) on the host"}
         log(f"cpu incremental comparator: {C} updates ({n_edge} edge, {n_vertex} vertex) on {threads} threads -> "
             f"{rate:.2f} updates/s (edge {n_edge / max(t_edge, 1e-9):.2f}/s, vertex {n_vertex / max(t_vertex, 1e-9):.2f}/s); "
             f"same sampled state as the GPU: {same}; state read back in {fill_s:.1f}s")

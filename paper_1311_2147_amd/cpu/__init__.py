@@ -1,8 +1,9 @@
 """Multi-core CPU comparator for the incremental BC update (C / OpenMP).
 
-The paper's arc update (Lemma 2) with the partial dependency over the
-ancestors of the changed pairs, run over the sources on CPU threads; a vertex
-update is applied as its arcs in turn.  It starts from a computed state (the
+The paper's arc update (Lemma 2) and vertex update (Section 4: Alg 4 over the
+new in-arcs, row v'' over the new out-arcs, Lemma 4 per pair), with the
+partial dependency over the ancestors of the changed pairs, run over the
+sources on CPU threads.  It starts from a computed state (the
 rows and scores of a graph, for instance read back from the GPU library) and
 is a comparator only: the GPU library never calls it.
 """

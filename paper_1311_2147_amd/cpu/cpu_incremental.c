@@ -22,10 +22,18 @@
  *     in-arcs), in non-increasing distance order (a reverse topological
  *     order, Section 2.1), once on the old row and arcs, once on the new.
  *   - BC(x) += delta'_B(x) - delta_B(x) for every such x other than s (Eq.3).
- * An undirected edge update is its two arc updates in turn (Section 3); a
- * vertex update (Section 4) is applied here as its arcs in turn, which
- * reaches the same state as the two-phase rule of Lemma 4 but takes one pass
- * over the affected sources per arc.
+ * A vertex update at v (Section 4) with new in-arcs E_i and out-arcs E_o
+ * takes one pass over the sources, as the paper does:
+ *   - Alg 4 per source over E_i: d'(s,v) (Eq.6), sigma'_sv, and the new
+ *     paths sigma-hat'_sv (Eq.7) when d'(s,v) = d(s,v);
+ *   - row v'' (the Out phase, Alg 4 on G'_R): d''(v,t) = min(d(v,t),
+ *     min_j w'(v,x_j) + d'(x_j,t)) with sigma''_vt and the new paths
+ *     sigma-hat''_vt, the rows x_j taken after the In phase;
+ *   - Lemma 4 per pair, In phase with row v (d'(s,v) + d(v,t)), then on
+ *     G'_R with row v'' (d'(s,v) + d''(v,t)); a tie adds only new paths.
+ *   Row v is read from a snapshot, since source v rewrites it.
+ * An undirected edge update {u,v} is the vertex form at u with E_i =
+ * {(v,u)} and E_o = {(u,v)} (Section 3).
  *
  * Distances are int32 (INT32_MAX: unreachable; a sum that reaches it is a
  * distance overflow), path counts uint64 (every product and sum checked).
@@ -56,9 +64,25 @@ typedef struct {
 } scratch_t;
 
 typedef struct {
+    int32_t dv;      /* d'(s,v) */
+    uint8_t same;    /* d'(s,v) = d(s,v) */
+    uint8_t aff;     /* the source can change */
+    uint64_t sv, hv; /* sigma'_sv, sigma-hat'_sv */
+} scal_t;
+
+typedef struct {
     int32_t n;
     int directed;
     int threads;
+    /* the arcs of the update in progress: (ua, ub) gets weight uw (replacing
+     * the stored arc or added); uhead marks their heads */
+    int32_t nupd, upd_cap;
+    int32_t *ua, *ub;
+    int64_t *uw;
+    uint8_t *uhead;
+    scal_t *scal;                    /* per source */
+    int32_t *rvD, *rvvD;             /* row v (snapshot) and row v'' */
+    uint64_t *rvS, *rvvS, *rvvH;
     int32_t *D;      /* n x n */
     uint64_t *S;     /* n x n */
     double *bc;      /* n */
@@ -119,6 +143,16 @@ void icpu_destroy(void *h) {
     free(c->D);
     free(c->S);
     free(c->bc);
+    free(c->ua);
+    free(c->ub);
+    free(c->uw);
+    free(c->uhead);
+    free(c->scal);
+    free(c->rvD);
+    free(c->rvvD);
+    free(c->rvS);
+    free(c->rvvS);
+    free(c->rvvH);
     free(c);
 }
 
@@ -141,7 +175,15 @@ int icpu_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, co
     c->in_src = calloc((size_t)n, sizeof(int32_t *));
     c->in_w = calloc((size_t)n, sizeof(int64_t *));
     c->sc = calloc((size_t)c->threads, sizeof(scratch_t));
-    if (!c->D || !c->S || !c->bc || !c->deg || !c->cap || !c->in_src || !c->in_w || !c->sc) {
+    c->uhead = calloc((size_t)n, 1);
+    c->scal = calloc((size_t)n, sizeof(scal_t));
+    c->rvD = malloc(sizeof(int32_t) * (size_t)n);
+    c->rvvD = malloc(sizeof(int32_t) * (size_t)n);
+    c->rvS = malloc(sizeof(uint64_t) * (size_t)n);
+    c->rvvS = malloc(sizeof(uint64_t) * (size_t)n);
+    c->rvvH = malloc(sizeof(uint64_t) * (size_t)n);
+    if (!c->D || !c->S || !c->bc || !c->deg || !c->cap || !c->in_src || !c->in_w || !c->sc || !c->uhead || !c->scal ||
+        !c->rvD || !c->rvvD || !c->rvS || !c->rvvS || !c->rvvH) {
         icpu_destroy(c);
         return IC_NOMEM;
     }
@@ -240,31 +282,39 @@ static void sort_by_dist_desc(int32_t *v, int32_t k, const int32_t *D) {
     }
 }
 
-/* The DAG in-arcs of x in row Drow: in-arcs (a, x, w) with d(s,a) + w =
- * d(s,x) (Eq.1).  With upd set, arc (upd_a, x) has weight upd_w instead of
- * its stored one (or is added when absent). */
-#define FOR_DAG_IN_ARCS(c, Drow, x, upd, upd_a, upd_b, upd_w, BODY)                             \
+static int in_update(const ic_t *c, int32_t a, int32_t b) {
+    for (int32_t k = 0; k < c->nupd; ++k)
+        if (c->ua[k] == a && c->ub[k] == b) return 1;
+    return 0;
+}
+
+/* The DAG in-arcs (a, x) of x in row Drow: in-arcs with d(s,a) + w =
+ * d(s,x) (Eq.1).  With ovl set, the arcs of the update in progress carry
+ * their new weights. */
+#define FOR_DAG_IN_ARCS(c, Drow, x, ovl, BODY)                                                  \
     do {                                                                                        \
         const int32_t dx_ = (Drow)[x];                                                          \
-        const int up_ = (upd) && (x) == (upd_b);                                                \
+        const int up_ = (ovl) && (c)->uhead[x];                                                 \
         for (int32_t i_ = 0; i_ < (c)->deg[x]; ++i_) {                                          \
             const int32_t a = (c)->in_src[x][i_];                                               \
-            if (up_ && a == (upd_a)) continue;                                                  \
+            if (up_ && in_update(c, a, x)) continue;                                            \
             const int32_t da_ = (Drow)[a];                                                      \
             if (da_ != INF32 && (int64_t)da_ + (c)->in_w[x][i_] == (int64_t)dx_) { BODY }       \
         }                                                                                       \
-        if (up_) {                                                                              \
-            const int32_t a = (upd_a);                                                          \
-            const int32_t da_ = (Drow)[a];                                                      \
-            if (da_ != INF32 && (int64_t)da_ + (upd_w) == (int64_t)dx_) { BODY }                \
-        }                                                                                       \
+        if (up_)                                                                                \
+            for (int32_t k_ = 0; k_ < (c)->nupd; ++k_) {                                        \
+                if ((c)->ub[k_] != (x)) continue;                                               \
+                const int32_t a = (c)->ua[k_];                                                  \
+                const int32_t da_ = (Drow)[a];                                                  \
+                if (da_ != INF32 && (int64_t)da_ + (c)->uw[k_] == (int64_t)dx_) { BODY }        \
+            }                                                                                   \
     } while (0)
 
 /* delta_B(x) (Eq.4 over the targets in B) for every ancestor x of B in the
  * DAG of row (Drow, Srow); B is marked with bit 1.  Adds sign * delta_B(x)
- * to bcd[x] for x != s.  Uses the updated arc when upd is set. */
+ * to bcd[x] for x != s. */
 static void partial_dependency(const ic_t *c, scratch_t *x, int32_t s, const int32_t *Drow, const uint64_t *Srow,
-                               int32_t nb, double sign, int upd, int32_t ua, int32_t ub, int64_t uw) {
+                               int32_t nb, double sign, int ovl) {
     int32_t k = 0;
     for (int32_t i = 0; i < nb; ++i) {
         const int32_t t = x->t[i];
@@ -275,7 +325,7 @@ static void partial_dependency(const ic_t *c, scratch_t *x, int32_t s, const int
     /* backward search over DAG in-arcs: the ancestors of B */
     for (int32_t h = 0; h < k; ++h) {
         const int32_t y = x->list[h];
-        FOR_DAG_IN_ARCS(c, Drow, y, upd, ua, ub, uw, {
+        FOR_DAG_IN_ARCS(c, Drow, y, ovl, {
             if (!(x->mark[a] & 1)) {
                 x->mark[a] |= 1;
                 x->list[k++] = a;
@@ -286,7 +336,7 @@ static void partial_dependency(const ic_t *c, scratch_t *x, int32_t s, const int
     for (int32_t h = 0; h < k; ++h) {
         const int32_t y = x->list[h];
         const double coef = (((x->mark[y] & 2) ? 1.0 : 0.0) + x->acc[y]) / (double)Srow[y];
-        FOR_DAG_IN_ARCS(c, Drow, y, upd, ua, ub, uw, { x->acc[a] += (double)Srow[a] * coef; });
+        FOR_DAG_IN_ARCS(c, Drow, y, ovl, { x->acc[a] += (double)Srow[a] * coef; });
     }
     for (int32_t h = 0; h < k; ++h) {
         const int32_t y = x->list[h];
@@ -296,9 +346,73 @@ static void partial_dependency(const ic_t *c, scratch_t *x, int32_t s, const int
     }
 }
 
-/* One arc update (u, v) to weight w (checked by the caller). */
-static int arc_update(ic_t *c, int32_t u, int32_t v, int64_t w) {
-    const int32_t n = c->n;
+/* The changed pairs of source s are in x->t/d/sg: old partial dependency,
+ * the new values written, new partial dependency. */
+static void apply_source(ic_t *c, scratch_t *x, int32_t s, int32_t nb) {
+    int32_t *Ds = c->D + (size_t)s * c->n;
+    uint64_t *Ss = c->S + (size_t)s * c->n;
+    for (int32_t i = 0; i < nb; ++i) x->mark[x->t[i]] |= 2;
+    partial_dependency(c, x, s, Ds, Ss, nb, -1.0, 0);
+    for (int32_t i = 0; i < nb; ++i) {
+        Ds[x->t[i]] = x->d[i];
+        Ss[x->t[i]] = x->sg[i];
+    }
+    partial_dependency(c, x, s, Ds, Ss, nb, 1.0, 1);
+    for (int32_t i = 0; i < nb; ++i) x->mark[x->t[i]] = 0;
+}
+
+/* After every source: the threads' BC changes, then the update's arcs. */
+static int finish_update(ic_t *c) {
+    for (int i = 0; i < c->threads; ++i) {
+        double *b = c->sc[i].bcd;
+        for (int32_t t = 0; t < c->n; ++t) {
+            c->bc[t] += b[t];
+            b[t] = 0.0;
+        }
+    }
+    int rc = IC_OK;
+    for (int32_t k = 0; k < c->nupd; ++k) {
+        const int32_t a = c->ua[k], b = c->ub[k];
+        c->uhead[b] = 0;
+        int found = 0;
+        for (int32_t i = 0; i < c->deg[b]; ++i)
+            if (c->in_src[b][i] == a) {
+                c->in_w[b][i] = c->uw[k];
+                found = 1;
+                break;
+            }
+        if (!found && !rc) rc = add_in_arc(c, a, b, c->uw[k]);
+    }
+    c->nupd = 0;
+    return rc;
+}
+
+static int push_update_arc(ic_t *c, int32_t a, int32_t b, int64_t w) {
+    if (c->nupd == c->upd_cap) {
+        const int32_t nc = c->upd_cap ? 2 * c->upd_cap : 16;
+        int32_t *na = realloc(c->ua, sizeof(int32_t) * (size_t)nc);
+        if (!na) return IC_NOMEM;
+        c->ua = na;
+        int32_t *nb = realloc(c->ub, sizeof(int32_t) * (size_t)nc);
+        if (!nb) return IC_NOMEM;
+        c->ub = nb;
+        int64_t *nw = realloc(c->uw, sizeof(int64_t) * (size_t)nc);
+        if (!nw) return IC_NOMEM;
+        c->uw = nw;
+        c->upd_cap = nc;
+    }
+    c->ua[c->nupd] = a;
+    c->ub[c->nupd] = b;
+    c->uw[c->nupd] = w;
+    c->nupd++;
+    c->uhead[b] = 1;
+    return IC_OK;
+}
+
+/* Lemma 2: the one arc (u, v) of the update list, weight w. */
+static int arc_update(ic_t *c) {
+    const int32_t n = c->n, u = c->ua[0], v = c->ub[0];
+    const int64_t w = c->uw[0];
     int err = IC_OK;
     const int32_t *Dv = c->D + (size_t)v * n;
     const uint64_t *Sv = c->S + (size_t)v * n;
@@ -308,8 +422,8 @@ static int arc_update(ic_t *c, int32_t u, int32_t v, int64_t w) {
         int my_err = IC_OK;
 #pragma omp for schedule(dynamic, 16)
         for (int32_t s = 0; s < n; ++s) {
-            int32_t *Ds = c->D + (size_t)s * n;
-            uint64_t *Ss = c->S + (size_t)s * n;
+            const int32_t *Ds = c->D + (size_t)s * n;
+            const uint64_t *Ss = c->S + (size_t)s * n;
             const int32_t dsu = Ds[u];
             if (dsu == INF32 || s == v) continue;
             const int64_t cu = (int64_t)dsu + w;
@@ -342,35 +456,200 @@ static int arc_update(ic_t *c, int32_t u, int32_t v, int64_t w) {
                 x->sg[nb] = ns;
                 ++nb;
             }
-            if (nb == 0) continue;
-            for (int32_t i = 0; i < nb; ++i) x->mark[x->t[i]] |= 2;
-            partial_dependency(c, x, s, Ds, Ss, nb, -1.0, 0, 0, 0, 0);
-            for (int32_t i = 0; i < nb; ++i) {
-                Ds[x->t[i]] = x->d[i];
-                Ss[x->t[i]] = x->sg[i];
-            }
-            partial_dependency(c, x, s, Ds, Ss, nb, 1.0, 1, u, v, w);
-            for (int32_t i = 0; i < nb; ++i) x->mark[x->t[i]] = 0;
+            if (nb) apply_source(c, x, s, nb);
         }
         if (my_err) {
 #pragma omp critical
             err = my_err;
         }
     }
-    /* the BC changes of every thread, then the arc itself */
-    for (int i = 0; i < c->threads; ++i) {
-        double *b = c->sc[i].bcd;
-        for (int32_t t = 0; t < n; ++t) {
-            c->bc[t] += b[t];
-            b[t] = 0.0;
+    const int rc = finish_update(c);
+    return err ? err : rc;
+}
+
+/* Section 4: the update list holds arcs into v (E_i) and out of v (E_o). */
+static int vertex_update(ic_t *c, int32_t v) {
+    const int32_t n = c->n;
+    int32_t nout = 0;
+    for (int32_t k = 0; k < c->nupd; ++k) nout += c->ua[k] == v;
+    int err = IC_OK;
+    memcpy(c->rvD, c->D + (size_t)v * n, sizeof(int32_t) * (size_t)n);
+    memcpy(c->rvS, c->S + (size_t)v * n, sizeof(uint64_t) * (size_t)n);
+    const int32_t *rvD = c->rvD;
+    const uint64_t *rvS = c->rvS;
+    /* Alg 4 over E_i per source, and whether the source can change */
+#pragma omp parallel for num_threads(c->threads) schedule(static)
+    for (int32_t s = 0; s < n; ++s) {
+        const int32_t *Ds = c->D + (size_t)s * n;
+        const uint64_t *Ss = c->S + (size_t)s * n;
+        const int32_t dsv = Ds[v];
+        int64_t cur = dsv;
+        uint64_t sig = Ss[v], hat = 0;
+        int bad = 0;
+        for (int32_t k = 0; k < c->nupd; ++k) {
+            if (c->ub[k] != v) continue;
+            const int32_t du = Ds[c->ua[k]];
+            if (du == INF32) continue;
+            const int64_t cc = (int64_t)du + c->uw[k];
+            if (cc >= INF32) {
+                bad = IC_DIST_OVERFLOW;
+                continue;
+            }
+            const uint64_t su = Ss[c->ua[k]];
+            if (cc == cur) {
+                if (__builtin_add_overflow(sig, su, &sig) || __builtin_add_overflow(hat, su, &hat))
+                    bad = IC_SIGMA_OVERFLOW;
+            } else if (cc < cur) {
+                cur = cc;
+                sig = su;
+                hat = 0;
+            }
+        }
+        scal_t sc;
+        sc.dv = (int32_t)cur;
+        sc.same = cur == (int64_t)dsv;
+        sc.sv = sig;
+        sc.hv = hat;
+        sc.aff = cur < (int64_t)dsv || hat != 0;
+        if (!sc.aff && cur != INF32 && nout)
+            for (int32_t k = 0; k < c->nupd && !sc.aff; ++k) {
+                if (c->ua[k] != v) continue;
+                const int32_t xh = c->ub[k];
+                int64_t d1 = Ds[xh];
+                if (rvD[xh] != INF32 && cur + rvD[xh] < d1) d1 = cur + rvD[xh];
+                const int64_t cc = cur + c->uw[k];
+                if (cc < INF32 && cc <= d1) sc.aff = 1;
+            }
+        c->scal[s] = sc;
+        if (bad) {
+#pragma omp critical
+            err = bad;
         }
     }
-    for (int32_t i = 0; i < c->deg[v]; ++i)
-        if (c->in_src[v][i] == u) {
-            c->in_w[v][i] = w;
-            return err;
+    /* row v'': Alg 4 on G'_R over E_o, the rows x_j after the In phase */
+    if (nout) {
+#pragma omp parallel for num_threads(c->threads) schedule(static)
+        for (int32_t t = 0; t < n; ++t) {
+            const int32_t dvt = rvD[t];
+            int64_t best = dvt;
+            uint64_t sig = rvS[t], hat = 0;
+            int bad = 0;
+            for (int32_t k = 0; k < c->nupd; ++k) {
+                if (c->ua[k] != v) continue;
+                const int32_t xh = c->ub[k];
+                const scal_t sx = c->scal[xh];
+                int64_t d1 = c->D[(size_t)xh * n + t];
+                uint64_t s1 = c->S[(size_t)xh * n + t];
+                if (sx.dv != INF32 && dvt != INF32) {
+                    const int64_t cc = (int64_t)sx.dv + dvt;
+                    if (cc <= d1) {
+                        uint64_t add;
+                        if (cc >= INF32) {
+                            bad = IC_DIST_OVERFLOW;
+                        } else if (__builtin_mul_overflow(cc < d1 || !sx.same ? sx.sv : sx.hv, rvS[t], &add)) {
+                            bad = IC_SIGMA_OVERFLOW;
+                        } else if (cc < d1) {
+                            d1 = cc;
+                            s1 = add;
+                        } else if (__builtin_add_overflow(s1, add, &s1)) {
+                            bad = IC_SIGMA_OVERFLOW;
+                        }
+                    }
+                }
+                if (d1 == INF32) continue;
+                const int64_t c2 = c->uw[k] + d1;
+                if (c2 >= INF32) {
+                    bad = IC_DIST_OVERFLOW;
+                    continue;
+                }
+                if (c2 < best) {
+                    best = c2;
+                    sig = s1;
+                    hat = 0;
+                } else if (c2 == best) {
+                    if (__builtin_add_overflow(sig, s1, &sig) || __builtin_add_overflow(hat, s1, &hat))
+                        bad = IC_SIGMA_OVERFLOW;
+                }
+            }
+            c->rvvD[t] = (int32_t)best;
+            c->rvvS[t] = sig;
+            c->rvvH[t] = hat;
+            if (bad) {
+#pragma omp critical
+                err = bad;
+            }
         }
-    const int rc = add_in_arc(c, u, v, w);
+    }
+    const int32_t *rvvD = c->rvvD;
+    const uint64_t *rvvS = c->rvvS, *rvvH = c->rvvH;
+    /* Lemma 4 per pair of every source that can change */
+#pragma omp parallel num_threads(c->threads)
+    {
+        scratch_t *x = &c->sc[omp_get_thread_num()];
+        int my_err = IC_OK;
+#pragma omp for schedule(dynamic, 16)
+        for (int32_t s = 0; s < n; ++s) {
+            const scal_t sc = c->scal[s];
+            if (!sc.aff) continue;
+            const int32_t *Ds = c->D + (size_t)s * n;
+            const uint64_t *Ss = c->S + (size_t)s * n;
+            int32_t nb = 0;
+            for (int32_t t = 0; t < n; ++t) {
+                const int32_t d0 = Ds[t];
+                int64_t d = d0;
+                uint64_t sg = 0;
+                int known = 0;
+                if (sc.dv != INF32 && rvD[t] != INF32) {
+                    const int64_t cc = (int64_t)sc.dv + rvD[t];
+                    if (cc <= d0) {
+                        uint64_t add;
+                        if (cc >= INF32) {
+                            my_err = IC_DIST_OVERFLOW;
+                        } else if (__builtin_mul_overflow(cc < d0 || !sc.same ? sc.sv : sc.hv, rvS[t], &add)) {
+                            my_err = IC_SIGMA_OVERFLOW;
+                        } else if (cc < d0) {
+                            d = cc;
+                            sg = add;
+                            known = 1;
+                        } else if (add != 0) {
+                            if (__builtin_add_overflow(Ss[t], add, &sg)) my_err = IC_SIGMA_OVERFLOW;
+                            known = 1;
+                        }
+                    }
+                }
+                if (nout && sc.dv != INF32 && rvvD[t] != INF32) {
+                    const int64_t cc = (int64_t)sc.dv + rvvD[t];
+                    if (cc <= d) {
+                        uint64_t add;
+                        const uint64_t mult = (cc < d || rvvD[t] != rvD[t]) ? rvvS[t] : rvvH[t];
+                        if (cc >= INF32) {
+                            my_err = IC_DIST_OVERFLOW;
+                        } else if (__builtin_mul_overflow(sc.sv, mult, &add)) {
+                            my_err = IC_SIGMA_OVERFLOW;
+                        } else if (cc < d) {
+                            d = cc;
+                            sg = add;
+                            known = 1;
+                        } else if (add != 0) {
+                            if (__builtin_add_overflow(known ? sg : Ss[t], add, &sg)) my_err = IC_SIGMA_OVERFLOW;
+                            known = 1;
+                        }
+                    }
+                }
+                if (!known) continue;
+                x->t[nb] = t;
+                x->d[nb] = (int32_t)d;
+                x->sg[nb] = sg;
+                ++nb;
+            }
+            if (nb) apply_source(c, x, s, nb);
+        }
+        if (my_err) {
+#pragma omp critical
+            err = my_err;
+        }
+    }
+    const int rc = finish_update(c);
     return err ? err : rc;
 }
 
@@ -381,19 +660,26 @@ static int check_arc(const ic_t *c, int32_t a, int32_t b, int64_t w) {
     return IC_OK;
 }
 
-/* Decrease or insert edge (u, v) to weight w (both arcs when undirected). */
+/* Decrease or insert edge (u, v) to weight w: Lemma 2 for an arc, the
+ * vertex form at u for an undirected edge. */
 int icpu_update_edge(void *h, int32_t u, int32_t v, int64_t w) {
     ic_t *c = (ic_t *)h;
     if (!c) return IC_BAD_ARG;
     int rc = check_arc(c, u, v, w);
     if (rc) return rc;
-    rc = arc_update(c, u, v, w);
-    if (!rc && !c->directed) rc = arc_update(c, v, u, w);
-    return rc;
+    if (c->directed) {
+        if ((rc = push_update_arc(c, u, v, w))) return rc;
+        return arc_update(c);
+    }
+    if ((rc = push_update_arc(c, v, u, w)) || (rc = push_update_arc(c, u, v, w))) {
+        c->nupd = 0;
+        return rc;
+    }
+    return vertex_update(c, u);
 }
 
 /* Vertex update at v: k edges (a[i], b[i]) each incident to v, each a
- * decrease or an insertion, no edge twice; applied arc by arc. */
+ * decrease or an insertion, no edge twice. */
 int icpu_update_vertex(void *h, int32_t v, int32_t k, const int32_t *a, const int32_t *b, const int64_t *w) {
     ic_t *c = (ic_t *)h;
     if (!c || k < 0 || (k > 0 && (!a || !b || !w)) || v < 0 || v >= c->n) return IC_BAD_ARG;
@@ -406,9 +692,15 @@ int icpu_update_vertex(void *h, int32_t v, int32_t k, const int32_t *a, const in
             if (same) return IC_BAD_ARG;
         }
     }
+    if (k == 0) return IC_OK;
     for (int32_t i = 0; i < k; ++i) {
-        const int rc = icpu_update_edge(c, a[i], b[i], w[i]);
-        if (rc) return rc;
+        int rc = push_update_arc(c, a[i], b[i], w[i]);
+        if (!rc && !c->directed) rc = push_update_arc(c, b[i], a[i], w[i]);
+        if (rc) {
+            for (int32_t j = 0; j < c->nupd; ++j) c->uhead[c->ub[j]] = 0;
+            c->nupd = 0;
+            return rc;
+        }
     }
-    return IC_OK;
+    return vertex_update(c, v);
 }

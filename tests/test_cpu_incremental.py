@@ -1,5 +1,6 @@
-"""The multi-core CPU comparator (Lemma 2 per arc with the partial dependency
-over the changed pairs' ancestors) against the oracle: distances and path
+"""The multi-core CPU comparator (Lemma 2 for an arc, Section 4's two-phase
+rule for a vertex update, the partial dependency over the changed pairs'
+ancestors) against the oracle: distances and path
 counts bit-exact and BC within the parity tolerance after every update, on
 undirected, directed, tie-heavy and complete graphs with edge and vertex
 updates; the thread count changes nothing but the BC summation order; bad

@@ -199,6 +199,18 @@ bc_status bc_recompute_estar(bc_ctx *ctx, bc_graph_id g);
  * bc_state_hash: 128-bit hash of D and sigma (order-fixed, bit-exact).
  * bc_get_stats: counters of the last update (see bc_update_stats). */
 bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id g, int32_t s0, int32_t cnt, int64_t *D, uint64_t *sigma);
+
+/* Checkpoint: the graph's current arcs, as bc_load_graph takes them (arcs
+ * (src[i] -> dst[i]) of a directed graph; one entry per edge, src < dst, of
+ * an undirected one), with every update submitted so far applied (the host
+ * keeps this list as it validates updates).  cap entries at most, *cnt gets
+ * the full count; the pointers may be NULL to ask for the count.  Loading the
+ * arcs again (bc_load_graph, the static pass of Section 6) re-derives D,
+ * sigma, E*, the stored predecessors and BC: the restored graph's D and sigma
+ * equal the live one's once its updates have run (bc_sync), and its BC agrees
+ * within rounding.  Host-side only; needs no synchronisation. */
+bc_status bc_get_arcs(bc_ctx *ctx, bc_graph_id g, int32_t *src, int32_t *dst, int64_t *w, int64_t cap,
+                      int64_t *cnt);
 bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *a, int32_t *b, int64_t cap, int64_t *cnt);
 bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id g, int32_t *a, int32_t *b, int64_t *w, int64_t cap, int64_t *cnt);
 bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id g, int32_t s, double *out);

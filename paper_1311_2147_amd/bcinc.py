@@ -106,6 +106,7 @@ _SIGS = {
     "bc_get_rows": (_i32, [_P, _i32, _i32, _i32, _P, _P]),
     "bc_get_dag": (_i32, [_P, _i32, _i32, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_estar": (_i32, [_P, _i32, _P, _P, _P, _i64, ctypes.POINTER(_i64)]),
+    "bc_get_arcs": (_i32, [_P, _i32, _P, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_delta": (_i32, [_P, _i32, _i32, _P]),
     "bc_get_preds": (_i32, [_P, _i32, _i32, _P]),
     "bc_state_hash": (_i32, [_P, _i32, _P]),
@@ -286,6 +287,32 @@ class Context:
         self._check(_lib.bc_set_schedule(self.h, ctypes.byref(s)), "bc_set_schedule")
 
 
+class Arcs:
+    """A graph's arcs as load_graph takes them (n, directed, src, dst, w)."""
+
+    def __init__(self, n: int, directed: bool, src, dst, w):
+        self.n, self.directed = int(n), bool(directed)
+        self.src, self.dst, self.w = src, dst, w
+
+    @property
+    def m(self) -> int:
+        return int(len(self.src))
+
+
+def save_checkpoint(gr: "Graph", path: str):
+    """Writes the graph's current arcs (bc_get_arcs) to an .npz file."""
+    a = gr.arcs()
+    np.savez(path, n=np.int64(a.n), directed=np.int64(a.directed), src=a.src, dst=a.dst, w=a.w)
+
+
+def load_checkpoint(ctx: "Context", path: str, **kw) -> "Graph":
+    """Loads a checkpoint written by save_checkpoint (plain arrays only, no
+    pickles): the static pass re-derives the state."""
+    with np.load(path, allow_pickle=False) as z:
+        a = Arcs(int(z["n"]), bool(z["directed"]), z["src"], z["dst"], z["w"])
+    return ctx.load_graph(a, **kw)
+
+
 class Graph:
     """A graph resident on the device (bc_graph_id)."""
 
@@ -344,6 +371,18 @@ class Graph:
         self.ctx._check(_lib.bc_get_estar(self.ctx.h, self.gid, _np_ptr(a), _np_ptr(b), _np_ptr(w), k,
                                           ctypes.byref(cnt)), "bc_get_estar")
         return a[:k], b[:k], w[:k]
+
+    def arcs(self) -> "Arcs":
+        """bc_get_arcs: the current arcs, in the form load_graph takes."""
+        cnt = ctypes.c_int64()
+        self.ctx._check(_lib.bc_get_arcs(self.ctx.h, self.gid, None, None, None, 0, ctypes.byref(cnt)), "bc_get_arcs")
+        k = cnt.value
+        src = np.empty(max(k, 1), dtype=np.int32)
+        dst = np.empty(max(k, 1), dtype=np.int32)
+        w = np.empty(max(k, 1), dtype=np.int64)
+        self.ctx._check(_lib.bc_get_arcs(self.ctx.h, self.gid, _np_ptr(src), _np_ptr(dst), _np_ptr(w), k,
+                                         ctypes.byref(cnt)), "bc_get_arcs")
+        return Arcs(self.n, self.directed, src[:k], dst[:k], w[:k])
 
     def delta(self, s: int) -> np.ndarray:
         out = np.empty(self.n, dtype=np.float64)

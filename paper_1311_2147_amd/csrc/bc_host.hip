@@ -1392,6 +1392,32 @@ bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id gid, int32_t s0, int32_t cnt, int
     return BC_OK;
 }
 
+bc_status bc_get_arcs(bc_ctx *ctx, bc_graph_id gid, int32_t *src, int32_t *dst, int64_t *w, int64_t cap,
+                      int64_t *cnt) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || !cnt || cap < 0) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    const Mirror &M = g->mirror;
+    // the CSR in tail order, then the arcs inserted since its last rebuild
+    // (sorted); an undirected edge once, from its smaller endpoint
+    std::vector<std::pair<uint64_t, int32_t>> extra(M.extra.begin(), M.extra.end());
+    std::sort(extra.begin(), extra.end());
+    int64_t k = 0;
+    auto emit = [&](int32_t a, int32_t b, int32_t wt) {
+        if (!g->directed && b < a) return;
+        if (k < cap) {
+            if (src) src[k] = a;
+            if (dst) dst[k] = b;
+            if (w) w[k] = wt;
+        }
+        ++k;
+    };
+    for (int32_t a = 0; a < g->n; ++a)
+        for (int64_t i = M.ptr[a]; i < M.ptr[a + 1]; ++i) emit(a, M.dst[i], M.w[i]);
+    for (auto &e : extra) emit((int32_t)(e.first / (uint64_t)g->n), (int32_t)(e.first % (uint64_t)g->n), e.second);
+    *cnt = k;
+    return BC_OK;
+}
+
 bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id gid, int32_t *a, int32_t *b, int64_t *w, int64_t cap, int64_t *cnt) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g || !cnt || cap < 0) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");

@@ -925,8 +925,8 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
         //    the B vertices whose stored predecessor may not be read) test
         //    their E* in-arcs by Eq.1 in a round of their own, arc-parallel,
         //    and the tails first found there start the next round's walks.
-        //    A round costs one barrier pair per such vertex on a path instead
-        //    of one per level.
+        //    So the rounds follow the vertices with two or more in-arcs along
+        //    a path, not its levels.
         int32_t wlo = 0, whi = sh.next;
         bool first = true;
         for (;;) {
@@ -942,7 +942,9 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                         if (p == PRED_MULTI || x != s) u.q1[atomicAdd(&sh.head, 1)] = x;
                         break;
                     }
-                    const int32_t pp = pred[p];  // issued before the count returns
+                    // p's own predecessor, loaded before the count returns (unused
+                    // when p is already in the sub-DAG, as every B vertex is)
+                    const int32_t pp = pred[p];
                     const int32_t old = atomicAdd(&u.outdeg[p], 1);
                     if (kcap > 0) {
                         const int32_t k = atomicAdd(&sh.nk, 1);
@@ -2565,8 +2567,10 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                     __syncthreads();
                 }
                 // B vertices are always tested, so the old pass of a source never
-                // reads a stored predecessor that its new pass (another
-                // workgroup, at the same time) rewrites
+                // uses a stored predecessor that its new pass (another
+                // workgroup, at the same time) rewrites: its walk may load one
+                // ahead, but stops at the B vertex, which is in the sub-DAG from
+                // the start
                 preds_done = restricted_pass<false, 2, 4>(
                     s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
                     ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u, ph ? 1.0 : -1.0,

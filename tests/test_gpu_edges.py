@@ -266,3 +266,27 @@ def test_capacity_and_admission_errors():
         tiny.load_graph(g, arc_capacity=2 * g.m)
     assert e.value.name == "BC_ERR_ADMISSION"
     tiny.close()
+
+
+def test_lemma1_row_v_column_u_and_undirected_symmetry():
+    """Lemma 1: an arc update (u, v) leaves row v and column u as they were;
+    an undirected graph's D and sigma stay symmetric through every update."""
+    g = W.random_small(90, 0.06, 10, seed=91, directed=True)
+    h = W.random_small(80, 0.06, 10, seed=93, directed=False)
+    ctx = make_ctx(max(g.n, h.n), slots=8)
+    gr = ctx.load_graph(g)
+    ups = W.mixed_stream(g, 12, 10, 92, 0.5, 0.5, 4)
+    assert all(up.kind == "edge" for up in ups)
+    for up in ups:
+        D0, S0 = gr.rows()
+        gr.update(up)
+        D1, S1 = gr.rows()
+        assert np.array_equal(D1[up.v], D0[up.v]) and np.array_equal(S1[up.v], S0[up.v]), "row v changed"
+        assert np.array_equal(D1[:, up.u], D0[:, up.u]) and np.array_equal(S1[:, up.u], S0[:, up.u]), \
+            "column u changed"
+    gh = ctx.load_graph(h)
+    for up in W.mixed_stream(h, 10, 10, 94, 0.35, 0.35, 4):
+        gh.update(up)
+        D, S = gh.rows()
+        assert np.array_equal(D, D.T) and np.array_equal(S, S.T), "undirected state lost its symmetry"
+    ctx.close()

@@ -2358,13 +2358,15 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     uint64_t *const Sg = J.g.S + (size_t)s * n;
     const int32_t *Drow = lds ? lds_row : Dg;
     double *const bc_delta = J.g.bc_delta;
-    // an LDS table holds at most 3/4 of its slots in vertices, and a B of
-    // half that many or more almost never fits with its ancestors (on the
-    // Chung-Lu headline window, 120 of 20 600 such sources fit with the
-    // 128-slot table): those go straight to the slot passes
-    const bool fits = try_small && nb < TS * 3 / 8;
+    // an LDS table holds at most 3/4 of its slots in vertices: larger B sets
+    // go straight to the slot passes.  The union of both sub-DAGs with a B of
+    // half that many or more almost never fits (on the Chung-Lu headline
+    // window, 120 of 20 600 such sources fit with the 128-slot table), so
+    // those skip the union walk; the new sub-DAG alone often fits
+    const bool fits = try_small && nb < TS * 3 / 4;
+    const bool dual_fits = try_small && nb < TS * 3 / 8;
     int32_t *const pred_row = J.g.pred + (size_t)s * n;
-    const bool dual = fits && dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs,
+    const bool dual = dual_fits && dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs,
                                             pred_row, nb, bc_delta, sh, es, dd);
     // a large B (here 1/16 of the row or more) makes the sub-DAG most of
     // DAG(s): take every vertex's DAG in-arcs instead of walking back from B

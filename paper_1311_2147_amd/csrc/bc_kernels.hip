@@ -662,8 +662,10 @@ __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t 
 
 // Arc-parallel expansion helpers: the in-arcs of a list of vertices are
 // flattened with a block-wide scan of their in-degrees; each lane takes XU
-// consecutive arcs and issues their loads together.
-constexpr int XU = 4;
+// consecutive arcs and issues their loads together.  Two keep the DAG kernel
+// within its 96 registers without spills (four cost six spilled registers
+// and were slower).
+constexpr int XU = 2;
 
 struct ExpandShared {
     int32_t *off, *vtx, *beg, *dx;
@@ -2407,7 +2409,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
 // the context-wide n_layout (the largest graph), so the zero-kept arrays sit
 // at the same place for every job.  The work is bound by dependent gathers, so
 // the register budget is held to five waves per SIMD (ten 128-thread
-// workgroups per CU) at the price of a couple of spilled registers.
+// workgroups per CU), 96 registers with no spills.
 template <int TS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_source(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
                                                 char *__restrict__ scratch, size_t slot_bytes, int32_t lds_cap,

@@ -428,9 +428,7 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, jobs, nj, pool);
         hipLaunchKernelGGL(k_scan, dim3(g_elem), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_targets, dim3(g_elem), dim3(256), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_es_count<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_es_scan<ES_MERGE>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_es_scatter<ES_MERGE>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_merge, dim3(g_wave), dim3(256), 0, st, jobs, nj);
     } else if (part == 1) {
         hipLaunchKernelGGL(k_rows, dim3(ctx->rows_grid), dim3(256), 0, st, jobs, nj, ctx->big_b, pool);
     } else if (part == 2) {

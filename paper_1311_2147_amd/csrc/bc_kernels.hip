@@ -281,8 +281,9 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
 //
 // E* is kept as segments of arcs keyed by tail (X, built by the static pass
 // for its forward Kahn order) or by head (XC, kept current; the update walks
-// DAG predecessors).  One wave-per-segment compaction serves every mode; see
-// the ES_* enum.  An arc whose weight exceeds its distance lies on no
+// DAG predecessors).  One wave-per-segment compaction serves the build and
+// filter modes (see the ES_* enum); the per-update merge is elementwise
+// (k_es_merge).  An arc whose weight exceeds its distance lies on no
 // shortest path and is dropped; distances only decrease under incremental
 // updates, so E*' is contained in E* plus the updated arcs (Section 1
 // definition of E*; Alg 6 steps 2-4 use the same test w(u,v) = d(u,v)).
@@ -290,7 +291,6 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
 struct EsView {
     const int32_t *ptr, *other, *w;  // input segments; other = the non-key endpoint
     bool by_head;                    // key endpoint: head (true) or tail (false)
-    bool keep_all, merge;
     int32_t *optr, *osrc, *odst, *ow;
     int32_t m_limit;
     int32_t *m_out;
@@ -298,8 +298,6 @@ struct EsView {
 
 __device__ __forceinline__ EsView es_view(const UpdateJob &J, int mode) {
     EsView e;
-    e.keep_all = false;
-    e.merge = false;
     e.m_limit = (int32_t)J.g.es_cap;
     if (mode == ES_BUILD) {
         e.ptr = J.g.arc_ptr; e.other = J.g.arc_dst; e.w = J.g.arc_w; e.by_head = false;
@@ -309,12 +307,6 @@ __device__ __forceinline__ EsView es_view(const UpdateJob &J, int mode) {
         e.ptr = J.g.arcin_ptr; e.other = J.g.arcin_src; e.w = J.g.arcin_w; e.by_head = true;
         e.optr = J.g.xc_ptr; e.osrc = J.g.xc_src; e.odst = J.g.xc_dst; e.ow = J.g.xc_w;
         e.m_out = &J.g.ctl->esc_m;
-    } else if (mode == ES_MERGE) {
-        e.ptr = J.g.xc_ptr; e.other = J.g.xc_src; e.w = J.g.xc_w; e.by_head = true;
-        e.optr = J.g.yc_ptr; e.osrc = J.g.yc_src; e.odst = J.g.yc_dst; e.ow = J.g.yc_w;
-        e.m_out = &J.g.ctl->esc_m_tmp;
-        e.keep_all = true;
-        e.merge = true;
     } else {
         e.ptr = J.g.yc_ptr; e.other = J.g.yc_src; e.w = J.g.yc_w; e.by_head = true;
         e.optr = J.g.xc_ptr; e.osrc = J.g.xc_src; e.odst = J.g.xc_dst; e.ow = J.g.xc_w;
@@ -324,7 +316,7 @@ __device__ __forceinline__ EsView es_view(const UpdateJob &J, int mode) {
 }
 
 __device__ __forceinline__ bool es_keep(const UpdateJob &J, const EsView &e, int32_t a, int32_t b, int32_t w) {
-    return e.keep_all || J.g.D[(size_t)a * J.g.n + b] == w;
+    return J.g.D[(size_t)a * J.g.n + b] == w;
 }
 
 template <int MODE>
@@ -349,12 +341,6 @@ __global__ void __launch_bounds__(256) k_es_count(const UpdateJob *__restrict__ 
                     keep = e.by_head ? es_keep(J, e, o, (int32_t)key, e.w[i]) : es_keep(J, e, (int32_t)key, o, e.w[i]);
                 }
                 cnt += (int32_t)__popcll(__ballot(keep));
-            }
-            if (e.merge) {
-                for (int32_t base = 0; base < J.n_u; base += 64) {
-                    const int32_t k = base + lane;
-                    cnt += (int32_t)__popcll(__ballot(k < J.n_u && J.u_head[k] == key));
-                }
             }
             if (lane == 0) J.g.es_cnt[key] = cnt;
         }
@@ -457,20 +443,55 @@ __global__ void __launch_bounds__(256) k_es_scatter(const UpdateJob *__restrict_
                 }
                 out += (int32_t)__popcll(mask);
             }
-            if (e.merge) {
-                for (int32_t base = 0; base < J.n_u; base += 64) {
-                    const int32_t k = base + lane;
-                    const bool hit = (k < J.n_u) && (J.u_head[k] == key);
-                    const uint64_t mask = __ballot(hit);
-                    if (hit) {
-                        const int32_t o = out + (int32_t)popc_below(mask, lane);
-                        e.osrc[o] = J.u_tail[k];
-                        e.odst[o] = (int32_t)key;
-                        e.ow[o] = J.u_w[k];
-                    }
-                    out += (int32_t)__popcll(mask);
-                }
-            }
+        }
+    }
+}
+
+// E* merge in one elementwise pass: YC keeps every XC arc and adds the
+// update's arcs behind their head's XC arcs, so head h's segment starts
+// before(h) entries later than in XC, before(h) = the update arcs into heads
+// below h.  Each XC arc and each update arc is placed directly (the same
+// layout the count / scan / scatter passes produce in the other modes).  An
+// XC arc that the update lowers stays beside its new copy: its old weight
+// satisfies Eq.1 for no source, and the filter drops it.
+__global__ void __launch_bounds__(256) k_es_merge(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
+    const int njobs = *njobs_p;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    for (int j = 0; j < njobs; ++j) {
+        const UpdateJob &J = jobs[j];
+        if (job_dead(J)) continue;
+        const int32_t n = J.g.n, nu = J.n_u;
+        const int32_t *__restrict__ ptr = J.g.xc_ptr;
+        const int32_t m = ptr[n];
+        const int64_t total = (int64_t)m + nu;
+        if (total > J.g.es_cap) {
+            if (gid == 0) atomicOr(&J.g.ctl->status, ST_ESTAR_CAP);
+            continue;
+        }
+        if (gid == 0) J.g.ctl->esc_m_tmp = (int32_t)total;
+        for (int64_t h = gid; h <= n; h += nthreads) {
+            int32_t before = 0;
+            for (int k = 0; k < nu; ++k) before += J.u_head[k] < h;
+            J.g.yc_ptr[h] = ptr[h] + before;
+        }
+        for (int64_t i = gid; i < m; i += nthreads) {
+            const int32_t h = J.g.xc_dst[i];
+            int32_t before = 0;
+            for (int k = 0; k < nu; ++k) before += J.u_head[k] < h;
+            const int64_t o = i + before;
+            J.g.yc_src[o] = J.g.xc_src[i];
+            J.g.yc_dst[o] = h;
+            J.g.yc_w[o] = J.g.xc_w[i];
+        }
+        for (int64_t k = gid; k < nu; k += nthreads) {
+            const int32_t h = J.u_head[k];
+            int32_t before = 0;
+            for (int q = 0; q < nu; ++q) before += J.u_head[q] < h || (J.u_head[q] == h && q < k);
+            const int64_t o = (int64_t)ptr[h + 1] + before;
+            J.g.yc_src[o] = J.u_tail[k];
+            J.g.yc_dst[o] = h;
+            J.g.yc_w[o] = J.u_w[k];
         }
     }
 }

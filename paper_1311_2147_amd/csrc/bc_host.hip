@@ -149,6 +149,9 @@ struct bc_ctx {
     std::vector<GraphRec *> graphs;
     std::string last_error;
     // staging
+    // pinned host image of each staging slot, laid out as on the device (the
+    // job count in a 256-byte header, then the jobs): one copy stages a step
+    char *h_ring[RING] = {};
     UpdateJob *h_jobs[RING] = {};
     int32_t *h_njobs[RING] = {};
     hipEvent_t ring_ev[RING] = {};
@@ -386,10 +389,8 @@ bc_status ring_stage(bc_ctx *ctx, int r, const std::vector<UpdateJob> &jobs) {
     if (nj > (size_t)JCAP) return fail(ctx, BC_ERR_CAPACITY, "too many jobs in one step");
     *ctx->h_njobs[r] = (int32_t)nj;
     if (nj) memcpy(ctx->h_jobs[r], jobs.data(), sizeof(UpdateJob) * nj);
-    HIPCHK(hipMemcpyAsync(ring_njobs_dev(ctx, r), ctx->h_njobs[r], sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-    if (nj)
-        HIPCHK(hipMemcpyAsync(ring_jobs_dev(ctx, r), ctx->h_jobs[r], sizeof(UpdateJob) * nj, hipMemcpyHostToDevice,
-                              ctx->stream));
+    HIPCHK(hipMemcpyAsync(ring_dev(ctx, r), ctx->h_ring[r], 256 + sizeof(UpdateJob) * nj, hipMemcpyHostToDevice,
+                          ctx->stream));
     return BC_OK;
 }
 
@@ -909,10 +910,10 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
     e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
     if (e != hipSuccess) return bail(e, "hipEventCreate");
     for (int r = 0; r < RING; ++r) {
-        e = hipHostMalloc((void **)&ctx->h_jobs[r], sizeof(UpdateJob) * JCAP, hipHostMallocDefault);
+        e = hipHostMalloc((void **)&ctx->h_ring[r], ring_slot_bytes(), hipHostMallocDefault);
         if (e != hipSuccess) return bail(e, "hipHostMalloc");
-        e = hipHostMalloc((void **)&ctx->h_njobs[r], 256, hipHostMallocDefault);
-        if (e != hipSuccess) return bail(e, "hipHostMalloc");
+        ctx->h_njobs[r] = (int32_t *)ctx->h_ring[r];
+        ctx->h_jobs[r] = (UpdateJob *)(ctx->h_ring[r] + 256);
         e = hipEventCreateWithFlags(&ctx->ring_ev[r], hipEventDisableTiming);
         if (e != hipSuccess) return bail(e, "hipEventCreate");
         for (int q = 0; q < 5; ++q) {
@@ -1098,8 +1099,7 @@ bc_status bc_destroy(bc_ctx *ctx) {
     for (auto &kv : ctx->tickets) (void)hipEventDestroy(kv.second);
     for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
     for (int r = 0; r < RING; ++r) {
-        if (ctx->h_jobs[r]) (void)hipHostFree(ctx->h_jobs[r]);
-        if (ctx->h_njobs[r]) (void)hipHostFree(ctx->h_njobs[r]);
+        if (ctx->h_ring[r]) (void)hipHostFree(ctx->h_ring[r]);
         if (ctx->ring_ev[r]) (void)hipEventDestroy(ctx->ring_ev[r]);
         for (int q = 0; q < 5; ++q)
             if (ctx->tev[r][q]) (void)hipEventDestroy(ctx->tev[r][q]);

@@ -455,9 +455,9 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
                            L.n_layout);
         HIPCHK(hipStreamWaitEvent(st, ctx->join_ev, 0));
     } else {
-        hipLaunchKernelGGL(k_es_count<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_es_scan<ES_FILTER>, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_es_scatter<ES_FILTER>, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_keep, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_wscan, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_place, dim3(g_wave), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_commit, dim3(g_elem), dim3(256), 0, st, jobs, nj, 0);
     }
     HIPCHK(hipGetLastError());

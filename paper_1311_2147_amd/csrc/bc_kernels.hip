@@ -496,6 +496,99 @@ __global__ void __launch_bounds__(256) k_es_merge(const UpdateJob *__restrict__ 
     }
 }
 
+// E* filter, arc-parallel: XC = the arcs of YC with w = d'(a,b), in YC
+// order.  One gather per arc sets a bit of a 64-bit keep mask per 64 arcs;
+// one workgroup per job scans the masks' popcounts; then every kept arc and
+// every head's segment start is placed directly.  The masks and their
+// prefix sit in the by-tail E* arrays (X), which only the static pass uses
+// and rebuilds before use.
+__device__ __forceinline__ uint64_t *es_mask(const UpdateJob &J) { return (uint64_t *)J.g.x_src; }
+__device__ __forceinline__ int32_t *es_wpre(const UpdateJob &J) { return J.g.x_dst; }
+
+__global__ void __launch_bounds__(256) k_es_keep(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
+    const int njobs = *njobs_p;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    for (int j = 0; j < njobs; ++j) {
+        const UpdateJob &J = jobs[j];
+        if (job_dead(J)) continue;
+        const int32_t n = J.g.n;
+        const int64_t m = J.g.yc_ptr[n];
+        const int64_t m64 = (m + 63) & ~(int64_t)63;
+        uint64_t *const mask = es_mask(J);
+        // a wave covers 64 consecutive arcs (the stride is a multiple of 64)
+        for (int64_t i = gid; i < m64; i += nthreads) {
+            bool keep = false;
+            if (i < m) {
+                const int32_t a = J.g.yc_src[i], b = J.g.yc_dst[i];
+                keep = J.g.D[(size_t)a * n + b] == J.g.yc_w[i];
+            }
+            const uint64_t word = __ballot(keep);
+            if (lane_id() == 0) mask[i >> 6] = word;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_es_wscan(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
+    __shared__ int32_t sh[40];
+    const int j = blockIdx.x;
+    if (j >= *njobs_p) return;
+    const UpdateJob &J = jobs[j];
+    if (job_dead(J)) return;
+    const int64_t m = J.g.yc_ptr[J.g.n];
+    const int32_t words = (int32_t)((m + 63) >> 6);
+    const uint64_t *const mask = es_mask(J);
+    int32_t *const wpre = es_wpre(J);
+    int32_t carry = 0;
+    for (int32_t base = 0; base < words; base += 4 * (int32_t)blockDim.x) {
+        const int32_t w0 = base + 4 * (int32_t)threadIdx.x;
+        int32_t c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = w0 + k < words ? __popcll(mask[w0 + k]) : 0;
+        int32_t total;
+        int32_t off = block_excl_scan(c[0] + c[1] + c[2] + c[3], sh, total) + carry;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (w0 + k < words) wpre[w0 + k] = off;
+            off += c[k];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        wpre[words] = carry;
+        J.g.ctl->esc_m = carry;
+    }
+}
+
+// arcs of YC before position p that are kept
+__device__ __forceinline__ int32_t es_kept_before(const uint64_t *mask, const int32_t *wpre, const int64_t p) {
+    const int64_t w = p >> 6;
+    const int r = (int)(p & 63);
+    return wpre[w] + (r ? __popcll(mask[w] & ((1ull << r) - 1)) : 0);
+}
+
+__global__ void __launch_bounds__(256) k_es_place(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
+    const int njobs = *njobs_p;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    for (int j = 0; j < njobs; ++j) {
+        const UpdateJob &J = jobs[j];
+        if (job_dead(J)) continue;
+        const int32_t n = J.g.n;
+        const int64_t m = J.g.yc_ptr[n];
+        const uint64_t *const mask = es_mask(J);
+        const int32_t *const wpre = es_wpre(J);
+        for (int64_t i = gid; i < m; i += nthreads) {
+            if (!((mask[i >> 6] >> (i & 63)) & 1)) continue;
+            const int32_t o = es_kept_before(mask, wpre, i);
+            J.g.xc_src[o] = J.g.yc_src[i];
+            J.g.xc_dst[o] = J.g.yc_dst[i];
+            J.g.xc_w[o] = J.g.yc_w[i];
+        }
+        for (int64_t h = gid; h <= n; h += nthreads) J.g.xc_ptr[h] = es_kept_before(mask, wpre, J.g.yc_ptr[h]);
+    }
+}
+
 // ------------------------------------------------------------ DAG passes ---
 
 struct BlockShared {

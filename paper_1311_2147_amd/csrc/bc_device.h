@@ -28,7 +28,8 @@ constexpr int32_t LDS_ROW_MAX = 36864;
 //   ES_BUILD   all arcs (CSR by tail)  -> X  (arcs with w == d)
 //   ES_BUILD_C all arcs (CSR by head)  -> XC (arcs with w == d)
 //   ES_MERGE   XC plus the updated arcs -> YC (k_es_merge, elementwise)
-//   ES_FILTER  YC                       -> XC (arcs with w == d after the update)
+//   ES_FILTER  YC                       -> XC (arcs with w == d after the update;
+//              k_es_keep, k_es_wscan, k_es_place, arc-parallel)
 enum { ES_BUILD = 0, ES_BUILD_C = 1, ES_MERGE = 2, ES_FILTER = 3 };
 
 // Flags of the restricted dependency pass.  The LDS table keeps them apart;

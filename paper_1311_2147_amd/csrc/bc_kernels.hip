@@ -281,9 +281,10 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
 //
 // E* is kept as segments of arcs keyed by tail (X, built by the static pass
 // for its forward Kahn order) or by head (XC, kept current; the update walks
-// DAG predecessors).  One wave-per-segment compaction serves the build and
-// filter modes (see the ES_* enum); the per-update merge is elementwise
-// (k_es_merge).  An arc whose weight exceeds its distance lies on no
+// DAG predecessors).  A wave-per-segment compaction builds X and XC in the
+// static pass (see the ES_* enum); an update's merge (k_es_merge) and filter
+// (k_es_keep / k_es_wscan / k_es_place) are arc-parallel.  An arc whose
+// weight exceeds its distance lies on no
 // shortest path and is dropped; distances only decrease under incremental
 // updates, so E*' is contained in E* plus the updated arcs (Section 1
 // definition of E*; Alg 6 steps 2-4 use the same test w(u,v) = d(u,v)).
@@ -303,12 +304,8 @@ __device__ __forceinline__ EsView es_view(const UpdateJob &J, int mode) {
         e.ptr = J.g.arc_ptr; e.other = J.g.arc_dst; e.w = J.g.arc_w; e.by_head = false;
         e.optr = J.g.x_ptr; e.osrc = J.g.x_src; e.odst = J.g.x_dst; e.ow = J.g.x_w;
         e.m_out = &J.g.ctl->es_m;
-    } else if (mode == ES_BUILD_C) {
-        e.ptr = J.g.arcin_ptr; e.other = J.g.arcin_src; e.w = J.g.arcin_w; e.by_head = true;
-        e.optr = J.g.xc_ptr; e.osrc = J.g.xc_src; e.odst = J.g.xc_dst; e.ow = J.g.xc_w;
-        e.m_out = &J.g.ctl->esc_m;
     } else {
-        e.ptr = J.g.yc_ptr; e.other = J.g.yc_src; e.w = J.g.yc_w; e.by_head = true;
+        e.ptr = J.g.arcin_ptr; e.other = J.g.arcin_src; e.w = J.g.arcin_w; e.by_head = true;
         e.optr = J.g.xc_ptr; e.osrc = J.g.xc_src; e.odst = J.g.xc_dst; e.ow = J.g.xc_w;
         e.m_out = &J.g.ctl->esc_m;
     }
@@ -327,7 +324,7 @@ __global__ void __launch_bounds__(256) k_es_count(const UpdateJob *__restrict__ 
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (MODE >= ES_MERGE && job_dead(J)) continue;
+
         const EsView e = es_view(J, MODE);
         const int32_t n = J.g.n;
         for (int64_t key = wave; key < n; key += nwaves) {
@@ -357,7 +354,7 @@ __global__ void __launch_bounds__(1024) k_es_scan(const UpdateJob *__restrict__ 
     const int j = blockIdx.x;
     if (j >= *njobs_p) return;
     const UpdateJob &J = jobs[j];
-    if (MODE >= ES_MERGE && job_dead(J)) return;
+
     const EsView e = es_view(J, MODE);
     const int32_t n = J.g.n;
     const int32_t *cnt = J.g.es_cnt;
@@ -416,7 +413,7 @@ __global__ void __launch_bounds__(256) k_es_scatter(const UpdateJob *__restrict_
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (MODE >= ES_MERGE && job_dead(J)) continue;
+
         const EsView e = es_view(J, MODE);
         const int32_t n = J.g.n;
         if (e.optr[n] > e.m_limit) continue;

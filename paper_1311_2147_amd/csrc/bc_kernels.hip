@@ -2721,16 +2721,36 @@ __global__ void __launch_bounds__(256) k_wide_apply(const UpdateJob *__restrict_
         const int32_t n = J.g.n;
         const int32_t count = *(volatile int32_t *)&J.g.ctl->big_count;
         const int32_t paired = min(count, item_regions - region0);
-        for (int32_t item = blockIdx.x; item < paired; item += gridDim.x) {
+        // every workgroup takes a share of every source's changed pairs (a
+        // few sources can hold tens of thousands each), four in flight per lane
+        constexpr int U = 4;
+        const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+        for (int32_t item = 0; item < paired; ++item) {
             const ItemRegion ir = item_region_at(items + (size_t)(region0 + item) * region_bytes, n_layout);
             const int32_t s = J.g.biglist[item];
             const int32_t nb = *ir.nb;
             int32_t *Dg = J.g.D + (size_t)s * n;
             uint64_t *Sg = J.g.S + (size_t)s * n;
-            for (int32_t i = threadIdx.x; i < nb; i += blockDim.x) {
-                const int32_t t = ir.t[i];
-                Dg[t] = ir.d[i];
-                Sg[t] = ir.s[i];
+            for (int64_t i0 = gid; i0 < nb; i0 += U * nthreads) {
+                int32_t tv[U], dv[U];
+                uint64_t sv[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int64_t i = i0 + k * nthreads;
+                    tv[k] = -1;
+                    if (i < nb) {
+                        tv[k] = ir.t[i];
+                        dv[k] = ir.d[i];
+                        sv[k] = ir.s[i];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    if (tv[k] >= 0) {
+                        Dg[tv[k]] = dv[k];
+                        Sg[tv[k]] = sv[k];
+                    }
             }
         }
         region0 += paired;

@@ -2721,23 +2721,25 @@ __global__ void __launch_bounds__(256) k_wide_apply(const UpdateJob *__restrict_
         const int32_t n = J.g.n;
         const int32_t count = *(volatile int32_t *)&J.g.ctl->big_count;
         const int32_t paired = min(count, item_regions - region0);
-        // every workgroup takes a share of every source's changed pairs (a
-        // few sources can hold tens of thousands each), four in flight per lane
+        // a group of gridDim / paired workgroups (at least one) per source,
+        // sharing its changed pairs (a few sources can hold tens of thousands
+        // each), four in flight per lane
         constexpr int U = 4;
-        const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-        for (int32_t item = 0; item < paired; ++item) {
+        const int32_t per = paired > 0 ? max(1, (int32_t)gridDim.x / paired) : 1;
+        for (int32_t w = blockIdx.x; w < paired * per; w += gridDim.x) {
+            const int32_t item = w / per, slice = w % per;
             const ItemRegion ir = item_region_at(items + (size_t)(region0 + item) * region_bytes, n_layout);
             const int32_t s = J.g.biglist[item];
             const int32_t nb = *ir.nb;
             int32_t *Dg = J.g.D + (size_t)s * n;
             uint64_t *Sg = J.g.S + (size_t)s * n;
-            for (int64_t i0 = gid; i0 < nb; i0 += U * nthreads) {
+            const int32_t stride = per * (int32_t)blockDim.x;
+            for (int32_t i0 = slice * (int32_t)blockDim.x + (int32_t)threadIdx.x; i0 < nb; i0 += U * stride) {
                 int32_t tv[U], dv[U];
                 uint64_t sv[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const int64_t i = i0 + k * nthreads;
+                    const int32_t i = i0 + k * stride;
                     tv[k] = -1;
                     if (i < nb) {
                         tv[k] = ir.t[i];

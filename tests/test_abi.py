@@ -83,3 +83,33 @@ def test_create_without_device_fails_cleanly(lib_built):
     h = ctypes.c_void_p()
     rc = bcinc._lib.bc_create(ctypes.byref(h), ctypes.byref(cfg))
     assert rc in (-12, -1)
+
+
+def test_checkpoint_file_holds_plain_arrays(lib_built, tmp_path):
+    """save_checkpoint writes the arcs as plain arrays; load_checkpoint reads
+    them without pickles and hands load_graph exactly what was saved."""
+    import numpy as np
+
+    from paper_1311_2147_amd import bcinc
+
+    arcs = bcinc.Arcs(6, False, np.array([0, 1, 4], np.int32), np.array([2, 3, 5], np.int32),
+                      np.array([7, 9, 11], np.int64))
+
+    class Saved:
+        def arcs(self):
+            return arcs
+
+    class Loader:
+        def load_graph(self, g, **kw):
+            self.g = g
+            return "loaded"
+
+    path = str(tmp_path / "graph.npz")
+    bcinc.save_checkpoint(Saved(), path)
+    with np.load(path, allow_pickle=False) as z:
+        assert set(z.files) == {"n", "directed", "src", "dst", "w"}
+    ld = Loader()
+    assert bcinc.load_checkpoint(ld, path) == "loaded"
+    g = ld.g
+    assert g.n == 6 and g.directed is False and g.m == 3
+    assert np.array_equal(g.src, arcs.src) and np.array_equal(g.dst, arcs.dst) and np.array_equal(g.w, arcs.w)

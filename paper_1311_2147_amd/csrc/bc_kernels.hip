@@ -513,12 +513,18 @@ __global__ void __launch_bounds__(256) k_es_keep(const UpdateJob *__restrict__ j
         const int64_t m = J.g.yc_ptr[n];
         const int64_t m64 = (m + 63) & ~(int64_t)63;
         uint64_t *const mask = es_mask(J);
-        // a wave covers 64 consecutive arcs (the stride is a multiple of 64)
+        // a wave covers 64 consecutive arcs (the stride is a multiple of 64).
+        // A tail outside the affected sources kept its row, so an arc of XC
+        // (the front of its head's YC segment: XC's pointers still hold the
+        // previous E*) stays without a test; the update's arcs, and the old
+        // copy of a lowered arc (whose tail's row did change), are tested.
         for (int64_t i = gid; i < m64; i += nthreads) {
             bool keep = false;
             if (i < m) {
                 const int32_t a = J.g.yc_src[i], b = J.g.yc_dst[i];
-                keep = J.g.D[(size_t)a * n + b] == J.g.yc_w[i];
+                const bool affected = (J.g.scal[a].flags & 2) != 0;
+                const bool from_xc = i - J.g.yc_ptr[b] < J.g.xc_ptr[b + 1] - J.g.xc_ptr[b];
+                keep = (!affected && from_xc) || J.g.D[(size_t)a * n + b] == J.g.yc_w[i];
             }
             const uint64_t word = __ballot(keep);
             if (lane_id() == 0) mask[i >> 6] = word;

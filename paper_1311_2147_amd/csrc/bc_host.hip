@@ -427,9 +427,9 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
     const StepPool pool = step_pool(ctx);
     if (part == 0) {
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, jobs, nj, pool);
-        hipLaunchKernelGGL(k_scan, dim3(g_elem), dim3(256), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_targets, dim3(g_elem), dim3(256), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_es_merge, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_scan, dim3(g_elem, L.njobs), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_targets, dim3(g_elem, L.njobs), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_merge, dim3(g_wave, L.njobs), dim3(256), 0, st, jobs, nj);
     } else if (part == 1) {
         hipLaunchKernelGGL(k_rows, dim3(ctx->rows_grid), dim3(256), 0, st, jobs, nj, ctx->big_b, pool);
     } else if (part == 2) {
@@ -455,10 +455,10 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
                            L.n_layout);
         HIPCHK(hipStreamWaitEvent(st, ctx->join_ev, 0));
     } else {
-        hipLaunchKernelGGL(k_es_keep, dim3(g_wave), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_es_keep, dim3(g_wave, L.njobs), dim3(256), 0, st, jobs, nj);
         hipLaunchKernelGGL(k_es_wscan, dim3(L.njobs), dim3(1024), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_es_place, dim3(g_wave), dim3(256), 0, st, jobs, nj);
-        hipLaunchKernelGGL(k_commit, dim3(g_elem), dim3(256), 0, st, jobs, nj, 0);
+        hipLaunchKernelGGL(k_es_place, dim3(g_wave, L.njobs), dim3(256), 0, st, jobs, nj);
+        hipLaunchKernelGGL(k_commit, dim3(g_elem, L.njobs), dim3(256), 0, st, jobs, nj, 0);
     }
     HIPCHK(hipGetLastError());
     return BC_OK;

@@ -97,7 +97,7 @@ __device__ int32_t block_excl_scan(int32_t x, int32_t *sh /* >= 32 */, int32_t &
 // compacted with a wave ballot and one atomic per wave.
 __global__ void __launch_bounds__(256) k_scan(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
     const int njobs = *njobs_p;
-    for (int j = 0; j < njobs; ++j) {
+    for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
         const int32_t n = J.g.n, v = J.v, n_in = J.n_in, n_out = J.n_out;
         const int32_t *D = J.g.D;
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) k_scan(const UpdateJob *__restrict__ jobs
 // candidates, INF32 elsewhere.
 __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p) {
     const int njobs = *njobs_p;
-    for (int j = 0; j < njobs; ++j) {
+    for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
         const int32_t n = J.g.n, v = J.v;
         const int32_t *D = J.g.D;
@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(256) k_es_merge(const UpdateJob *__restrict__ 
     const int njobs = *njobs_p;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int j = 0; j < njobs; ++j) {
+    for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
         if (job_dead(J)) continue;
         const int32_t n = J.g.n, nu = J.n_u;
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(256) k_es_keep(const UpdateJob *__restrict__ j
     const int njobs = *njobs_p;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int j = 0; j < njobs; ++j) {
+    for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
         if (job_dead(J)) continue;
         const int32_t n = J.g.n;
@@ -574,7 +574,7 @@ __global__ void __launch_bounds__(256) k_es_place(const UpdateJob *__restrict__ 
     const int njobs = *njobs_p;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    for (int j = 0; j < njobs; ++j) {
+    for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
         if (job_dead(J)) continue;
         const int32_t n = J.g.n;
@@ -2772,7 +2772,7 @@ __global__ void __launch_bounds__(256) k_wide_apply(const UpdateJob *__restrict_
 __global__ void __launch_bounds__(256) k_commit(const UpdateJob *__restrict__ jobs, const int32_t *__restrict__ njobs_p,
                                                 int32_t replace) {
     const int njobs = *njobs_p;
-    for (int j = 0; j < njobs; ++j) {
+    for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
         const int32_t n = J.g.n;
         for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {

@@ -90,3 +90,28 @@ def test_bad_requests_leave_the_state_unchanged():
     D1, S1 = c.rows()
     assert np.array_equal(D0, D1) and np.array_equal(S0, S1) and np.array_equal(bc0, c.scores())
     c.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17])
+def test_trivial_and_ragged_graphs(n):
+    """A lone vertex, a single arc, a path piece and a sparse graph with
+    unreachable pairs: insertions that connect pieces, then a vertex update."""
+    if n == 1:
+        g = W.Graph(1, True, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64))
+        c = start(g, threads=2)
+        check(c, g, "lone vertex")
+        c.close()
+        return
+    src = np.arange(0, n - 1, 2, dtype=np.int32)
+    g = W.Graph(n, True, src, src + 1, np.full(len(src), 5, np.int64))
+    c = start(g, threads=3)
+    cur = g
+    ups = [W.Update("edge", u=n - 1, v=0, w=2, insert=True)]
+    if n > 2:
+        ups.append(W.Update("edge", u=1, v=2, w=1, insert=True))
+        ups.append(W.Update("vertex", v=0, edges=[(0, n - 1, 3), (2, 0, 1)]))
+    for i, up in enumerate(ups):
+        c.update(up)
+        cur = W.apply_update(cur, up)
+        check(c, cur, f"n={n} #{i}")
+    c.close()

@@ -196,6 +196,12 @@ bc_status bc_recompute_estar(bc_ctx *ctx, bc_graph_id g);
  *   the tail of x's only DAG(s) in-arc (Eq.1 over E*), -2 if x has two or
  *   more, -1 at x == s and at vertices unreachable from s.  The walks use it
  *   in place of Eq.1 tests where it names one tail.
+ * bc_get_affected: the affected sources A of the graph's last update (the
+ *   sources whose row the update changes: Lemma 2 case 1 fails for them at
+ *   t = v, Section 3; for a vertex update the In and Out tests of Section 4),
+ *   in no particular order, from the last job when a vertex update with more
+ *   than 64 arcs per direction was split; cap entries at most (out may be
+ *   NULL when cap is 0), *cnt gets |A|.  Empty right after a load.
  * bc_state_hash: 128-bit hash of D and sigma (order-fixed, bit-exact).
  * bc_get_stats: counters of the last update (see bc_update_stats). */
 bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id g, int32_t s0, int32_t cnt, int64_t *D, uint64_t *sigma);
@@ -215,6 +221,7 @@ bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *a, int32_t 
 bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id g, int32_t *a, int32_t *b, int64_t *w, int64_t cap, int64_t *cnt);
 bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id g, int32_t s, double *out);
 bc_status bc_get_preds(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *out);
+bc_status bc_get_affected(bc_ctx *ctx, bc_graph_id g, int32_t *out, int64_t cap, int64_t *cnt);
 bc_status bc_state_hash(bc_ctx *ctx, bc_graph_id g, uint64_t out[2]);
 
 typedef struct {

@@ -109,6 +109,7 @@ _SIGS = {
     "bc_get_arcs": (_i32, [_P, _i32, _P, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_delta": (_i32, [_P, _i32, _i32, _P]),
     "bc_get_preds": (_i32, [_P, _i32, _i32, _P]),
+    "bc_get_affected": (_i32, [_P, _i32, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_state_hash": (_i32, [_P, _i32, _P]),
     "bc_get_stats": (_i32, [_P, _i32, ctypes.POINTER(bc_update_stats)]),
     "bc_get_timing": (_i32, [_P, ctypes.POINTER(bc_timing)]),
@@ -394,6 +395,16 @@ class Graph:
         out = np.empty(self.n, dtype=np.int32)
         self.ctx._check(_lib.bc_get_preds(self.ctx.h, self.gid, s, _np_ptr(out)), "bc_get_preds")
         return out
+
+    def affected(self) -> np.ndarray:
+        """bc_get_affected: the affected sources of the last update, sorted."""
+        cnt = ctypes.c_int64()
+        self.ctx._check(_lib.bc_get_affected(self.ctx.h, self.gid, None, 0, ctypes.byref(cnt)), "bc_get_affected")
+        k = cnt.value
+        out = np.empty(max(k, 1), dtype=np.int32)
+        self.ctx._check(_lib.bc_get_affected(self.ctx.h, self.gid, _np_ptr(out), k, ctypes.byref(cnt)),
+                        "bc_get_affected")
+        return np.sort(out[:k])
 
     def state_hash(self) -> tuple[int, int]:
         out = np.zeros(2, dtype=np.uint64)

@@ -164,7 +164,8 @@ struct bc_ctx {
     bool tev_pending[RING] = {};
     double step_ms = 0, source_ms = 0, rows_ms = 0;
     int64_t timed_steps = 0;
-    std::map<std::tuple<int, int, size_t, int, int>, StepGraph> graph_cache;
+    // captured step parts, keyed by everything their launches bake in
+    std::map<std::vector<int64_t>, StepGraph> graph_cache;
     // tickets
     uint64_t next_ticket = 1;
     std::map<uint64_t, hipEvent_t> tickets;
@@ -466,7 +467,29 @@ bc_status launch_update_part(bc_ctx *ctx, int r, const LaunchShape &L, int part)
 
 // Captured graph of one part, instantiated once per staging slot and shape.
 bc_status part_graph(bc_ctx *ctx, int r, const LaunchShape &L, int part, hipGraphExec_t *exec) {
-    auto key = std::make_tuple(r, L.njobs, L.slot_bytes, L.slots, L.src_lds_cap * 4 + part);
+    // every launch argument that comes from the shape (grid sizes from n_max,
+    // slot and region layouts from n_layout, bases and counts of the scratch
+    // plan) and the schedule fields read at launch are part of the key
+    const std::vector<int64_t> key = {r,
+                                      part,
+                                      L.njobs,
+                                      L.n_max,
+                                      L.n_layout,
+                                      L.slots,
+                                      (int64_t)L.slot_bytes,
+                                      L.src_lds_cap,
+                                      L.wide_slots,
+                                      (int64_t)L.wide_bytes,
+                                      L.wide_lds_cap,
+                                      L.item_regions,
+                                      (int64_t)(uintptr_t)L.src_base,
+                                      (int64_t)(uintptr_t)L.wide_base,
+                                      (int64_t)(uintptr_t)L.items_base,
+                                      ctx->block,
+                                      ctx->wide_block,
+                                      ctx->table,
+                                      ctx->big_b,
+                                      ctx->rows_grid};
     auto it = ctx->graph_cache.find(key);
     if (it == ctx->graph_cache.end()) {
         StepGraph sg;
@@ -1459,6 +1482,21 @@ bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id gid, int32_t s, int32_t *a, int32_
     if (k) {
         if (a) HIPCHK(hipMemcpyAsync(a, g->P.yc_src, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
         if (b) HIPCHK(hipMemcpyAsync(b, g->P.yc_dst, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return BC_OK;
+}
+
+bc_status bc_get_affected(bc_ctx *ctx, bc_graph_id gid, int32_t *out, int64_t cap, int64_t *cnt) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || !cnt || cap < 0 || (cap > 0 && !out)) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    unsigned long long a = 0;
+    HIPCHK(hipMemcpyAsync(&a, &g->P.ctl->affected_last, sizeof a, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *cnt = (int64_t)a;
+    const size_t k = (size_t)std::min<int64_t>(cap, (int64_t)a);
+    if (k) {
+        HIPCHK(hipMemcpyAsync(out, g->P.alist, 4 * k, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     return BC_OK;

@@ -50,6 +50,18 @@ __device__ __forceinline__ bool job_dead(const UpdateJob &J) {
     return (*(volatile int32_t *)&J.g.ctl->status & ST_ESTAR_CAP) != 0;
 }
 
+// A graph with any sticky error holds no valid state until it is recomputed:
+// the update kernels after the scan skip it (the bits only ever get set
+// during a step, so a kernel that skips a job is never followed by one that
+// runs it).
+__device__ __forceinline__ bool job_halted(const UpdateJob &J) {
+    return *(volatile int32_t *)&J.g.ctl->status != 0;
+}
+
+// Unreachable in the 64-bit sums of the scan kernels: far above every sum of
+// two finite 31-bit distances, so a finite candidate never equals it.
+constexpr int64_t INF64 = INT64_MAX / 4;
+
 // ------------------------------------------------------------ wave tools ---
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -111,14 +123,17 @@ __global__ void __launch_bounds__(256) k_scan(const UpdateJob *__restrict__ jobs
                 const int32_t *Ds = D + (size_t)s * n;
                 const uint64_t *Ss = S + (size_t)s * n;
                 const int32_t dsv = Ds[v];
-                int64_t cur = dsv;
+                // 64-bit sums with INF64 for unreachable: a candidate of 2^31-1
+                // or more is compared like any other and is an overflow only
+                // if it wins (it is then the new finite d'(s,v))
+                const int64_t d0 = dsv == INF32 ? INF64 : (int64_t)dsv;
+                int64_t cur = d0;
                 uint64_t sig = Ss[v], hat = 0;
                 for (int k = 0; k < n_in; ++k) {
                     const int32_t u = J.in_tail[k];
                     const int32_t du = Ds[u];
                     if (du == INF32) continue;
                     const int64_t c = (int64_t)du + J.in_w[k];
-                    if (c >= INF32) { ovf_d = true; continue; }
                     if (c == cur) {
                         const uint64_t su = Ss[u];
                         sig = add_chk(sig, su, ovf_s);
@@ -129,20 +144,30 @@ __global__ void __launch_bounds__(256) k_scan(const UpdateJob *__restrict__ jobs
                         hat = 0;
                     }
                 }
-                const bool same = (cur == (int64_t)dsv);
-                aff = (cur < (int64_t)dsv) || (hat != 0);
-                if (!aff && cur != INF32) {
+                if (cur != INF64 && cur >= INF32) {
+                    // d'(s,v) does not fit the distance matrix: the graph is
+                    // halted (sticky), s is left out
+                    ovf_d = true;
+                    cur = d0;
+                    hat = 0;
+                }
+                const bool same = (cur == d0);
+                aff = (cur < d0) || (hat != 0);
+                if (!aff && cur != INF64) {
                     for (int k = 0; k < n_out; ++k) {
                         const int32_t x = J.out_head[k];
-                        int64_t d1 = Ds[x];
+                        int64_t d1 = Ds[x] == INF32 ? INF64 : (int64_t)Ds[x];
                         const int32_t dvx = Dv[x];
                         if (dvx != INF32 && cur + dvx < d1) d1 = cur + dvx;
+                        // a candidate of 2^31-1 or more also marks s: the row
+                        // kernel's pair update decides with row v'' whether it
+                        // wins, and only then raises the overflow
                         const int64_t c = cur + J.out_w[k];
-                        if (c < INF32 && c <= d1) { aff = true; break; }
+                        if (c <= d1) { aff = true; break; }
                     }
                 }
                 SrcScal sc;
-                sc.dv = (int32_t)cur;
+                sc.dv = cur == INF64 ? INF32 : (int32_t)cur;
                 sc.flags = (same ? 1 : 0) | (aff ? 2 : 0);
                 sc.sv = sig;
                 sc.hv = hat;
@@ -213,7 +238,9 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
                     const uint64_t svt = S[(size_t)v * n + t];
                     J.g.rv_D[t] = dvt;
                     J.g.rv_S[t] = svt;
-                    int64_t c64 = dvt;
+                    // 64-bit sums with INF64 for unreachable, as in k_scan:
+                    // only a winning candidate of 2^31-1 or more overflows
+                    int64_t c64 = dvt == INF32 ? INF64 : (int64_t)dvt;
                     uint64_t sig = svt, hat = 0;
                     for (int k = 0; k < J.n_out; ++k) {
                         const int32_t x = J.out_head[k];
@@ -223,6 +250,8 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
                         bool s1_known = false;
                         int64_t c;
                         if (in_rule(d1, sc.dv, dvt, c)) {
+                            // in_rule takes c only where it is shortest: a
+                            // c of 2^31-1 or more is a real overflow of (x,t)
                             if (c >= INF32) { ovf_d = true; }
                             else if (c < d1) { d1 = (int32_t)c; s1 = mul_chk(sc.sv, svt, ovf_s); s1_known = true; }
                             else {
@@ -233,7 +262,6 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
                         }
                         if (d1 == INF32) continue;
                         const int64_t cc = (int64_t)J.out_w[k] + d1;
-                        if (cc >= INF32) { ovf_d = true; continue; }
                         if (cc <= c64) {
                             if (!s1_known) s1 = S[(size_t)x * n + t];
                             if (cc == c64) {
@@ -246,7 +274,13 @@ __global__ void __launch_bounds__(256) k_targets(const UpdateJob *__restrict__ j
                             }
                         }
                     }
-                    cur = (int32_t)c64;
+                    if (c64 != INF64 && c64 >= INF32) {
+                        // d''(v,t) does not fit: the graph is halted (sticky)
+                        ovf_d = true;
+                        c64 = INF64;
+                        hat = 0;
+                    }
+                    cur = c64 == INF64 ? INF32 : (int32_t)c64;
                     J.g.rvv_D[t] = cur;
                     J.g.rvv_S[t] = sig;
                     J.g.rvv_H[t] = hat;
@@ -457,7 +491,7 @@ __global__ void __launch_bounds__(256) k_es_merge(const UpdateJob *__restrict__ 
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
-        if (job_dead(J)) continue;
+        if (job_halted(J)) continue;
         const int32_t n = J.g.n, nu = J.n_u;
         const int32_t *__restrict__ ptr = J.g.xc_ptr;
         const int32_t m = ptr[n];
@@ -508,7 +542,7 @@ __global__ void __launch_bounds__(256) k_es_keep(const UpdateJob *__restrict__ j
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
-        if (job_dead(J)) continue;
+        if (job_halted(J)) continue;
         const int32_t n = J.g.n;
         const int64_t m = J.g.yc_ptr[n];
         const int64_t m64 = (m + 63) & ~(int64_t)63;
@@ -537,7 +571,7 @@ __global__ void __launch_bounds__(1024) k_es_wscan(const UpdateJob *__restrict__
     const int j = blockIdx.x;
     if (j >= *njobs_p) return;
     const UpdateJob &J = jobs[j];
-    if (job_dead(J)) return;
+    if (job_halted(J)) return;
     const int64_t m = J.g.yc_ptr[J.g.n];
     const int32_t words = (int32_t)((m + 63) >> 6);
     const uint64_t *const mask = es_mask(J);
@@ -576,7 +610,7 @@ __global__ void __launch_bounds__(256) k_es_place(const UpdateJob *__restrict__ 
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     for (int j = blockIdx.y; j < njobs; j += gridDim.y) {  // a row of blocks per job
         const UpdateJob &J = jobs[j];
-        if (job_dead(J)) continue;
+        if (job_halted(J)) continue;
         const int32_t n = J.g.n;
         const int64_t m = J.g.yc_ptr[n];
         const uint64_t *const mask = es_mask(J);
@@ -2389,7 +2423,7 @@ __global__ void __launch_bounds__(256) k_rows(const UpdateJob *__restrict__ jobs
     const BList L{lt, ld, ls, min(big_b, LCAP)};
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (job_dead(J)) continue;
+        if (job_halted(J)) continue;
         GraphCtl *ctl = J.g.ctl;
         const int32_t n = J.g.n;
         const int32_t count = *(volatile int32_t *)&ctl->a_count;
@@ -2543,7 +2577,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     const USlot u = uslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (job_dead(J)) continue;
+        if (job_halted(J)) continue;
         GraphCtl *ctl = J.g.ctl;
         const int32_t n = J.g.n;
         const bool lds = n <= lds_cap;
@@ -2607,12 +2641,17 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
     int32_t region0 = 0;  // first item region of the job
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (job_dead(J)) continue;
         GraphCtl *ctl = J.g.ctl;
         const int32_t n = J.g.n;
         const bool lds = n <= lds_cap;
+        // the item regions of a job follow those of the jobs before it, halted
+        // or not (k_wide_apply counts them the same way)
         const int32_t count = *(volatile int32_t *)&ctl->big_count;
         const int32_t paired = min(count, item_regions - region0);
+        if (job_halted(J)) {
+            region0 += paired;
+            continue;
+        }
         const int32_t units = 2 * paired + (count - paired);
         const RowV R = row_v_of(J);
         const int32_t t_count = *(volatile int32_t *)&ctl->t_count;
@@ -2723,10 +2762,15 @@ __global__ void __launch_bounds__(256) k_wide_apply(const UpdateJob *__restrict_
     int32_t region0 = 0;
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
-        if (job_dead(J)) continue;
         const int32_t n = J.g.n;
         const int32_t count = *(volatile int32_t *)&J.g.ctl->big_count;
         const int32_t paired = min(count, item_regions - region0);
+        // a job halted since (or before) the wide kernel ran gets no writes;
+        // its regions are still counted, as in k_source_wide
+        if (job_halted(J)) {
+            region0 += paired;
+            continue;
+        }
         // a group of gridDim / paired workgroups (at least one) per source,
         // sharing its changed pairs (a few sources can hold tens of thousands
         // each), four in flight per lane
@@ -2859,6 +2903,10 @@ __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ job
         __syncthreads();
         const int32_t s = sh.item;
         if (s >= n) break;
+        // a relaxation whose sum reaches 2^31-1 is dropped; it overflows only
+        // if nothing shorter ever reaches its head, which the check after the
+        // search settles (long candidates that lose are no error)
+        bool long_cand = false;
         int32_t *Dg = J.g.D + (size_t)s * n;
         int32_t *row = lds ? lds_row : Dg;
         int32_t *flag = sl.indeg;
@@ -2883,7 +2931,7 @@ __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ job
                 for (int32_t e = J.g.arc_ptr[a]; e < e1; ++e) {
                     const int32_t b = J.g.arc_dst[e];
                     const int64_t nd = (int64_t)da + J.g.arc_w[e];
-                    if (nd >= INF32) { ovf = true; continue; }
+                    if (nd >= INF32) { long_cand = true; continue; }
                     if ((int32_t)nd < __atomic_load_n(&row[b], __ATOMIC_RELAXED)) {
                         const int32_t old = atomicMin(&row[b], (int32_t)nd);
                         if ((int32_t)nd < old && atomicExch(&flag[b], 1) == 0) {
@@ -2905,6 +2953,17 @@ __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ job
             cur = nxt;
             nxt = tmp;
             __syncthreads();
+        }
+        if (__syncthreads_or(long_cand)) {
+            // converged: a vertex still unreached that has an arc from a
+            // reached one is reachable, and every path to it is 2^31-1 or
+            // longer
+            for (int32_t a = tid; a < n; a += bs) {
+                if (__atomic_load_n(&row[a], __ATOMIC_RELAXED) == INF32) continue;
+                const int32_t e1 = J.g.arc_ptr[a + 1];
+                for (int32_t e = J.g.arc_ptr[a]; e < e1; ++e)
+                    if (__atomic_load_n(&row[J.g.arc_dst[e]], __ATOMIC_RELAXED) == INF32) ovf = true;
+            }
         }
         if (lds)
             for (int32_t i = tid; i < n; i += bs) Dg[i] = row[i];

@@ -168,6 +168,53 @@ def test_sigma_overflow_at_35x35_grid_but_not_34x34():
         oracle.brandes(W.grid_graph(35, 35), rows=False)
 
 
+def _directed_grid(r, heavy=()):
+    src, dst, w = [], [], []
+    for i in range(r):
+        for j in range(r):
+            v = i * r + j
+            for (ii, jj) in ((i, j + 1), (i + 1, j)):
+                if ii < r and jj < r:
+                    u = ii * r + jj
+                    src.append(v)
+                    dst.append(u)
+                    w.append(2 if (v, u) in heavy else 1)
+    return W.Graph(r * r, True, np.asarray(src, np.int32), np.asarray(dst, np.int32), np.asarray(w, np.int64))
+
+
+def test_sigma_overflow_after_lowering_the_corner_arc_of_a_directed_grid():
+    """Right/down unit grid 35 x 35 whose last arc into the far corner has
+    weight 2: every shortest path to the corner comes through its left
+    neighbour, C(67,33) of them (below 2^64); at weight 1 both neighbours
+    count, C(68,34) > 2^64 - 1.  A shortcut from the first to the last vertex
+    brings every count back below 2^64."""
+    r = 35
+    corner = ((r - 2) * r + r - 1, r * r - 1)
+    g = _directed_grid(r, heavy={corner})
+    s = oracle.source(g, 0)
+    assert int(s["sigma"][r * r - 1]) == math.comb(67, 33) < 2**64
+    assert s["D"][r * r - 1] == 2 * (r - 1)
+    low = W.apply_update(g, W.Update("edge", u=corner[0], v=corner[1], w=1))
+    assert math.comb(68, 34) >= 2**64
+    with pytest.raises(oracle.SigmaOverflow):
+        oracle.brandes(low, rows=False)
+    fixed = W.apply_update(low, W.Update("edge", u=0, v=r * r - 1, w=1))
+    ref = oracle.brandes(fixed)
+    assert int(ref["sigma"][0, r * r - 1]) == 1 and ref["D"][0, r * r - 1] == 1
+
+
+def test_distances_past_31_bits_are_exact_int64():
+    """The oracle keeps 64-bit distances: 0->1 at 2^31 - 2 and 1->2 at 5
+    give d(0,2) = 2^31 + 3, and a shorter arc wins over that candidate."""
+    big = 2**31 - 2
+    g = W.Graph(3, True, np.asarray([0, 1], np.int32), np.asarray([1, 2], np.int32), np.asarray([big, 5], np.int64))
+    ref = oracle.brandes(g)
+    assert ref["D"][0, 2] == big + 5 and ref["D"][0, 1] == big
+    h = W.apply_update(g, W.Update("edge", u=0, v=2, w=1))
+    ref = oracle.brandes(h)
+    assert ref["D"][0, 2] == 1 and int(ref["sigma"][0, 2]) == 1
+
+
 # ------------------------------------------------ independent recomputations
 
 

@@ -220,6 +220,24 @@ bc_status bc_get_arcs(bc_ctx *ctx, bc_graph_id g, int32_t *src, int32_t *dst, in
 bc_status bc_get_dag(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *a, int32_t *b, int64_t cap, int64_t *cnt);
 bc_status bc_get_estar(bc_ctx *ctx, bc_graph_id g, int32_t *a, int32_t *b, int64_t *w, int64_t cap, int64_t *cnt);
 bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id g, int32_t s, double *out);
+
+/* bc_get_delta for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the same
+ * dependency row delta_s.(.) (Eq.4 summed over every reachable target, 0 at
+ * s and at unreachable vertices), written to out_dev[0..n), caller-owned
+ * device memory of n doubles, by one kernel enqueued on the context's stream.
+ * It allocates nothing and uses no caller workspace: its work area is a fixed
+ * array in the library's device image (one wide-kernel slot, about 3.5 MB,
+ * held by every device the library runs on until the process ends), resolved
+ * once per device at bc_create.  It does not synchronise; the row is there
+ * once the stream reaches it, and device errors surface at the next
+ * synchronising call.  Graphs of up to 32768 vertices; a larger one returns
+ * BC_ERR_CAPACITY and enqueues nothing.  Every call on one device shares the
+ * array: calls that can overlap on the device (other contexts' streams on the
+ * same GPU) race and must be ordered by the caller.
+ * Errors: BC_ERR_INVALID_ARG (no such graph, s out of range, null out_dev),
+ * BC_ERR_CAPACITY. */
+bc_status bc_get_delta_noalloc(bc_ctx *ctx, bc_graph_id g, int32_t s, double *out_dev);
 bc_status bc_get_preds(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *out);
 bc_status bc_get_affected(bc_ctx *ctx, bc_graph_id g, int32_t *out, int64_t cap, int64_t *cnt);
 bc_status bc_state_hash(bc_ctx *ctx, bc_graph_id g, uint64_t out[2]);

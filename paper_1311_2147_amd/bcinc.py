@@ -108,6 +108,7 @@ _SIGS = {
     "bc_get_estar": (_i32, [_P, _i32, _P, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_arcs": (_i32, [_P, _i32, _P, _P, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_get_delta": (_i32, [_P, _i32, _i32, _P]),
+    "bc_get_delta_noalloc": (_i32, [_P, _i32, _i32, _P]),
     "bc_get_preds": (_i32, [_P, _i32, _i32, _P]),
     "bc_get_affected": (_i32, [_P, _i32, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_state_hash": (_i32, [_P, _i32, _P]),
@@ -389,6 +390,14 @@ class Graph:
         out = np.empty(self.n, dtype=np.float64)
         self.ctx._check(_lib.bc_get_delta(self.ctx.h, self.gid, s, _np_ptr(out)), "bc_get_delta")
         return out
+
+    def delta_noalloc(self, s: int, out_dev) -> None:
+        """bc_get_delta_noalloc: enqueues the dependency row of s into out_dev
+        (a float64 device tensor of n entries); no synchronisation."""
+        if out_dev.dtype != torch.float64 or not out_dev.is_cuda or out_dev.numel() < self.n:
+            raise ValueError("out_dev must be a float64 device tensor of n entries")
+        self.ctx._check(_lib.bc_get_delta_noalloc(self.ctx.h, self.gid, s, ctypes.c_void_p(out_dev.data_ptr())),
+                        "bc_get_delta_noalloc")
 
     def preds(self, s: int) -> np.ndarray:
         """bc_get_preds: stored DAG(s) predecessor per vertex (-1 none, -2 several)."""

@@ -161,7 +161,7 @@ struct UpdateJob {
     int32_t u_tail[2 * KMAX], u_head[2 * KMAX], u_w[2 * KMAX];
 };
 
-__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+__host__ __device__ constexpr inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Per-workgroup scratch of the static pass (Kahn levels over a whole DAG).
 struct StaticLayout {
@@ -222,8 +222,8 @@ struct WideLayout {
     int64_t kcap;
 };
 
-__host__ __device__ inline WideLayout wide_layout(int32_t n) {
-    WideLayout L;
+__host__ __device__ constexpr inline WideLayout wide_layout(int32_t n) {
+    WideLayout L{};
     size_t off = 0;
     L.kcap = (int64_t)KARC_PER_VERTEX * n;
     L.outdeg = off; off += align256(sizeof(int32_t) * (size_t)n);

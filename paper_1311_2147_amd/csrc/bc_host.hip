@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <unordered_map>
@@ -24,6 +25,14 @@
 using namespace bcinc;
 
 namespace {
+// size of the fixed scratch array below (one wide-kernel slot, n <= 32768)
+constexpr size_t FIXED_BYTES = wide_layout(32768).total;
+}  // namespace
+
+// Fixed device scratch of bc_get_delta_noalloc (see fixed_scratch_setup).
+static __device__ __align__(256) char bc_fixed_scratch[FIXED_BYTES];
+
+namespace {
 
 constexpr int RING = 4;            // job staging slots in flight
 constexpr int JCAP = 256;          // jobs per staging slot
@@ -33,6 +42,20 @@ constexpr int WIDE_SLOTS_MAX = 256; // wide-kernel slots: one per CU
 constexpr int DEFAULT_BLOCK = 256;  // 4 waves per affected source
 constexpr int DEFAULT_WIDE_BLOCK = 512;
 constexpr int64_t W_MAX = (int64_t)INF32 - 1;
+
+// Fixed scratch of the allocation-free entry point (bc_get_delta_noalloc):
+// one wide-kernel work slot laid out for graphs of up to FIXED_N_MAX vertices,
+// in the library's device image.  Each device holds its own copy until the
+// process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device (the array's name in host code
+// is not a device address).
+constexpr int32_t FIXED_N_MAX = 32768;
+constexpr size_t FIXED_SCRATCH_BYTES = wide_layout(FIXED_N_MAX).total;
+static_assert(FIXED_SCRATCH_BYTES == FIXED_BYTES, "fixed scratch sized for another n");
+constexpr int FIXED_MAX_DEVICES = 64;
+
+std::mutex fixed_mu;
+void *fixed_addr[FIXED_MAX_DEVICES] = {};  // per device, resolved once
 
 size_t ring_slot_bytes() { return align256(256 + sizeof(UpdateJob) * JCAP); }
 size_t ring_bytes() { return RING * ring_slot_bytes(); }
@@ -170,6 +193,8 @@ struct bc_ctx {
     uint64_t next_ticket = 1;
     std::map<uint64_t, hipEvent_t> tickets;
     std::vector<hipEvent_t> spare_events;
+    // this device's copy of the fixed scratch array (see bc_fixed_scratch)
+    char *fixed_scratch = nullptr;
 };
 
 namespace {
@@ -824,6 +849,26 @@ bc_status set_lds_limit(bc_ctx *ctx, const void *fn, size_t *limit = nullptr) {
     return BC_OK;
 }
 
+// Resolves this device's address of the fixed scratch array, once per
+// device (the context's device is current), and zeroes the array then: the
+// dependency pass run in it keeps its counters at zero after every use.
+bc_status fixed_scratch_setup(bc_ctx *ctx) {
+    if (ctx->device < 0 || ctx->device >= FIXED_MAX_DEVICES)
+        return fail(ctx, BC_ERR_NO_DEVICE, "device ordinal above the fixed scratch table");
+    std::lock_guard<std::mutex> lock(fixed_mu);
+    if (!fixed_addr[ctx->device]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(bc_fixed_scratch)));
+        if (!p) return fail(ctx, BC_ERR_HIP, "hipGetSymbolAddress returned no address");
+        hipLaunchKernelGGL(k_zero_fill, dim3(256), dim3(256), 0, ctx->stream, (char *)p, FIXED_SCRATCH_BYTES);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        fixed_addr[ctx->device] = p;
+    }
+    ctx->fixed_scratch = (char *)fixed_addr[ctx->device];
+    return BC_OK;
+}
+
 bc_status set_lds_limits(bc_ctx *ctx) {
     bc_status st;
     if ((st = set_lds_limit(ctx, (const void *)k_source<256>))) return st;
@@ -831,6 +876,7 @@ bc_status set_lds_limits(bc_ctx *ctx) {
     if ((st = set_lds_limit(ctx, (const void *)k_source_wide, &ctx->wide_lds_limit))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_sssp))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_static))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_delta_row_byval))) return st;
     return set_lds_limit(ctx, (const void *)k_delta_row);
 }
 
@@ -961,6 +1007,11 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
     if (e != hipSuccess) return bail(e, "hipMemsetAsync");
     e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return bail(e, "hipStreamSynchronize");
+    if (fixed_scratch_setup(ctx) != BC_OK) {
+        fprintf(stderr, "bcinc: %s\n", ctx->last_error.c_str());
+        delete ctx;
+        return BC_ERR_HIP;
+    }
     *out = ctx;
     return BC_OK;
 }
@@ -1530,6 +1581,22 @@ bc_status bc_get_delta(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
     if ((st = ring_release(ctx, r))) return st;
     HIPCHK(hipMemcpyAsync(out, row, 8 * (size_t)g->n, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BC_OK;
+}
+
+bc_status bc_get_delta_noalloc(bc_ctx *ctx, bc_graph_id gid, int32_t s, double *out) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g || s < 0 || s >= g->n || !out) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments");
+    if (g->n > FIXED_N_MAX)
+        return fail(ctx, BC_ERR_CAPACITY, "graph has more vertices than the fixed scratch serves (32768)");
+    if (!ctx->fixed_scratch) return fail(ctx, BC_ERR_HIP, "fixed scratch not resolved on this device");
+    // the same pass as bc_get_delta, in the fixed slot laid out for the
+    // largest n it serves (its zero-kept arrays then sit at fixed offsets for
+    // every graph), the graph's pointers passed by value
+    const int lds = std::min<int32_t>(g->n, 28672);
+    hipLaunchKernelGGL(k_delta_row_byval, dim3(1), dim3(1024), source_lds_bytes(lds, 1024, 0), ctx->stream, g->P, s,
+                       ctx->fixed_scratch, lds, FIXED_N_MAX, out);
+    HIPCHK(hipGetLastError());
     return BC_OK;
 }
 

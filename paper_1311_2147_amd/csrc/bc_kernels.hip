@@ -3011,19 +3011,19 @@ __global__ void k_reset_work(GraphCtl *ctl) {
 
 // Dependency row of one source, delta_s.(x) = sum over all reachable t of
 // delta_st(x), by the same restricted pass with B = every reachable t != s.
-// Writes the row to out_row (n values, 0 at s and at unreachable x).
-__global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict__ jobs, int32_t s, char *__restrict__ scratch,
-                                                    int32_t lds_cap, int32_t n_layout, double *out_row) {
+// Writes the row to out_row (n values, 0 at s and at unreachable x).  One
+// workgroup; `scratch` is one wide-kernel slot laid out for n_layout >= n.
+__device__ __forceinline__ void delta_row(const GraphPtrs &G, int32_t s, char *__restrict__ scratch, int32_t lds_cap,
+                                          int32_t n_layout, double *out_row) {
     extern __shared__ __align__(16) char dyn_lds[];
     int32_t *const lds_row = (int32_t *)dyn_lds;
     const ExpandShared es = expand_at(dyn_lds, lds_cap);
     __shared__ BlockShared sh;
-    const UpdateJob &J = jobs[0];
-    const int32_t n = J.g.n;
+    const int32_t n = G.n;
     const bool lds = n <= lds_cap;
     const USlot u = wslot_at(scratch, n_layout);
-    if (job_dead(J)) return;
-    const int32_t *Dg = J.g.D + (size_t)s * n;
+    if ((*(volatile int32_t *)&G.ctl->status & ST_ESTAR_CAP) != 0) return;
+    const int32_t *Dg = G.D + (size_t)s * n;
     const int32_t *Drow = Dg;
     if (threadIdx.x == 0) sh.nb = 0;
     __syncthreads();
@@ -3034,8 +3034,28 @@ __global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict_
     }
     if (lds) Drow = lds_row;
     __syncthreads();
-    restricted_pass<true, XU>(s, n, Drow, J.g.S + (size_t)s * n, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, u.bl_t,
-                          sh.nb, true, u, 1.0, out_row, nullptr, nullptr, false, sh, es);
+    restricted_pass<true, XU>(s, n, Drow, G.S + (size_t)s * n, G.xc_ptr, G.xc_src, G.xc_dst, G.xc_w, u.bl_t, sh.nb,
+                              true, u, 1.0, out_row, nullptr, nullptr, false, sh, es);
+}
+
+__global__ void __launch_bounds__(1024) k_delta_row(const UpdateJob *__restrict__ jobs, int32_t s, char *__restrict__ scratch,
+                                                    int32_t lds_cap, int32_t n_layout, double *out_row) {
+    delta_row(jobs[0].g, s, scratch, lds_cap, n_layout, out_row);
+}
+
+// The same with the graph's pointers passed by value (no staged job) and the
+// slot in the caller-supplied scratch address (the library's fixed array).
+__global__ void __launch_bounds__(1024) k_delta_row_byval(const GraphPtrs G, int32_t s, char *__restrict__ scratch,
+                                                          int32_t lds_cap, int32_t n_layout, double *out_row) {
+    delta_row(G, s, scratch, lds_cap, n_layout, out_row);
+}
+
+// Zero fill of a byte range (the fixed scratch array at set-up).
+__global__ void __launch_bounds__(256) k_zero_fill(char *__restrict__ p, size_t bytes) {
+    const size_t words = bytes / 8;
+    uint64_t *q = (uint64_t *)p;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        q[i] = 0;
 }
 
 // Arcs of DAG(s): the predicate of Eq.1 over E*.

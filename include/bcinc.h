@@ -155,16 +155,52 @@ typedef struct {
     int32_t u, v;
     int64_t w;
     int32_t k;
-    const bc_edge *edges;  /* host pointer, k entries, read during bc_submit only */
+    const bc_edge *edges;  /* host pointer, k entries, read during the call only */
 } bc_request;
 
 bc_status bc_submit(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *ticket, int32_t *bad_index);
-/* *done = 1 once every step of the ticket has finished on the device. */
-bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, int32_t *done);
+
+/* Continuous batching.  bc_enqueue validates requests like bc_submit (none is
+ * taken if one fails) and appends each to its graph's queue without
+ * launching anything; tickets[i] identifies request i.  bc_step launches one
+ * step: the head request of every graph with a non-empty queue, oldest head
+ * first, at most max_jobs of them (0 = 256), all in one batched launch
+ * sequence (the same kernels and captured graphs as bc_submit); *launched
+ * gets the number of requests in it, 0 when every queue is empty.  If
+ * step_ticket is not NULL it gets a ticket of the step itself (poll it to
+ * learn when the step finishes).  A queued request changes no device state
+ * until a step launches it; bc_wait on its ticket, bc_sync, and every call
+ * that enqueues work directly or acts on a graph's state (bc_update_*,
+ * bc_submit, bc_clone_graph, bc_free_graph, bc_recompute*, bc_autotune)
+ * first launch every queued request, so the device applies requests in the
+ * order they were validated.  Introspection calls and bc_scores see the
+ * state of the steps launched so far. */
+bc_status bc_enqueue(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *tickets, int32_t *bad_index);
+bc_status bc_step(bc_ctx *ctx, int32_t max_jobs, int32_t *launched, uint64_t *step_ticket);
+
+/* Result of a ticket.  Times are nanoseconds of the host's CLOCK_MONOTONIC:
+ * t_enqueue_ns is read on the host when the ticket was issued; t_start_ns and
+ * t_finish_ns are device timestamps (HIP timing events recorded on the
+ * context's stream before the first step that ran the ticket's requests and
+ * after the last one) mapped to that clock through an event on an idle
+ * stream of the library, to within tens of microseconds. */
+typedef struct {
+    int32_t done;          /* 1 once every step of the ticket has finished on the device */
+    int32_t status;        /* when done: BC_OK, or the sticky error of one of its graphs */
+    int64_t t_enqueue_ns;
+    int64_t t_start_ns;    /* when done */
+    int64_t t_finish_ns;   /* when done */
+} bc_result;
+
+/* bc_poll fills *out without waiting.  Once it reports done the ticket is
+ * collected: polling it again reports done with status BC_OK and zero times.
+ * bc_wait launches the ticket's queued requests if any, waits for its last
+ * step and collects it. */
+bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, bc_result *out);
 bc_status bc_wait(bc_ctx *ctx, uint64_t ticket);
 
-/* Waits for all work of the context; returns the first sticky error of any
- * graph, or BC_OK. */
+/* Launches every queued request, waits for all work of the context, and
+ * returns the first sticky error of any graph, or BC_OK. */
 bc_status bc_sync(bc_ctx *ctx);
 
 /* BC(v) for all v (Eq.3 over ordered pairs) into host memory out[0..n).

@@ -68,6 +68,11 @@ class bc_update_stats(ctypes.Structure):
                 ("total_scan_bytes", ctypes.c_int64)]
 
 
+class bc_result(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("t_enqueue_ns", ctypes.c_int64),
+                ("t_start_ns", ctypes.c_int64), ("t_finish_ns", ctypes.c_int64)]
+
+
 class bc_timing(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_double), ("source_ms", ctypes.c_double), ("steps", ctypes.c_int64),
                 ("rows_ms", ctypes.c_double)]
@@ -97,7 +102,9 @@ _SIGS = {
     "bc_update_edge": (_i32, [_P, _i32, _i32, _i32, _i64]),
     "bc_update_vertex": (_i32, [_P, _i32, _i32, _i32, ctypes.POINTER(bc_edge)]),
     "bc_submit": (_i32, [_P, _i32, ctypes.POINTER(bc_request), ctypes.POINTER(_u64), ctypes.POINTER(_i32)]),
-    "bc_poll": (_i32, [_P, _u64, ctypes.POINTER(_i32)]),
+    "bc_enqueue": (_i32, [_P, _i32, ctypes.POINTER(bc_request), ctypes.POINTER(_u64), ctypes.POINTER(_i32)]),
+    "bc_step": (_i32, [_P, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_u64)]),
+    "bc_poll": (_i32, [_P, _u64, ctypes.POINTER(bc_result)]),
     "bc_wait": (_i32, [_P, _u64]),
     "bc_sync": (_i32, [_P]),
     "bc_scores": (_i32, [_P, _i32, _P]),
@@ -255,10 +262,37 @@ class Context:
             raise BcError(rc, f"bc_submit (request {bad.value}): {_lib.bc_last_error(self.h).decode()}")
         return ticket.value
 
-    def poll(self, ticket: int) -> bool:
-        done = ctypes.c_int32()
-        self._check(_lib.bc_poll(self.h, ticket, ctypes.byref(done)), "bc_poll")
-        return bool(done.value)
+    def enqueue(self, requests) -> list[int]:
+        """bc_enqueue of [(graph, update)]: one ticket per request; nothing
+        runs until a step launches it."""
+        reqs, keep = self._requests(requests)
+        tickets = (ctypes.c_uint64 * max(len(requests), 1))()
+        bad = ctypes.c_int32(-1)
+        rc = _lib.bc_enqueue(self.h, len(requests), reqs, tickets, ctypes.byref(bad))
+        if rc != BC_OK:
+            raise BcError(rc, f"bc_enqueue (request {bad.value}): {_lib.bc_last_error(self.h).decode()}")
+        del keep
+        return [int(tickets[i]) for i in range(len(requests))]
+
+    def step(self, max_jobs: int = 0, want_ticket: bool = False):
+        """bc_step: launches the head request of every queued graph; returns
+        the number launched (and the step's ticket when asked)."""
+        launched = ctypes.c_int32()
+        st = ctypes.c_uint64()
+        self._check(_lib.bc_step(self.h, max_jobs, ctypes.byref(launched), ctypes.byref(st) if want_ticket else None),
+                    "bc_step")
+        return (launched.value, int(st.value)) if want_ticket else launched.value
+
+    def poll(self, ticket: int):
+        """bc_poll: None while the ticket runs, then its result (status and
+        CLOCK_MONOTONIC nanoseconds: enqueue on the host, start and finish
+        stamped on the device)."""
+        r = bc_result()
+        self._check(_lib.bc_poll(self.h, ticket, ctypes.byref(r)), "bc_poll")
+        if not r.done:
+            return None
+        return {"status": STATUS_NAMES.get(r.status, r.status), "t_enqueue_ns": r.t_enqueue_ns,
+                "t_start_ns": r.t_start_ns, "t_finish_ns": r.t_finish_ns}
 
     def wait(self, ticket: int):
         self._check(_lib.bc_wait(self.h, ticket), "bc_wait")

@@ -6,9 +6,12 @@
 // sequence (directly for single updates, replayed from a captured HIP graph
 // for batched steps) and introspection copies.  All arithmetic of the method
 // runs in the kernels of bc_kernels.hip.
+#include <time.h>
+
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -42,6 +45,8 @@ constexpr int WIDE_SLOTS_MAX = 256; // wide-kernel slots: one per CU
 constexpr int DEFAULT_BLOCK = 256;  // 4 waves per affected source
 constexpr int DEFAULT_WIDE_BLOCK = 512;
 constexpr int64_t W_MAX = (int64_t)INF32 - 1;
+constexpr int STATUS_BATCH = 256;   // graph status words read back per copy batch
+constexpr int64_t CLOCK_REFRESH_NS = 10000000000ll;  // re-map the device clock after 10 s
 
 // Fixed scratch of the allocation-free entry point (bc_get_delta_noalloc):
 // one wide-kernel work slot laid out for graphs of up to FIXED_N_MAX vertices,
@@ -141,6 +146,37 @@ struct StepGraph {
     hipGraphExec_t exec = nullptr;
 };
 
+// Timing events recorded on the stream around one update step (before its
+// staging copy, after its last kernel); tickets whose requests ran in the
+// step hold references to them.
+struct StepEvents {
+    hipEvent_t begin = nullptr, end = nullptr;
+    int refs = 0;
+};
+
+// A submission (bc_submit), a queued request (bc_enqueue) or a step
+// (bc_step): its first and last step's events, the graphs it touched, and
+// its jobs not launched yet.
+struct Ticket {
+    int64_t t_enqueue_ns = 0;
+    StepEvents *first = nullptr, *last = nullptr;
+    std::vector<int32_t> graphs;
+    int32_t jobs_queued = 0;
+};
+
+// A job waiting in its graph's FIFO for bc_step.
+struct QueuedJob {
+    UpdateJob job;
+    uint64_t ticket;
+    uint64_t seq;  // enqueue order over all graphs
+};
+
+int64_t monotonic_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
+}
+
 }  // namespace
 
 struct bc_ctx {
@@ -189,10 +225,20 @@ struct bc_ctx {
     int64_t timed_steps = 0;
     // captured step parts, keyed by everything their launches bake in
     std::map<std::vector<int64_t>, StepGraph> graph_cache;
-    // tickets
+    // tickets, the step events they refer to, and the FIFOs of queued jobs
     uint64_t next_ticket = 1;
-    std::map<uint64_t, hipEvent_t> tickets;
-    std::vector<hipEvent_t> spare_events;
+    std::map<uint64_t, Ticket> tickets;
+    std::vector<StepEvents *> spare_steps;
+    std::map<int32_t, std::deque<QueuedJob>> queues;
+    uint64_t queue_seq = 0;
+    int64_t queued_jobs = 0;
+    // device clock against CLOCK_MONOTONIC: clock_ev completed at host time
+    // clock_ns (within half of clock_span_ns); recorded on a stream of its
+    // own, which never waits for update work
+    hipStream_t clock_stream = nullptr;
+    hipEvent_t clock_ev = nullptr;
+    int64_t clock_ns = 0, clock_span_ns = 0;
+    int32_t *h_status = nullptr;  // pinned: graph status words read back for results
     // this device's copy of the fixed scratch array (see bc_fixed_scratch)
     char *fixed_scratch = nullptr;
 };
@@ -558,12 +604,13 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     return BC_OK;
 }
 
-bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_graph) {
+bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_graph, StepEvents *se = nullptr) {
     LaunchShape L;
     bc_status st = shape_for(ctx, jobs, &L);
     if (st) return st;
     int r;
     if ((st = ring_acquire(ctx, &r))) return st;
+    if (se) HIPCHK(hipEventRecord(se->begin, ctx->stream));
     if ((st = ring_stage(ctx, r, jobs))) return st;
     const bool timed = ctx->timing;
     // timing events sit on the stream between the parts (never inside a graph)
@@ -579,7 +626,139 @@ bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_gra
     }
     if (timed) HIPCHK(hipEventRecord(ctx->tev[r][4], ctx->stream));
     if (timed) ctx->tev_pending[r] = true;
+    if (se) HIPCHK(hipEventRecord(se->end, ctx->stream));
     return ring_release(ctx, r);
+}
+
+// Step events from the pool (timing-enabled events; created on first use).
+bc_status take_step_events(bc_ctx *ctx, StepEvents **out) {
+    StepEvents *se;
+    if (!ctx->spare_steps.empty()) {
+        se = ctx->spare_steps.back();
+        ctx->spare_steps.pop_back();
+    } else {
+        se = new StepEvents();
+        hipError_t e = hipEventCreate(&se->begin);
+        if (e == hipSuccess) e = hipEventCreate(&se->end);
+        if (e != hipSuccess) {
+            if (se->begin) (void)hipEventDestroy(se->begin);
+            delete se;
+            return hip_fail(ctx, e, "hipEventCreate");
+        }
+    }
+    se->refs = 0;
+    *out = se;
+    return BC_OK;
+}
+
+void unref_step(bc_ctx *ctx, StepEvents *se) {
+    if (se && --se->refs == 0) ctx->spare_steps.push_back(se);
+}
+
+// The ticket's requests ran (in part) in step se: it starts at its first
+// such step and ends at its last.
+void attach_step(bc_ctx *ctx, Ticket &t, StepEvents *se) {
+    if (!t.first) {
+        t.first = se;
+        se->refs++;
+    }
+    if (t.last != se) {
+        StepEvents *prev = t.last;
+        t.last = se;
+        se->refs++;
+        unref_step(ctx, prev);  // still held as t.first when it was the first step
+    }
+}
+
+void release_ticket(bc_ctx *ctx, Ticket &t) {
+    StepEvents *a = t.first, *b = t.last;
+    t.first = t.last = nullptr;
+    if (a) unref_step(ctx, a);
+    if (b) unref_step(ctx, b);
+}
+
+// Maps the device clock to CLOCK_MONOTONIC: an event recorded on the idle
+// clock stream completes between two host readings, whose midpoint is taken
+// as its time (to within half their distance).  A try whose readings lie
+// more than 50 us apart is repeated, up to four tries; the reference is
+// always the last try's event and readings.
+bc_status calibrate_clock(bc_ctx *ctx) {
+    for (int i = 0; i < 4; ++i) {
+        const int64_t t0 = monotonic_ns();
+        HIPCHK(hipEventRecord(ctx->clock_ev, ctx->clock_stream));
+        HIPCHK(hipEventSynchronize(ctx->clock_ev));
+        const int64_t t1 = monotonic_ns();
+        ctx->clock_ns = t0 + (t1 - t0) / 2;
+        ctx->clock_span_ns = t1 - t0;
+        if (t1 - t0 < 50000) break;
+    }
+    return BC_OK;
+}
+
+// CLOCK_MONOTONIC time of a completed timing event.
+bc_status event_time_ns(bc_ctx *ctx, hipEvent_t ev, int64_t *out) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->clock_ev, ev));
+    *out = ctx->clock_ns + (int64_t)((double)ms * 1e6);
+    return BC_OK;
+}
+
+// Launches the next step of queued jobs: the head job of every graph whose
+// FIFO is not empty, oldest head first, at most max_jobs of them.
+bc_status launch_queued_step(bc_ctx *ctx, int32_t max_jobs, int32_t *launched, uint64_t *step_ticket) {
+    *launched = 0;
+    std::vector<std::pair<uint64_t, int32_t>> heads;
+    for (auto &kv : ctx->queues)
+        if (!kv.second.empty()) heads.push_back({kv.second.front().seq, kv.first});
+    if (heads.empty()) return BC_OK;
+    std::sort(heads.begin(), heads.end());
+    const size_t take = std::min<size_t>(heads.size(), (size_t)std::max(1, std::min<int32_t>(max_jobs, JCAP)));
+    std::vector<UpdateJob> jobs;
+    std::vector<uint64_t> owners;
+    Ticket st;
+    for (size_t i = 0; i < take; ++i) {
+        auto &q = ctx->queues[heads[i].second];
+        jobs.push_back(q.front().job);
+        owners.push_back(q.front().ticket);
+        st.graphs.push_back(heads[i].second);
+        q.pop_front();
+    }
+    ctx->queued_jobs -= (int64_t)jobs.size();
+    StepEvents *se;
+    bc_status rc = take_step_events(ctx, &se);
+    if (rc) return rc;
+    se->refs++;  // held while this function attaches it
+    rc = run_step(ctx, jobs, true, se);
+    if (!rc) {
+        for (uint64_t id : owners) {
+            auto it = ctx->tickets.find(id);
+            if (it == ctx->tickets.end()) continue;
+            attach_step(ctx, it->second, se);
+            it->second.jobs_queued--;
+        }
+        if (step_ticket) {
+            st.t_enqueue_ns = monotonic_ns();
+            attach_step(ctx, st, se);
+            *step_ticket = ctx->next_ticket++;
+            ctx->tickets[*step_ticket] = st;
+        }
+        *launched = (int32_t)jobs.size();
+    }
+    unref_step(ctx, se);
+    return rc;
+}
+
+// Launches every queued job (steps of heads until the FIFOs are empty): the
+// calls that enqueue work directly, or act on a graph's state, keep the
+// order in which requests were validated.
+bc_status flush_queues(bc_ctx *ctx) {
+    while (ctx->queued_jobs > 0) {
+        int32_t launched = 0;
+        bc_status st = launch_queued_step(ctx, JCAP, &launched, nullptr);
+        if (st) return st;
+        if (launched == 0) break;
+    }
+    return BC_OK;
 }
 
 UpdateJob job_template(const GraphRec *g) {
@@ -978,6 +1157,12 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
     if (e != hipSuccess) return bail(e, "hipEventCreate");
     e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
     if (e != hipSuccess) return bail(e, "hipEventCreate");
+    e = hipStreamCreateWithFlags(&ctx->clock_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(e, "hipStreamCreate");
+    e = hipEventCreate(&ctx->clock_ev);
+    if (e != hipSuccess) return bail(e, "hipEventCreate");
+    e = hipHostMalloc((void **)&ctx->h_status, 4 * STATUS_BATCH, hipHostMallocDefault);
+    if (e != hipSuccess) return bail(e, "hipHostMalloc");
     for (int r = 0; r < RING; ++r) {
         e = hipHostMalloc((void **)&ctx->h_ring[r], ring_slot_bytes(), hipHostMallocDefault);
         if (e != hipSuccess) return bail(e, "hipHostMalloc");
@@ -1007,7 +1192,7 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
     if (e != hipSuccess) return bail(e, "hipMemsetAsync");
     e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return bail(e, "hipStreamSynchronize");
-    if (fixed_scratch_setup(ctx) != BC_OK) {
+    if (fixed_scratch_setup(ctx) != BC_OK || calibrate_clock(ctx) != BC_OK) {
         fprintf(stderr, "bcinc: %s\n", ctx->last_error.c_str());
         delete ctx;
         return BC_ERR_HIP;
@@ -1056,6 +1241,10 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
                       bc_schedule *chosen) {
     if (!ctx || cnt <= 0 || !reqs || !workspace) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_autotune");
     if (((uintptr_t)workspace & 255) != 0) return fail(ctx, BC_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
     std::vector<int32_t> gids;
     uint64_t need = 0;
     for (int32_t i = 0; i < cnt; ++i) {
@@ -1170,8 +1359,16 @@ bc_status bc_destroy(bc_ctx *ctx) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
-    for (auto &kv : ctx->tickets) (void)hipEventDestroy(kv.second);
-    for (auto ev : ctx->spare_events) (void)hipEventDestroy(ev);
+    for (auto &kv : ctx->tickets) release_ticket(ctx, kv.second);
+    ctx->tickets.clear();
+    for (auto *se : ctx->spare_steps) {
+        (void)hipEventDestroy(se->begin);
+        (void)hipEventDestroy(se->end);
+        delete se;
+    }
+    if (ctx->clock_ev) (void)hipEventDestroy(ctx->clock_ev);
+    if (ctx->clock_stream) (void)hipStreamDestroy(ctx->clock_stream);
+    if (ctx->h_status) (void)hipHostFree(ctx->h_status);
     for (int r = 0; r < RING; ++r) {
         if (ctx->h_ring[r]) (void)hipHostFree(ctx->h_ring[r]);
         if (ctx->ring_ev[r]) (void)hipEventDestroy(ctx->ring_ev[r]);
@@ -1270,6 +1467,10 @@ bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
 bc_status bc_clone_graph(bc_ctx *ctx, bc_graph_id gid, void *arena, uint64_t arena_bytes, bc_graph_id *out) {
     GraphRec *src = get_graph(ctx, gid);
     if (!src) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
     if (!out || !arena) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_clone_graph");
     if (((uintptr_t)arena & 255) != 0) return fail(ctx, BC_ERR_INVALID_ARG, "arena not 256-byte aligned");
     const uint64_t need = bc_graph_bytes(src->n, src->arc_cap, src->es_cap);
@@ -1295,6 +1496,10 @@ bc_status bc_clone_graph(bc_ctx *ctx, bc_graph_id gid, void *arena, uint64_t are
 bc_status bc_free_graph(bc_ctx *ctx, bc_graph_id gid) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     g->live = false;
     ctx->in_use -= g->arena_bytes;
@@ -1305,6 +1510,10 @@ bc_status bc_free_graph(bc_ctx *ctx, bc_graph_id gid) {
 bc_status bc_update_edge(bc_ctx *ctx, bc_graph_id gid, int32_t u, int32_t v, int64_t w) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
     Pending p;
     std::vector<UpdateJob> jobs;
     bc_status st = validate_edge(ctx, g, u, v, w, p, jobs);
@@ -1321,6 +1530,10 @@ bc_status bc_update_edge(bc_ctx *ctx, bc_graph_id gid, int32_t u, int32_t v, int
 bc_status bc_update_vertex(bc_ctx *ctx, bc_graph_id gid, int32_t v, int32_t k, const bc_edge *e) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
     Pending p;
     std::vector<UpdateJob> jobs;
     bc_status st = validate_vertex(ctx, g, v, k, e, p, jobs);
@@ -1334,30 +1547,62 @@ bc_status bc_update_vertex(bc_ctx *ctx, bc_graph_id gid, int32_t v, int32_t k, c
     return BC_OK;
 }
 
-bc_status bc_submit(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *ticket, int32_t *bad_index) {
-    if (!ctx || cnt < 0 || (cnt > 0 && !reqs) || !ticket) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_submit");
-    if (bad_index) *bad_index = -1;
+// Validates requests as one call (none is taken if one fails): each request's
+// jobs, in order, with the graphs' arc changes applied to their mirrors.
+// req_jobs[i] holds request i's jobs.
+bc_status validate_requests(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, int32_t *bad_index,
+                            std::vector<std::vector<UpdateJob>> &req_jobs) {
     std::map<int32_t, Pending> pend;
-    std::map<int32_t, std::vector<UpdateJob>> per_graph;
-    std::vector<int32_t> order;
+    req_jobs.assign((size_t)cnt, {});
     for (int32_t i = 0; i < cnt; ++i) {
         const bc_request &r = reqs[i];
         GraphRec *g = get_graph(ctx, r.graph);
         bc_status st;
         if (!g) st = fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
-        else if (r.kind == 0) st = validate_edge(ctx, g, r.u, r.v, r.w, pend[r.graph], per_graph[r.graph]);
-        else if (r.kind == 1) st = validate_vertex(ctx, g, r.v, r.k, r.edges, pend[r.graph], per_graph[r.graph]);
+        else if (r.kind == 0) st = validate_edge(ctx, g, r.u, r.v, r.w, pend[r.graph], req_jobs[i]);
+        else if (r.kind == 1) st = validate_vertex(ctx, g, r.v, r.k, r.edges, pend[r.graph], req_jobs[i]);
         else st = fail(ctx, BC_ERR_INVALID_ARG, "bad request kind");
         if (st) {
             if (bad_index) *bad_index = i;
             return st;
         }
-        if (std::find(order.begin(), order.end(), r.graph) == order.end()) order.push_back(r.graph);
     }
     for (auto &kv : pend) apply_pending(ctx->graphs[kv.first], kv.second);
     for (int32_t i = 0; i < cnt; ++i) ctx->graphs[reqs[i].graph]->updates += 1;
+    return BC_OK;
+}
+
+bc_status bc_submit(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *ticket, int32_t *bad_index) {
+    if (!ctx || cnt < 0 || (cnt > 0 && !reqs) || !ticket) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_submit");
+    if (bad_index) *bad_index = -1;
+    bc_status st = flush_queues(ctx);
+    if (st) return st;
+    std::vector<std::vector<UpdateJob>> req_jobs;
+    if ((st = validate_requests(ctx, cnt, reqs, bad_index, req_jobs))) return st;
+    Ticket t;
+    t.t_enqueue_ns = monotonic_ns();
+    std::vector<int32_t> order;
+    std::map<int32_t, std::vector<UpdateJob>> per_graph;
+    for (int32_t i = 0; i < cnt; ++i) {
+        const int32_t gid = reqs[i].graph;
+        if (std::find(order.begin(), order.end(), gid) == order.end()) order.push_back(gid);
+        auto &v = per_graph[gid];
+        v.insert(v.end(), req_jobs[i].begin(), req_jobs[i].end());
+    }
+    t.graphs = order;
     size_t steps = 0;
     for (auto &kv : per_graph) steps = std::max(steps, kv.second.size());
+    std::vector<StepEvents *> used;
+    auto step_once = [&](const std::vector<UpdateJob> &part) -> bc_status {
+        StepEvents *se;
+        bc_status rc = take_step_events(ctx, &se);
+        if (rc) return rc;
+        se->refs++;
+        rc = run_step(ctx, part, true, se);
+        if (!rc) attach_step(ctx, t, se);
+        unref_step(ctx, se);
+        return rc;
+    };
     for (size_t k = 0; k < steps; ++k) {
         std::vector<UpdateJob> step;
         for (int32_t gid : order) {
@@ -1366,38 +1611,98 @@ bc_status bc_submit(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *
         }
         for (size_t off = 0; off < step.size(); off += JCAP) {
             std::vector<UpdateJob> part(step.begin() + off, step.begin() + std::min(step.size(), off + JCAP));
-            bc_status st = run_step(ctx, part, true);
-            if (st) return st;
+            if ((st = step_once(part))) {
+                release_ticket(ctx, t);
+                return st;
+            }
         }
     }
-    hipEvent_t ev;
-    if (!ctx->spare_events.empty()) {
-        ev = ctx->spare_events.back();
-        ctx->spare_events.pop_back();
-    } else {
-        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    if (steps == 0) {
+        // nothing to run: a marker step so the ticket still has device times
+        StepEvents *se;
+        if ((st = take_step_events(ctx, &se))) return st;
+        se->refs++;
+        HIPCHK(hipEventRecord(se->begin, ctx->stream));
+        HIPCHK(hipEventRecord(se->end, ctx->stream));
+        attach_step(ctx, t, se);
+        unref_step(ctx, se);
     }
-    HIPCHK(hipEventRecord(ev, ctx->stream));
     *ticket = ctx->next_ticket++;
-    ctx->tickets[*ticket] = ev;
+    ctx->tickets[*ticket] = t;
     return BC_OK;
 }
 
-bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, int32_t *done) {
-    if (!ctx || !done) return BC_ERR_INVALID_ARG;
+bc_status bc_enqueue(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *tickets, int32_t *bad_index) {
+    if (!ctx || cnt < 0 || (cnt > 0 && (!reqs || !tickets))) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_enqueue");
+    if (bad_index) *bad_index = -1;
+    std::vector<std::vector<UpdateJob>> req_jobs;
+    bc_status st = validate_requests(ctx, cnt, reqs, bad_index, req_jobs);
+    if (st) return st;
+    const int64_t now = monotonic_ns();
+    for (int32_t i = 0; i < cnt; ++i) {
+        const uint64_t id = ctx->next_ticket++;
+        Ticket t;
+        t.t_enqueue_ns = now;
+        t.graphs.push_back(reqs[i].graph);
+        t.jobs_queued = (int32_t)req_jobs[i].size();
+        ctx->tickets[id] = t;
+        auto &q = ctx->queues[reqs[i].graph];
+        for (auto &j : req_jobs[i]) q.push_back(QueuedJob{j, id, ctx->queue_seq++});
+        ctx->queued_jobs += (int64_t)req_jobs[i].size();
+        tickets[i] = id;
+    }
+    return BC_OK;
+}
+
+bc_status bc_step(bc_ctx *ctx, int32_t max_jobs, int32_t *launched, uint64_t *step_ticket) {
+    if (!ctx || !launched) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_step");
+    if (step_ticket) *step_ticket = 0;
+    return launch_queued_step(ctx, max_jobs > 0 ? max_jobs : JCAP, launched, step_ticket);
+}
+
+bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, bc_result *out) {
+    if (!ctx || !out) return BC_ERR_INVALID_ARG;
+    memset(out, 0, sizeof *out);
     auto it = ctx->tickets.find(ticket);
     if (it == ctx->tickets.end()) {
-        *done = (ticket > 0 && ticket < ctx->next_ticket) ? 1 : 0;
-        return *done ? BC_OK : fail(ctx, BC_ERR_INVALID_ARG, "unknown ticket");
+        if (ticket > 0 && ticket < ctx->next_ticket) {
+            out->done = 1;  // collected before: no times left to report
+            return BC_OK;
+        }
+        return fail(ctx, BC_ERR_INVALID_ARG, "unknown ticket");
     }
-    hipError_t e = hipEventQuery(it->second);
-    if (e == hipErrorNotReady) {
-        *done = 0;
-        return BC_OK;
-    }
+    Ticket &t = it->second;
+    out->t_enqueue_ns = t.t_enqueue_ns;
+    if (t.jobs_queued > 0 || !t.last) return BC_OK;  // not launched (all of it) yet
+    hipError_t e = hipEventQuery(t.last->end);
+    if (e == hipErrorNotReady) return BC_OK;
     if (e != hipSuccess) return hip_fail(ctx, e, "hipEventQuery");
-    *done = 1;
-    ctx->spare_events.push_back(it->second);
+    // keep the clock mapping fresh (the clock stream is idle; no update work
+    // is waited for)
+    if (monotonic_ns() - ctx->clock_ns > CLOCK_REFRESH_NS) {
+        bc_status cs = calibrate_clock(ctx);
+        if (cs) return cs;
+    }
+    bc_status st = event_time_ns(ctx, t.first->begin, &out->t_start_ns);
+    if (!st) st = event_time_ns(ctx, t.last->end, &out->t_finish_ns);
+    if (st) return st;
+    // the sticky status of the ticket's graphs, read on the clock stream
+    int32_t acc = 0;
+    for (size_t b = 0; b < t.graphs.size(); b += STATUS_BATCH) {
+        const size_t e2 = std::min(t.graphs.size(), b + STATUS_BATCH);
+        int used = 0;
+        for (size_t k = b; k < e2; ++k) {
+            GraphRec *g = get_graph(ctx, t.graphs[k]);
+            if (!g) continue;
+            HIPCHK(hipMemcpyAsync(ctx->h_status + used, &g->P.ctl->status, 4, hipMemcpyDeviceToHost, ctx->clock_stream));
+            ++used;
+        }
+        HIPCHK(hipStreamSynchronize(ctx->clock_stream));
+        for (int k = 0; k < used; ++k) acc |= ctx->h_status[k];
+    }
+    out->status = sticky_to_status(acc);
+    out->done = 1;
+    release_ticket(ctx, t);
     ctx->tickets.erase(it);
     return BC_OK;
 }
@@ -1406,14 +1711,23 @@ bc_status bc_wait(bc_ctx *ctx, uint64_t ticket) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     auto it = ctx->tickets.find(ticket);
     if (it == ctx->tickets.end()) return (ticket > 0 && ticket < ctx->next_ticket) ? BC_OK : fail(ctx, BC_ERR_INVALID_ARG, "unknown ticket");
-    HIPCHK(hipEventSynchronize(it->second));
-    ctx->spare_events.push_back(it->second);
+    // queued requests of the ticket are launched first (steps of heads)
+    while (it->second.jobs_queued > 0) {
+        int32_t launched = 0;
+        bc_status st = launch_queued_step(ctx, JCAP, &launched, nullptr);
+        if (st) return st;
+        if (!launched) return fail(ctx, BC_ERR_INVALID_ARG, "ticket has queued jobs but no queue holds them");
+    }
+    if (it->second.last) HIPCHK(hipEventSynchronize(it->second.last->end));
+    release_ticket(ctx, it->second);
     ctx->tickets.erase(it);
     return BC_OK;
 }
 
 bc_status bc_sync(bc_ctx *ctx) {
     if (!ctx) return BC_ERR_INVALID_ARG;
+    bc_status fs = flush_queues(ctx);
+    if (fs) return fs;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     for (auto *g : ctx->graphs) {
         if (!g || !g->live) continue;
@@ -1442,12 +1756,20 @@ bc_status bc_scores(bc_ctx *ctx, bc_graph_id gid, double *out) {
 bc_status bc_recompute(bc_ctx *ctx, bc_graph_id gid) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
     return static_pass(ctx, g);
 }
 
 bc_status bc_recompute_estar(bc_ctx *ctx, bc_graph_id gid) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
     return static_pass(ctx, g, true);
 }
 

@@ -423,26 +423,28 @@ def main():
                 + ", ".join(f"n={k} p50 {v['p50']:.2f} p99 {v['p99']:.2f}" for k, v in res["by_n"].items()))
         served = {"graphs": [g.n for g in c5], "load_s": c5_load_s, "saturation": sat, "sweep": sweep}
 
-        # admission under a memory budget: the 8 graphs' arenas less one
-        # n=4096 arena and half an n=8192 one, so at any time one graph of
-        # n >= 8192 (or more) stays off the device; requests for it wait
-        # until idle graphs are evicted (their arcs kept on the host) and it
-        # is loaded again by the static pass
+        # admission under a memory budget: the 8 graphs' arenas less half an
+        # n=4096 arena, so one graph stays off the device at any time;
+        # requests for it wait until an idle graph of its size is evicted
+        # (its arcs kept on the host) and it is loaded again by the static
+        # pass
         if "budget" in legs:
             nbytes = [gr.nbytes + 256 for gr in sg]
-            small4, small8 = nbytes[0], nbytes[1]
-            budget = sum(nbytes) - small4 - small8 // 2
-            # the resident graphs stay; graph 1 (n=8192) is evicted to fit
+            budget = sum(nbytes) - nbytes[0] // 2
+            # the resident graphs stay but for graph 0 (n=4096): the two
+            # n=4096 graphs share one place, and a request for the one that
+            # is out waits until the other is idle, is evicted and it is
+            # loaded again
             res_mgr = serve.Resident(ctx, [None] * len(sg), budget, lambda i: nbytes[i])
             for i, gr in enumerate(sg):
                 res_mgr.live[i] = gr
-            evicted = res_mgr.live.pop(1)
-            res_mgr.arcs[1] = evicted.arcs()
+            evicted = res_mgr.live.pop(0)
+            res_mgr.arcs[0] = evicted.arcs()
             evicted.free()
             del sg
             torch.cuda.empty_cache()
             breqs = part(1000)
-            rate = 0.5 * sat_rate
+            rate = 0.25 * sat_rate
             arrivals = W.poisson_arrivals(len(breqs), rate, W.derive_seed(5, 5104))
             srv = serve.Server(ctx, resident=res_mgr, max_in_flight=2)
             t = time.perf_counter()

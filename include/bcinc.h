@@ -68,7 +68,9 @@ typedef struct bc_ctx bc_ctx;
 typedef int32_t bc_graph_id;
 
 /* bc_config.flags */
-#define BC_FLAG_TIMING 1 /* time every update step and its per-source kernels with HIP events */
+#define BC_FLAG_TIMING 1      /* time every update step and its per-source kernels with HIP events */
+#define BC_FLAG_FULL_SEARCH 2 /* the static pass (load, bc_recompute) relaxes every arc, never a
+                                 checked subset (see bc_load_graph) */
 
 typedef struct {
     int32_t device;         /* HIP device ordinal */
@@ -98,7 +100,15 @@ bc_status bc_destroy(bc_ctx *ctx);
 
 /* Loads a graph and computes its initial state with a static Brandes pass on
  * the GPU (the paper assumes BC and every DAG are available before the first
- * update: Section 1, and Alg 7 of the appendix).
+ * update: Section 1, and Alg 7 of the appendix).  The distance search of a
+ * dense graph (at least 4k out-arcs per vertex on average, k = ceil(2 ln n)
+ * + 4) relaxes a checked subset instead of every arc (Static-BC of Section
+ * 6, which needs only an arc set containing E*): the k lightest out-arcs of
+ * every vertex, plus, round by round, every arc whose weight is at most the
+ * distance between its ends that the subset gives, until no such arc is
+ * missing.  On complete graphs with random weights E* has about n ln n arcs,
+ * so the search relaxes a small fraction of the n^2 arcs.  bc_recompute does
+ * the same; BC_FLAG_FULL_SEARCH turns the check off.
  *   src, dst, w: host arrays of m arcs (edges when undirected), copied in;
  *     the caller keeps ownership.
  *   arc_capacity: most arcs (of G_D) the graph may ever hold, >= its arc count.
@@ -291,6 +301,8 @@ typedef struct {
                                  source (4|T| when the update's candidate targets T are scanned
                                  instead, |T| <= n/8) plus 8 per changed pair (its old sigma) */
     int64_t total_scan_bytes; /* the same summed over all updates since load */
+    int64_t search_arcs;      /* arcs the distance search of the last static pass relaxed */
+    int64_t search_rounds;    /* its searches when the arc set was checked (0: one search) */
 } bc_update_stats;
 bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id g, bc_update_stats *out);
 

@@ -65,7 +65,8 @@ class bc_update_stats(ctypes.Structure):
                 ("estar_arcs", ctypes.c_int64), ("max_levels", ctypes.c_int64), ("updates_applied", ctypes.c_int64),
                 ("total_affected", ctypes.c_int64), ("total_changed", ctypes.c_int64),
                 ("deferred_sources", ctypes.c_int64), ("scan_bytes", ctypes.c_int64),
-                ("total_scan_bytes", ctypes.c_int64)]
+                ("total_scan_bytes", ctypes.c_int64), ("search_arcs", ctypes.c_int64),
+                ("search_rounds", ctypes.c_int64)]
 
 
 class bc_result(ctypes.Structure):
@@ -87,6 +88,7 @@ class bc_schedule(ctypes.Structure):
 SCHEDULE_FIELDS = tuple(f for f, _ in bc_schedule._fields_)
 
 BC_FLAG_TIMING = 1
+BC_FLAG_FULL_SEARCH = 2
 
 
 _P = ctypes.c_void_p
@@ -171,14 +173,14 @@ class Context:
     """A bcinc context on one GPU (bc_create / bc_destroy)."""
 
     def __init__(self, device: int = 0, n_max: int = 4096, slots: int = 0, block: int = 0, memory_budget: int = 0,
-                 stream=None, timing: bool = False):
+                 stream=None, timing: bool = False, full_search: bool = False):
         import torch
 
         self.device = device
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.scratch_bytes = bc_scratch_bytes(n_max, slots)
         self._scratch, addr = _device_buffer(self.scratch_bytes, device)
-        flags = BC_FLAG_TIMING if timing else 0
+        flags = (BC_FLAG_TIMING if timing else 0) | (BC_FLAG_FULL_SEARCH if full_search else 0)
         cfg = bc_config(device, flags, self.stream.cuda_stream, addr, self.scratch_bytes, memory_budget, slots, block)
         h = ctypes.c_void_p()
         rc = _lib.bc_create(ctypes.byref(h), ctypes.byref(cfg))

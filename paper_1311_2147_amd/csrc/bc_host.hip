@@ -8,6 +8,8 @@
 // runs in the kernels of bc_kernels.hip.
 #include <time.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -139,6 +141,8 @@ struct GraphRec {
     GraphPtrs P{};
     Mirror mirror;
     uint64_t updates = 0;
+    int64_t search_arcs = 0;   // arcs the last static pass's distance search relaxed
+    int32_t search_rounds = 0; // searches of its checked search (0: one search over a given set)
 };
 
 struct StepGraph {
@@ -204,6 +208,7 @@ struct bc_ctx {
     size_t wide_lds_limit = 0;  // dynamic LDS the wide kernel may use
     int rows_grid = 1024;       // workgroups of the row kernel (all resident)
     int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
+    bool full_search = false;  // BC_FLAG_FULL_SEARCH: the static pass relaxes every arc
     int32_t src_lds_max = 8192;  // per-source kernel stages rows up to this n in LDS
     std::vector<GraphRec *> graphs;
     std::string last_error;
@@ -933,47 +938,131 @@ bc_status estar_by_tail(bc_ctx *ctx, GraphRec *g, std::vector<int32_t> &hp, std:
     return BC_OK;
 }
 
-// Static pass: all-pairs distances, path counts, E* and BC from scratch.
-// over_estar: the distance search relaxes only the maintained E* instead of
-// every arc (Section 6: every shortest path lies in E*, so any arc set
-// containing E* gives the same distances, DAGs, counts and BC).
+// An arc set by tail (heads ascending within a tail).
+struct ArcCsr {
+    std::vector<int32_t> ptr, dst, w;
+    int64_t size() const { return (int64_t)dst.size(); }
+};
+
+// The same arcs grouped by head (counting sort; tails stay ascending).
+void by_head(int32_t n, const ArcCsr &t, ArcCsr &h) {
+    const int64_t m = t.size();
+    h.ptr.assign(n + 1, 0);
+    h.dst.resize((size_t)m);
+    h.w.resize((size_t)m);
+    for (int64_t e = 0; e < m; ++e) h.ptr[t.dst[e] + 1]++;
+    for (int32_t i = 0; i < n; ++i) h.ptr[i + 1] += h.ptr[i];
+    std::vector<int32_t> fill(h.ptr.begin(), h.ptr.end() - 1);
+    for (int32_t a = 0; a < n; ++a)
+        for (int32_t e = t.ptr[a]; e < t.ptr[a + 1]; ++e) {
+            const int32_t q = fill[t.dst[e]]++;
+            h.dst[q] = a;
+            h.w[q] = t.w[e];
+        }
+}
+
+bc_status upload_csr(bc_ctx *ctx, int32_t n, const ArcCsr &c, int32_t *ptr, int32_t *other, int32_t *w) {
+    HIPCHK(hipMemcpyAsync(ptr, c.ptr.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, ctx->stream));
+    if (c.size()) {
+        HIPCHK(hipMemcpyAsync(other, c.dst.data(), 4 * (size_t)c.size(), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(w, c.w.data(), 4 * (size_t)c.size(), hipMemcpyHostToDevice, ctx->stream));
+    }
+    return BC_OK;
+}
+
+// The k lightest out-arcs of every vertex (all of them where there are at
+// most k), heads ascending.
+void lightest_arcs(int32_t n, const ArcCsr &full, int32_t k, ArcCsr &out) {
+    out.ptr.assign(n + 1, 0);
+    out.dst.clear();
+    out.w.clear();
+    std::vector<std::pair<int32_t, int32_t>> row;  // (w, head)
+    for (int32_t a = 0; a < n; ++a) {
+        row.clear();
+        for (int32_t e = full.ptr[a]; e < full.ptr[a + 1]; ++e) row.push_back({full.w[e], full.dst[e]});
+        if ((int32_t)row.size() > k) {
+            std::nth_element(row.begin(), row.begin() + k, row.end());
+            row.resize(k);
+        }
+        std::sort(row.begin(), row.end(), [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
+            return x.second < y.second;
+        });
+        for (auto &p : row) {
+            out.dst.push_back(p.second);
+            out.w.push_back(p.first);
+        }
+        out.ptr[a + 1] = (int32_t)out.dst.size();
+    }
+}
+
+// Adds the listed arcs that the set lacks; returns how many were new.
+int64_t add_missing(int32_t n, ArcCsr &set, const std::vector<int32_t> &a, const std::vector<int32_t> &b,
+                    const std::vector<int32_t> &w) {
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> extra;
+    int64_t added = 0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        auto first = set.dst.begin() + set.ptr[a[i]], last = set.dst.begin() + set.ptr[a[i] + 1];
+        if (std::binary_search(first, last, b[i])) continue;
+        if (extra.empty()) extra.resize(n);
+        extra[a[i]].push_back({b[i], w[i]});
+        ++added;
+    }
+    if (!added) return 0;
+    ArcCsr out;
+    out.ptr.assign(n + 1, 0);
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int32_t t = 0; t < n; ++t) {
+        row.clear();
+        for (int32_t e = set.ptr[t]; e < set.ptr[t + 1]; ++e) row.push_back({set.dst[e], set.w[e]});
+        row.insert(row.end(), extra[t].begin(), extra[t].end());
+        std::sort(row.begin(), row.end());
+        for (auto &p : row) {
+            out.dst.push_back(p.first);
+            out.w.push_back(p.second);
+        }
+        out.ptr[t + 1] = (int32_t)out.dst.size();
+    }
+    set = std::move(out);
+    return added;
+}
+
+// Out-arcs per vertex in the first searched set of a checked search, and
+// the density from which the check pays (the set is at most a quarter of
+// the arcs).
+int32_t search_k(int32_t n) { return (int32_t)std::ceil(2.0 * std::log((double)std::max(n, 2))) + 4; }
+bool use_checked_search(int32_t n, int64_t m) { return m >= 4 * (int64_t)search_k(n) * n; }
+
+// Static pass: all-pairs distances, path counts, E* and BC from scratch
+// (Alg 7 with the DAG taken from E*, Alg 6 steps 2-8).
+//
+// The distance search relaxes a set of arcs that contains E*; every
+// shortest path lies in E* and any such set gives the same distances, DAGs,
+// counts and BC (Section 6):
+//   over_estar: the maintained E* (a graph without sticky errors);
+//   a dense graph (checked search): the k lightest out-arcs of every vertex
+//     first; then one pass over all arcs lists those with w(a,b) <= d_H(a,b)
+//     for the distances d_H of the searched set H; the listed arcs H lacks
+//     join it and the search runs again, until none is missing, when d_H is
+//     the distance matrix and H contains E* (see k_search_check).  On
+//     complete graphs with random weights E* has about n ln n arcs
+//     (Section 1), so H stays a small fraction of the n^2 arcs;
+//   otherwise (sparse graphs, or BC_FLAG_FULL_SEARCH): every arc.
 bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
     const int32_t n = g->n;
-    std::vector<int32_t> hp, hd, hw;
+    ArcCsr full;
     if (over_estar) {
-        bc_status st = estar_by_tail(ctx, g, hp, hd, hw);
+        bc_status st = estar_by_tail(ctx, g, full.ptr, full.dst, full.w);
         if (st) return st;
     } else {
         g->mirror.compact();
-        hp.resize(n + 1);
-        hd = g->mirror.dst;
-        hw = g->mirror.w;
-        for (int32_t i = 0; i <= n; ++i) hp[i] = (int32_t)g->mirror.ptr[i];
+        full.ptr.resize(n + 1);
+        full.dst = g->mirror.dst;
+        full.w = g->mirror.w;
+        for (int32_t i = 0; i <= n; ++i) full.ptr[i] = (int32_t)g->mirror.ptr[i];
     }
-    const int64_t m = (int64_t)hd.size();
+    const int64_t m = full.size();
     if (m > g->arc_cap) return fail(ctx, BC_ERR_CAPACITY, "arc capacity exceeded");
-    g->P.arc_m = m;
-    // the same arcs grouped by head (counting sort; tails stay ascending)
-    std::vector<int32_t> ip(n + 1, 0), is((size_t)m), iw((size_t)m);
-    for (int64_t e = 0; e < m; ++e) ip[hd[e] + 1]++;
-    for (int32_t i = 0; i < n; ++i) ip[i + 1] += ip[i];
-    {
-        std::vector<int32_t> fill(ip.begin(), ip.end() - 1);
-        for (int32_t a = 0; a < n; ++a)
-            for (int32_t e = hp[a]; e < hp[a + 1]; ++e) {
-                const int32_t q = fill[hd[e]]++;
-                is[q] = a;
-                iw[q] = hw[e];
-            }
-    }
-    HIPCHK(hipMemcpyAsync(g->P.arc_ptr, hp.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(g->P.arcin_ptr, ip.data(), 4 * (size_t)(n + 1), hipMemcpyHostToDevice, ctx->stream));
-    if (m) {
-        HIPCHK(hipMemcpyAsync(g->P.arc_dst, hd.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipMemcpyAsync(g->P.arc_w, hw.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipMemcpyAsync(g->P.arcin_src, is.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipMemcpyAsync(g->P.arcin_w, iw.data(), 4 * (size_t)m, hipMemcpyHostToDevice, ctx->stream));
-    }
+    const bool checked = !over_estar && !ctx->full_search && use_checked_search(n, m);
     HIPCHK(hipMemsetAsync(g->P.ctl, 0, sizeof(GraphCtl), ctx->stream));
     HIPCHK(hipMemsetAsync(g->P.bc_delta, 0, 8 * (size_t)n, ctx->stream));
     std::vector<UpdateJob> jobs(1, job_template(g));
@@ -992,9 +1081,70 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
     HIPCHK(hipMemsetAsync(sp.src_base, 0, slot_region, ctx->stream));
     const int g_wave = (int)std::min<int64_t>(((int64_t)n * 64 + 255) / 256, 4096);
     hipStream_t s = ctx->stream;
-    hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
-    hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, L.src_base, L.slot_bytes,
-                       L.lds_cap, L.n_layout);
+    ArcCsr search;  // the arcs the distance search relaxes
+    bool have_dist = false;
+    int32_t rounds = 0;
+    if (checked) {
+        // every arc by tail stays in arc_* for the check; the searched set
+        // goes by tail into the by-head arrays, unused until the E* build
+        if ((st = upload_csr(ctx, n, full, g->P.arc_ptr, g->P.arc_dst, g->P.arc_w))) return st;
+        lightest_arcs(n, full, search_k(n), search);
+        unsigned long long *cnt = (unsigned long long *)misc_dev(ctx);
+        std::vector<int32_t> ca, cb, cw;
+        for (;;) {
+            ++rounds;
+            if ((st = upload_csr(ctx, n, search, g->P.arcin_ptr, g->P.arcin_src, g->P.arcin_w))) return st;
+            hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
+            hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, L.src_base,
+                               L.slot_bytes, L.lds_cap, L.n_layout, g->P.arcin_ptr, g->P.arcin_src, g->P.arcin_w);
+            HIPCHK(hipMemsetAsync(cnt, 0, 8, s));
+            hipLaunchKernelGGL(k_search_check, dim3(std::max(1, std::min(g_wave, 4096))), dim3(256), 0, s, dj,
+                               g->P.yc_src, g->P.yc_dst, g->P.yc_w, g->es_cap, cnt);
+            HIPCHK(hipGetLastError());
+            unsigned long long c = 0;
+            int32_t status = 0;
+            HIPCHK(hipMemcpyAsync(&c, cnt, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&status, &g->P.ctl->status, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (status) {
+                have_dist = true;  // the sticky error is reported below
+                break;
+            }
+            if ((int64_t)c > g->es_cap) {
+                // more candidate arcs than E* may hold: search every arc
+                search = full;
+                break;
+            }
+            ca.resize((size_t)c);
+            cb.resize((size_t)c);
+            cw.resize((size_t)c);
+            if (c) {
+                HIPCHK(hipMemcpyAsync(ca.data(), g->P.yc_src, 4 * (size_t)c, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(cb.data(), g->P.yc_dst, 4 * (size_t)c, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(cw.data(), g->P.yc_w, 4 * (size_t)c, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+            }
+            if (add_missing(n, search, ca, cb, cw) == 0) {
+                have_dist = true;
+                break;
+            }
+        }
+    } else {
+        search = std::move(full);
+    }
+    g->search_arcs = search.size();
+    g->search_rounds = rounds;
+    // the final arc set, by tail and by head, for the E* build
+    ArcCsr head;
+    by_head(n, search, head);
+    if ((st = upload_csr(ctx, n, search, g->P.arc_ptr, g->P.arc_dst, g->P.arc_w))) return st;
+    if ((st = upload_csr(ctx, n, head, g->P.arcin_ptr, g->P.arcin_src, g->P.arcin_w))) return st;
+    g->P.arc_m = search.size();
+    if (!have_dist) {
+        hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
+        hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, L.src_base, L.slot_bytes,
+                           L.lds_cap, L.n_layout, g->P.arc_ptr, g->P.arc_dst, g->P.arc_w);
+    }
     hipLaunchKernelGGL(k_es_count<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
     hipLaunchKernelGGL(k_es_scan<ES_BUILD>, dim3(1), dim3(1024), 0, s, dj, nj);
     hipLaunchKernelGGL(k_es_scatter<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
@@ -1176,6 +1326,7 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
         }
     }
     ctx->timing = (cfg->flags & BC_FLAG_TIMING) != 0;
+    ctx->full_search = (cfg->flags & BC_FLAG_FULL_SEARCH) != 0;
     {
         // the row kernel is persistent: as many workgroups as stay resident
         int per_cu = 0;
@@ -1956,6 +2107,8 @@ bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id gid, bc_update_stats *out) {
     out->deferred_sources = c.big_last;
     out->scan_bytes = (int64_t)c.scan_bytes_last;
     out->total_scan_bytes = (int64_t)c.scan_bytes_total;
+    out->search_arcs = g->search_arcs;
+    out->search_rounds = g->search_rounds;
     return BC_OK;
 }
 

@@ -2885,9 +2885,14 @@ __global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__res
 
 // Distances from every source: frontier Bellman-Ford with the row in LDS
 // (atomicMin relaxations; a vertex improved in a round is queued once for
-// the next round).  Positive weights make it converge to d(s,.).
+// the next round).  Positive weights make it converge to d(s,.).  The search
+// relaxes the arcs of the set given by tail (sptr, sdst, sw): every arc of
+// the graph, or a set known or checked to contain E* (Section 6: any arc set
+// containing E* gives the same distances).
 __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ jobs, char *__restrict__ scratch,
-                                               size_t slot_bytes, int32_t lds_cap, int32_t n_layout) {
+                                               size_t slot_bytes, int32_t lds_cap, int32_t n_layout,
+                                               const int32_t *__restrict__ sptr, const int32_t *__restrict__ sdst,
+                                               const int32_t *__restrict__ sw) {
     extern __shared__ int32_t lds_row[];
     __shared__ BlockShared sh;
     const UpdateJob &J = jobs[0];
@@ -2927,10 +2932,10 @@ __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ job
             for (int32_t idx = tid; idx < qlen; idx += bs) {
                 const int32_t a = cur[idx];
                 const int32_t da = __atomic_load_n(&row[a], __ATOMIC_RELAXED);
-                const int32_t e1 = J.g.arc_ptr[a + 1];
-                for (int32_t e = J.g.arc_ptr[a]; e < e1; ++e) {
-                    const int32_t b = J.g.arc_dst[e];
-                    const int64_t nd = (int64_t)da + J.g.arc_w[e];
+                const int32_t e1 = sptr[a + 1];
+                for (int32_t e = sptr[a]; e < e1; ++e) {
+                    const int32_t b = sdst[e];
+                    const int64_t nd = (int64_t)da + sw[e];
                     if (nd >= INF32) { long_cand = true; continue; }
                     if ((int32_t)nd < __atomic_load_n(&row[b], __ATOMIC_RELAXED)) {
                         const int32_t old = atomicMin(&row[b], (int32_t)nd);
@@ -2960,15 +2965,62 @@ __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ job
             // longer
             for (int32_t a = tid; a < n; a += bs) {
                 if (__atomic_load_n(&row[a], __ATOMIC_RELAXED) == INF32) continue;
-                const int32_t e1 = J.g.arc_ptr[a + 1];
-                for (int32_t e = J.g.arc_ptr[a]; e < e1; ++e)
-                    if (__atomic_load_n(&row[J.g.arc_dst[e]], __ATOMIC_RELAXED) == INF32) ovf = true;
+                const int32_t e1 = sptr[a + 1];
+                for (int32_t e = sptr[a]; e < e1; ++e)
+                    if (__atomic_load_n(&row[sdst[e]], __ATOMIC_RELAXED) == INF32) ovf = true;
             }
         }
         if (lds)
             for (int32_t i = tid; i < n; i += bs) Dg[i] = row[i];
     }
     if (ovf) atomicOr(&ctl->status, ST_DIST_OVF);
+}
+
+// Check of a searched arc set H against every arc of the graph (by tail in
+// arc_ptr / arc_dst / arc_w), with D the distances the search over H found:
+// the arcs (a,b) with w(a,b) <= D(a,b) go to the out list (up to cap; *cnt
+// counts them all).  An arc of E* has w(a,b) = d(a,b) <= D(a,b), so it is
+// listed unless H holds it; and when every listed arc is in H, no path can
+// be shortened by an arc outside H (its weight exceeds the H-distance of its
+// ends), so D is the graph's distance matrix and H contains E*.  One wave
+// per tail (the tail's arcs and its distance row are contiguous).
+__global__ void __launch_bounds__(256) k_search_check(const UpdateJob *__restrict__ jobs, int32_t *__restrict__ out_a,
+                                                      int32_t *__restrict__ out_b, int32_t *__restrict__ out_w,
+                                                      int64_t cap, unsigned long long *__restrict__ cnt) {
+    const UpdateJob &J = jobs[0];
+    const int32_t n = J.g.n;
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t a = wave; a < n; a += nwaves) {
+        const int32_t *Da = J.g.D + (size_t)a * n;
+        const int32_t p0 = J.g.arc_ptr[a], p1 = J.g.arc_ptr[a + 1];
+        for (int32_t base = p0; base < p1; base += 64) {
+            const int32_t i = base + lane;
+            bool keep = false;
+            int32_t b = 0, w = 0;
+            if (i < p1) {
+                b = J.g.arc_dst[i];
+                w = J.g.arc_w[i];
+                const int32_t d = Da[b];
+                keep = d == INF32 || w <= d;
+            }
+            const uint64_t mask = __ballot(keep);
+            if (!mask) continue;
+            unsigned long long b0 = 0;
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            if (lane == leader) b0 = atomicAdd(cnt, (unsigned long long)__popcll(mask));
+            b0 = __shfl(b0, leader, 64);
+            if (keep) {
+                const unsigned long long o = b0 + popc_below(mask, lane);
+                if ((int64_t)o < cap) {
+                    out_a[o] = (int32_t)a;
+                    out_b[o] = b;
+                    out_w[o] = w;
+                }
+            }
+        }
+    }
 }
 
 // Per source after the distances and E* exist: path counts pushed in Kahn

@@ -17,8 +17,9 @@ step holding the request finished (bc_poll's t_finish_ns).
 Admission (Resident): graphs may be admitted to the device under a byte
 budget (their arenas, about 16 n^2 bytes each).  A request for a graph with no
 state on the device waits until the graph fits; graphs with no request queued
-or in flight are evicted for it (the smallest one that frees enough, else
-least recently used first until enough is free), their current
+or in flight, and not much larger than it, are evicted for it (the smallest
+one that frees enough, else least recently used first until enough is
+free), their current
 arcs kept on the host (bc_get_arcs) and loaded again by the static pass when
 they are needed.  Requests are queued in arrival order, so a waiting request
 holds back later ones until its graph is in (no graph starves).
@@ -34,11 +35,16 @@ import numpy as np
 class Resident:
     """Graphs admitted to one context under a byte budget."""
 
-    def __init__(self, ctx, arcs_list, budget_bytes: int, graph_bytes):
+    def __init__(self, ctx, arcs_list, budget_bytes: int, graph_bytes, victim_ratio: float = 2.0):
         self.ctx = ctx
         self.arcs = list(arcs_list)      # current arcs of every graph (host)
         self.budget = int(budget_bytes)
         self.graph_bytes = graph_bytes   # idx -> arena bytes the graph takes
+        # a graph is evicted for another only if its arena is at most this
+        # many times the other's: a small graph waits for a graph of its size
+        # to go idle rather than push out a large one (whose reload costs far
+        # more)
+        self.victim_ratio = victim_ratio
         self.live = {}                   # idx -> library graph
         self.last_use = {}
         self.loads = 0
@@ -62,7 +68,7 @@ class Resident:
         if need > self.budget:
             raise ValueError(f"graph {idx} needs {need} bytes, above the whole budget {self.budget}")
         free = self.budget - self.used()
-        idle = [i for i in self.live if i not in busy]
+        idle = [i for i in self.live if i not in busy and self.graph_bytes(i) <= self.victim_ratio * need]
         victims = []
         if free < need:
             # the smallest idle graph that frees enough by itself, else idle

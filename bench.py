@@ -20,6 +20,8 @@ Besides the headline the run measures:
     (no HIP graph, no batching); both legs must reach the same state;
   * the row kernel's achieved HBM bandwidth over the timed window;
   * a full GPU recompute (the static pass) and the recompute over E*;
+  * loads of dense graphs (complete, weights up to n^2) by the checked
+    search over a subset containing E*, against the search over every arc;
   * a dedicated 1000-update stream on one freshly loaded graph;
   * the served workload at full shape: 8 resident Chung-Lu graphs (n = 4096,
     8192, 16384, 32768, two of each) and Poisson streams over them, served by
@@ -92,7 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--graphs", type=int, default=2)
-    ap.add_argument("--legs", default="batched,plain,recompute,single,served,budget,cpuinc,cpu,copy")
+    ap.add_argument("--legs", default="batched,plain,recompute,loader,single,served,budget,cpuinc,cpu,copy")
     ap.add_argument("--served-updates", type=int, default=10000, help="updates of the 0.8x served run")
     ap.add_argument("--cpu-updates", type=int, default=12, help="updates of the CPU incremental comparator's sample")
     ap.add_argument("--cpu-one-core-sources", type=int, default=512, help="sources of the one-core oracle sample")
@@ -257,6 +259,42 @@ def main():
         comparators["estar_gpu_recompute_s"] = est_s
         comparators["batched_over_estar_recompute"] = value * est_s
         log(f"GPU recompute over E*: {est_s:.3f}s")
+
+    # ---------------------------------------------------------------- loader
+    # Loading dense graphs: the complete n=2048 workload (weights up to n^2)
+    # and the largest complete graph of the 64-graph batched workload, by the
+    # static pass's checked search over a subset containing E* (Section 6)
+    # and, in a second context, by the search over every arc.
+    if "loader" in legs:
+        dense = [("complete n=2048 (the vertex-update workload)", W.config3()[0])]
+        c4n = W.config4_sizes()
+        gi = max(range(32, 64), key=lambda i: c4n[i])  # graphs 32..63 are the complete ones
+        big = W.complete_undirected(c4n[gi], c4n[gi] ** 2, W.derive_seed(4, gi, 0), f"c4-complete-n{c4n[gi]}")
+        dense.append((f"complete n={big.n} (largest of the 64-graph workload)", big))
+        loads = []
+        full_ctx = bcinc.Context(device=0, n_max=max(g.n for _, g in dense), slots=0, full_search=True)
+        for name, g in dense:
+            row = {"graph": name, "n": g.n, "arcs": 2 * g.m}
+            for label, c in (("checked", ctx), ("full", full_ctx)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                gl = c.load_graph(g)
+                c.sync()
+                row[f"{label}_load_s"] = time.perf_counter() - t0
+                st = gl.stats()
+                row[f"{label}_searched_arcs"] = st["search_arcs"]
+                row[f"{label}_search_rounds"] = st["search_rounds"]
+                row[f"{label}_hash"] = gl.state_hash()
+                gl.free()
+                torch.cuda.empty_cache()
+            row["same_state"] = row.pop("checked_hash") == row.pop("full_hash")
+            loads.append(row)
+            log(f"load {name}: checked search {row['checked_load_s']:.2f}s ({row['checked_searched_arcs']} arcs, "
+                f"{row['checked_search_rounds']} rounds), full search {row['full_load_s']:.2f}s; same state "
+                f"{row['same_state']}")
+        full_ctx.close()
+        torch.cuda.empty_cache()
+        comparators["dense_loads"] = loads
 
     # ---------------------------------------------------------------- single
     # A dedicated stream of the same mix on one freshly loaded n-vertex graph:
@@ -443,22 +481,30 @@ def main():
             evicted.free()
             del sg
             torch.cuda.empty_cache()
-            breqs = part(1000)
-            rate = 0.25 * sat_rate
+            # its own saturation first (closed loop), then half of it offered
+            creqs = part(300)
+            srv = serve.Server(ctx, resident=res_mgr, max_in_flight=2)
+            lat, _, wall_s = srv.run(np.zeros(len(creqs)), creqs)
+            bsat = len(creqs) / wall_s
+            ev0, ld0, lds0 = res_mgr.evictions, res_mgr.loads, res_mgr.load_s
+            breqs = part(400)
+            rate = 0.5 * bsat
             arrivals = W.poisson_arrivals(len(breqs), rate, W.derive_seed(5, 5104))
             srv = serve.Server(ctx, resident=res_mgr, max_in_flight=2)
-            t = time.perf_counter()
             lat, _, wall_s = srv.run(arrivals, breqs)
             ctx.sync()
             pp = serve.percentiles(lat)
             served["budget"] = {
                 "budget_bytes": budget, "budget_in_16n2_units": budget / sum(16 * g.n * g.n for g in c5),
-                "all_graphs_bytes": sum(nbytes), "updates": len(breqs), "offered_updates_per_s": rate,
-                "served_updates_per_s": len(breqs) / wall_s, "loads": res_mgr.loads, "evictions": res_mgr.evictions,
-                "load_s": res_mgr.load_s, **pp}
-            log(f"served under a {budget / 1e9:.1f} GB budget (all graphs {sum(nbytes) / 1e9:.1f} GB): "
-                f"{res_mgr.evictions} evictions, {res_mgr.loads} loads ({res_mgr.load_s:.1f}s), "
-                f"{len(breqs) / wall_s:.0f}/s served at {rate:.0f}/s offered, p50 {pp['p50']:.2f} ms p99 {pp['p99']:.2f} ms")
+                "all_graphs_bytes": sum(nbytes), "saturation_updates_per_s": bsat, "updates": len(breqs),
+                "offered_updates_per_s": rate, "served_updates_per_s": len(breqs) / wall_s,
+                "loads": res_mgr.loads - ld0, "evictions": res_mgr.evictions - ev0, "load_s": res_mgr.load_s - lds0,
+                **pp}
+            b = served["budget"]
+            log(f"served under a {budget / 1e9:.2f} GB budget (all graphs {sum(nbytes) / 1e9:.2f} GB): saturation "
+                f"{bsat:.0f}/s; at {rate:.0f}/s offered: {b['evictions']} evictions, {b['loads']} loads "
+                f"({b['load_s']:.1f}s), {b['served_updates_per_s']:.0f}/s served, p50 {pp['p50']:.2f} ms "
+                f"p99 {pp['p99']:.2f} ms")
             for i in list(res_mgr.live):
                 res_mgr.live.pop(i).free()
         else:

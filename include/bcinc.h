@@ -81,6 +81,7 @@ typedef struct {
     uint64_t memory_budget; /* admission limit for the sum of graph arenas, 0 = none */
     int32_t slots;          /* workgroup slots of the DAG kernel and the static pass, 0 = 2560 */
     int32_t block;          /* threads per workgroup of the DAG kernel (64, 128, 192 or 256), 0 = 256 */
+    const char *tune_cache; /* path of the autotuner's cache file (see bc_autotune), or NULL */
 } bc_config;
 
 typedef struct {
@@ -354,19 +355,27 @@ bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out);
 
 /* Autotuner of the launch schedule.  reqs[0..cnt) is a sample of requests
  * in bc_submit form on resident graphs (typically updates like the expected
- * stream, drawn for tuning).  For each candidate schedule (table 128 or 256;
- * block 128 or 256; wide_block 512 or 1024; big_b 512 or 1024; the other
- * fields as set)
- * the sample runs on fresh device clones of its graphs, twice (the first run
- * also captures the step graphs), and the summed device time of the second
- * run's steps ranks the candidate.  The fastest is set on the context and
- * returned in *chosen (may be NULL).  The resident graphs are never modified.
+ * stream, drawn for tuning).  The sample is split by size bucket of its
+ * graphs (ceil(log2 n)); a bucket that already has a schedule, from an
+ * earlier tuning or from the cache file, keeps it and runs nothing.  For the
+ * others, each candidate schedule (table 128 or 256; block 256, 128 or 64,
+ * the last one wave per source; wide_block 512 or 1024; big_b 512 or 1024;
+ * the other fields as set) runs the bucket's sample on fresh device clones
+ * of its graphs, twice (the first run also captures the step graphs), and
+ * the summed device time of the second run's steps ranks it.  Afterwards
+ * every step takes the schedule of its bucket (the size of its largest
+ * graph) while one is known, the context's schedule is the largest sampled
+ * bucket's (returned in *chosen, may be NULL), and when bc_config named a
+ * cache file every known bucket's schedule is written to it (JSON, with the
+ * device kind; bc_create reads it back on the same kind of device).
+ * bc_set_schedule afterwards applies its schedule to every step again.  The
+ * resident graphs are never modified.
  *   workspace: caller-owned device memory, 256-byte aligned, of at least the
  *     sum over the distinct sampled graphs of align256(bc_graph_bytes(...)),
  *     holding the clones during the call.
- * Synchronises.  Errors: BC_ERR_INVALID_ARG, BC_ERR_CAPACITY (workspace too
- * small), any validation error of the sample (the schedule is then left as
- * it was). */
+ * Synchronises.  Errors: BC_ERR_INVALID_ARG (also: the cache file cannot be
+ * written), BC_ERR_CAPACITY (workspace too small), any validation error of
+ * the sample (the schedule is then left as it was). */
 bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *workspace, uint64_t workspace_bytes,
                       bc_schedule *chosen);
 

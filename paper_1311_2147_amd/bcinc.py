@@ -48,7 +48,8 @@ class BcError(RuntimeError):
 class bc_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("flags", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_uint64),
-                ("memory_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("block", ctypes.c_int32)]
+                ("memory_budget", ctypes.c_uint64), ("slots", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class bc_edge(ctypes.Structure):
@@ -173,7 +174,7 @@ class Context:
     """A bcinc context on one GPU (bc_create / bc_destroy)."""
 
     def __init__(self, device: int = 0, n_max: int = 4096, slots: int = 0, block: int = 0, memory_budget: int = 0,
-                 stream=None, timing: bool = False, full_search: bool = False):
+                 stream=None, timing: bool = False, full_search: bool = False, tune_cache: str | None = None):
         import torch
 
         self.device = device
@@ -181,7 +182,9 @@ class Context:
         self.scratch_bytes = bc_scratch_bytes(n_max, slots)
         self._scratch, addr = _device_buffer(self.scratch_bytes, device)
         flags = (BC_FLAG_TIMING if timing else 0) | (BC_FLAG_FULL_SEARCH if full_search else 0)
-        cfg = bc_config(device, flags, self.stream.cuda_stream, addr, self.scratch_bytes, memory_budget, slots, block)
+        self._tune_cache = tune_cache.encode() if tune_cache else None
+        cfg = bc_config(device, flags, self.stream.cuda_stream, addr, self.scratch_bytes, memory_budget, slots, block,
+                        self._tune_cache)
         h = ctypes.c_void_p()
         rc = _lib.bc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != BC_OK:

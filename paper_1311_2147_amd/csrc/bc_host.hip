@@ -209,6 +209,13 @@ struct bc_ctx {
     int rows_grid = 1024;       // workgroups of the row kernel (all resident)
     int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
     bool full_search = false;  // BC_FLAG_FULL_SEARCH: the static pass relaxes every arc
+    // schedules chosen by the autotuner per size bucket (ceil(log2 n) of a
+    // step's largest graph), used while use_tuned is set; the cache file
+    // keeps them across contexts of the same device kind
+    std::map<int, bc_schedule> tuned;
+    bool use_tuned = false;
+    std::string tune_cache;
+    std::string device_tag;
     int32_t src_lds_max = 8192;  // per-source kernel stages rows up to this n in LDS
     std::vector<GraphRec *> graphs;
     std::string last_error;
@@ -609,7 +616,58 @@ bc_status shape_for(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, LaunchShape
     return BC_OK;
 }
 
+int n_bucket(int32_t n) {
+    int b = 0;
+    while (b < 31 && (int64_t(1) << b) < (int64_t)n) ++b;
+    return b;
+}
+
+void put_schedule(bc_ctx *ctx, const bc_schedule &s) {
+    ctx->block = s.block;
+    ctx->run_slots = s.slots;
+    ctx->big_b = s.big_b;
+    ctx->wide_block = s.wide_block;
+    ctx->wide_stage = s.wide_stage;
+    ctx->wide_slots = s.wide_slots;
+    ctx->table = s.table;
+}
+
+bc_schedule cur_schedule(const bc_ctx *ctx) {
+    bc_schedule s;
+    s.block = ctx->block;
+    s.slots = ctx->run_slots;
+    s.big_b = ctx->big_b;
+    s.wide_block = ctx->wide_block;
+    s.wide_stage = ctx->wide_stage;
+    s.wide_slots = ctx->wide_slots;
+    s.table = ctx->table;
+    return s;
+}
+
+// The launch schedule of one step: the tuned one of its size bucket while
+// the context uses tuned schedules, else the context's schedule.  Held for
+// the step's shape and launches, then the context's schedule is back.
+struct ScheduleScope {
+    bc_ctx *ctx;
+    bc_schedule saved{};
+    bool active = false;
+    ScheduleScope(bc_ctx *c, int32_t n_max) : ctx(c) {
+        if (!ctx->use_tuned) return;
+        auto it = ctx->tuned.find(n_bucket(n_max));
+        if (it == ctx->tuned.end()) return;
+        saved = cur_schedule(ctx);
+        put_schedule(ctx, it->second);
+        active = true;
+    }
+    ~ScheduleScope() {
+        if (active) put_schedule(ctx, saved);
+    }
+};
+
 bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_graph, StepEvents *se = nullptr) {
+    int32_t n_max = 1;
+    for (auto &j : jobs) n_max = std::max(n_max, j.g.n);
+    ScheduleScope scope(ctx, n_max);
     LaunchShape L;
     bc_status st = shape_for(ctx, jobs, &L);
     if (st) return st;
@@ -1211,6 +1269,82 @@ bc_status set_lds_limits(bc_ctx *ctx) {
 
 }  // namespace
 
+namespace {
+
+bool schedule_valid(const bc_ctx *ctx, const bc_schedule &s) {
+    return !(s.block < 64 || s.block > 256 || s.block % 64 != 0 || s.slots < 0 || s.slots > ctx->slots || s.big_b < 1 ||
+             s.big_b > LCAP || (s.wide_block != 256 && s.wide_block != 512 && s.wide_block != 1024) ||
+             (s.table != 128 && s.table != 256) || (s.wide_stage != 1 && s.wide_stage != 2) || s.wide_slots < 0 ||
+             s.wide_slots > ctx->slots);
+}
+
+// Tuning cache: a JSON object naming the device kind and listing one
+// schedule per size bucket.  Written whole (to a temporary file, then
+// renamed) after every tuning; read at bc_create.
+bc_status write_tune_cache(bc_ctx *ctx) {
+    if (ctx->tune_cache.empty()) return BC_OK;
+    const std::string tmp = ctx->tune_cache + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(ctx, BC_ERR_INVALID_ARG, "cannot write the tuning cache " + tmp);
+    fprintf(f, "{\"device\": \"%s\", \"schedules\": [", ctx->device_tag.c_str());
+    bool first = true;
+    for (auto &kv : ctx->tuned) {
+        const bc_schedule &c = kv.second;
+        fprintf(f,
+                "%s\n  {\"n_bucket\": %d, \"block\": %d, \"slots\": %d, \"big_b\": %d, \"wide_block\": %d, "
+                "\"wide_stage\": %d, \"wide_slots\": %d, \"table\": %d}",
+                first ? "" : ",", kv.first, c.block, c.slots, c.big_b, c.wide_block, c.wide_stage, c.wide_slots,
+                c.table);
+        first = false;
+    }
+    fprintf(f, "\n]}\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), ctx->tune_cache.c_str()) != 0)
+        return fail(ctx, BC_ERR_INVALID_ARG, "cannot write the tuning cache " + ctx->tune_cache);
+    return BC_OK;
+}
+
+// Reads the integer after "key": inside [p, end); false when absent.
+bool json_int(const char *p, const char *end, const char *key, int *out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const std::string hay(p, end);
+    const size_t at = hay.find(k);
+    if (at == std::string::npos) return false;
+    return sscanf(hay.c_str() + at + k.size(), " %d", out) == 1;
+}
+
+// Loads the cache's schedules when it names this device kind; entries out
+// of range for this context are skipped.  A missing file is no error.
+void read_tune_cache(bc_ctx *ctx) {
+    if (ctx->tune_cache.empty()) return;
+    FILE *f = fopen(ctx->tune_cache.c_str(), "r");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    const std::string dev = "\"device\": \"" + ctx->device_tag + "\"";
+    if (text.find(dev) == std::string::npos) return;
+    size_t pos = text.find('[');
+    while (pos != std::string::npos) {
+        const size_t a = text.find('{', pos), b = text.find('}', a == std::string::npos ? pos : a);
+        if (a == std::string::npos || b == std::string::npos) break;
+        const char *p = text.c_str() + a, *e = text.c_str() + b;
+        int bucket;
+        bc_schedule c{};
+        if (json_int(p, e, "n_bucket", &bucket) && json_int(p, e, "block", &c.block) && json_int(p, e, "slots", &c.slots) &&
+            json_int(p, e, "big_b", &c.big_b) && json_int(p, e, "wide_block", &c.wide_block) &&
+            json_int(p, e, "wide_stage", &c.wide_stage) && json_int(p, e, "wide_slots", &c.wide_slots) &&
+            json_int(p, e, "table", &c.table) && schedule_valid(ctx, c))
+            ctx->tuned[bucket] = c;
+        pos = b + 1;
+    }
+    ctx->use_tuned = !ctx->tuned.empty();
+}
+
+}  // namespace
+
 // ============================================================== C ABI ====
 
 extern "C" {
@@ -1325,6 +1459,9 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
             if (e != hipSuccess) return bail(e, "hipEventCreate");
         }
     }
+    ctx->device_tag = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    if (cfg->tune_cache) ctx->tune_cache = cfg->tune_cache;
+    read_tune_cache(ctx);
     ctx->timing = (cfg->flags & BC_FLAG_TIMING) != 0;
     ctx->full_search = (cfg->flags & BC_FLAG_FULL_SEARCH) != 0;
     {
@@ -1361,10 +1498,8 @@ bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s) {
     const int wide_stage = s->wide_stage ? s->wide_stage : ctx->wide_stage;
     const int wide_slots = s->wide_slots ? s->wide_slots : ctx->wide_slots;
     const int table = s->table ? s->table : ctx->table;
-    if (block < 64 || block > 256 || block % 64 != 0 || slots < 0 || slots > ctx->slots || big_b < 1 || big_b > LCAP ||
-        (wide_block != 256 && wide_block != 512 && wide_block != 1024) || (table != 128 && table != 256) || (wide_stage != 1 && wide_stage != 2) || wide_slots < 0 ||
-        wide_slots > ctx->slots)
-        return fail(ctx, BC_ERR_INVALID_ARG, "schedule value out of range");
+    const bc_schedule want{block, slots, big_b, wide_block, wide_stage, wide_slots, table};
+    if (!schedule_valid(ctx, want)) return fail(ctx, BC_ERR_INVALID_ARG, "schedule value out of range");
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     // captured step graphs hold the old launch shapes
@@ -1380,6 +1515,7 @@ bc_status bc_set_schedule(bc_ctx *ctx, const bc_schedule *s) {
     ctx->wide_stage = wide_stage;
     ctx->wide_slots = wide_slots;
     ctx->table = table;
+    ctx->use_tuned = false;  // this schedule serves every step until the next tuning
     return BC_OK;
 }
 
@@ -1409,6 +1545,10 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
     if (workspace_bytes < need) return fail(ctx, BC_ERR_CAPACITY, "autotune workspace below the sampled graphs' bytes");
     bc_schedule start;
     bc_get_schedule(ctx, &start);
+    // the sample's requests by size bucket of their graph; a bucket with a
+    // schedule from the cache or an earlier tuning is not tuned again
+    std::map<int, std::vector<bc_request>> by_bucket;
+    for (int32_t i = 0; i < cnt; ++i) by_bucket[n_bucket(ctx->graphs[reqs[i].graph]->n)].push_back(reqs[i]);
     const bool timing0 = ctx->timing;
     bc_status st = BC_OK;
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1417,30 +1557,33 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
     const int64_t steps0 = ctx->timed_steps;
     const uint64_t budget0 = ctx->budget;
     ctx->budget = 0;  // the clones live in the caller's workspace, outside the admission budget
-    std::vector<bc_request> mapped(reqs, reqs + cnt);
-    // one sample run on fresh clones; returns the summed step time
-    auto run = [&](double *ms) -> bc_status {
+    // one run of a bucket's sample on fresh clones; returns the summed step time
+    auto run = [&](const std::vector<bc_request> &sub, double *ms) -> bc_status {
+        std::vector<int32_t> sg;
+        for (auto &r : sub)
+            if (std::find(sg.begin(), sg.end(), r.graph) == sg.end()) sg.push_back(r.graph);
         const size_t base_id = ctx->graphs.size();
         char *p = (char *)workspace;
         bc_status s2 = BC_OK;
-        for (size_t k = 0; k < gids.size() && !s2; ++k) {
-            GraphRec *g = ctx->graphs[gids[k]];
+        for (size_t k = 0; k < sg.size() && !s2; ++k) {
+            GraphRec *g = ctx->graphs[sg[k]];
             const uint64_t b = align256(bc_graph_bytes(g->n, g->arc_cap, g->es_cap));
             bc_graph_id c;
-            s2 = bc_clone_graph(ctx, gids[k], p, b, &c);
+            s2 = bc_clone_graph(ctx, sg[k], p, b, &c);
             p += b;
         }
         if (!s2) {
+            std::vector<bc_request> mapped(sub);
             for (auto &r : mapped)
-                r.graph = (bc_graph_id)(base_id + (std::find(gids.begin(), gids.end(), r.graph) - gids.begin()));
+                r.graph = (bc_graph_id)(base_id + (std::find(sg.begin(), sg.end(), r.graph) - sg.begin()));
             ctx->step_ms = 0;
             uint64_t ticket = 0;
-            s2 = bc_submit(ctx, cnt, mapped.data(), &ticket, nullptr);
+            s2 = bc_submit(ctx, (int32_t)mapped.size(), mapped.data(), &ticket, nullptr);
             if (!s2) s2 = bc_wait(ctx, ticket);
             if (!s2 && hipStreamSynchronize(ctx->stream) != hipSuccess) s2 = fail(ctx, BC_ERR_HIP, "autotune run");
             if (!s2) s2 = harvest_all(ctx);
             *ms = ctx->step_ms;
-            for (size_t k = 0; k < gids.size() && !s2; ++k) {
+            for (size_t k = 0; k < sg.size() && !s2; ++k) {
                 int32_t status = 0;
                 s2 = read_status(ctx, ctx->graphs[base_id + k], &status);
                 if (!s2 && status) s2 = fail(ctx, sticky_to_status(status), "sample failed on a clone");
@@ -1453,41 +1596,57 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
             delete g;
             ctx->graphs.pop_back();
         }
-        for (size_t i = 0; i < mapped.size(); ++i) mapped[i].graph = reqs[i].graph;
         return s2;
     };
-    bc_schedule best = start;
-    double best_ms = 1e300;
     ctx->timing = true;
-    for (int table : {256, 128})
-        for (int block : {256, 128})
-            for (int wide_block : {512, 1024})
-                for (int big_b : {512, 1024}) {
-                    if (st) break;
-                    bc_schedule c = start;
-                    c.block = block;
-                    c.wide_block = wide_block;
-                    c.big_b = big_b;
-                    c.table = table;
-                    if ((st = bc_set_schedule(ctx, &c))) break;
-                    double ms = 0;
-                    if ((st = run(&ms))) break;
-                    if ((st = run(&ms))) break;
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        bc_get_schedule(ctx, &best);
+    bool tuned_any = false;
+    for (auto &kv : by_bucket) {
+        if (st) break;
+        if (ctx->tuned.count(kv.first)) continue;  // reused (cache or earlier tuning)
+        bc_schedule best = start;
+        double best_ms = 1e300;
+        // candidates: LDS table size, workgroup size of the DAG kernel (64 is
+        // one wave per source, no workgroup barriers), wide-kernel workgroup
+        // size and the deferral threshold
+        for (int table : {256, 128})
+            for (int block : {256, 128, 64})
+                for (int wide_block : {512, 1024})
+                    for (int big_b : {512, 1024}) {
+                        if (st) break;
+                        bc_schedule c = start;
+                        c.block = block;
+                        c.wide_block = wide_block;
+                        c.big_b = big_b;
+                        c.table = table;
+                        if ((st = bc_set_schedule(ctx, &c))) break;
+                        double ms = 0;
+                        if ((st = run(kv.second, &ms))) break;
+                        if ((st = run(kv.second, &ms))) break;
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best = c;
+                        }
                     }
-                }
+        if (!st) {
+            ctx->tuned[kv.first] = best;
+            tuned_any = true;
+        }
+    }
     ctx->timing = timing0;
     ctx->step_ms = step0;
     ctx->source_ms = src0;
     ctx->rows_ms = rows0;
     ctx->timed_steps = steps0;
     ctx->budget = budget0;
-    bc_status st2 = bc_set_schedule(ctx, st ? &start : &best);
+    // the context's schedule becomes the largest sampled bucket's, and
+    // every step takes its own bucket's while one is known
+    const bc_schedule pick = st ? start : ctx->tuned[by_bucket.rbegin()->first];
+    bc_status st2 = bc_set_schedule(ctx, &pick);
     if (st) return st;
     if (st2) return st2;
-    if (chosen) *chosen = best;
+    ctx->use_tuned = true;
+    if (tuned_any && (st = write_tune_cache(ctx))) return st;
+    if (chosen) *chosen = pick;
     return BC_OK;
 }
 
@@ -1698,10 +1857,12 @@ bc_status bc_update_vertex(bc_ctx *ctx, bc_graph_id gid, int32_t v, int32_t k, c
     return BC_OK;
 }
 
+namespace {
+
 // Validates requests as one call (none is taken if one fails): each request's
 // jobs, in order, with the graphs' arc changes applied to their mirrors.
 // req_jobs[i] holds request i's jobs.
-bc_status validate_requests(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, int32_t *bad_index,
+static bc_status validate_requests(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, int32_t *bad_index,
                             std::vector<std::vector<UpdateJob>> &req_jobs) {
     std::map<int32_t, Pending> pend;
     req_jobs.assign((size_t)cnt, {});
@@ -1722,6 +1883,8 @@ bc_status validate_requests(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, in
     for (int32_t i = 0; i < cnt; ++i) ctx->graphs[reqs[i].graph]->updates += 1;
     return BC_OK;
 }
+
+}  // namespace
 
 bc_status bc_submit(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, uint64_t *ticket, int32_t *bad_index) {
     if (!ctx || cnt < 0 || (cnt > 0 && !reqs) || !ticket) return fail(ctx, BC_ERR_INVALID_ARG, "bad arguments to bc_submit");

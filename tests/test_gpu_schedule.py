@@ -138,3 +138,45 @@ def test_autotune_keeps_graphs_and_sets_a_candidate():
         cur = W.apply_update(cur, up)
     check_full(a, cur, "after autotune")
     ctx.close()
+
+
+def test_autotune_cache_is_reused_per_size_bucket(tmp_path):
+    """Schedules are tuned per size bucket and kept in the cache file; a
+    second context on the same device kind reads them back and its autotune
+    call on a fresh sample runs nothing; steps then take their bucket's
+    schedule and still reach the oracle's state."""
+    import json
+    import time
+
+    path = str(tmp_path / "tune.json")
+    g1 = W.random_small(200, 0.04, 30, seed=81, directed=True)    # bucket 8
+    g2 = W.random_small(1100, 0.006, 30, seed=82, directed=True)  # bucket 11
+    ctx = make_ctx(1100, slots=16, tune_cache=path)
+    a, b = ctx.load_graph(g1), ctx.load_graph(g2)
+    sample = [(a, up) for up in W.mixed_stream(g1, 4, 30, 83, 0.35, 0.35, 8)]
+    sample += [(b, up) for up in W.mixed_stream(g2, 4, 30, 84, 0.35, 0.35, 8)]
+    t0 = time.perf_counter()
+    first = ctx.autotune(sample)
+    tune_s = time.perf_counter() - t0
+    ctx.close()
+    cache = json.load(open(path))
+    buckets = {e["n_bucket"]: e for e in cache["schedules"]}
+    assert set(buckets) == {8, 11}, f"cache buckets {sorted(buckets)}"
+    assert first == {k: buckets[11][k] for k in first}, "the context takes the largest bucket's schedule"
+    ctx2 = make_ctx(1100, slots=16, tune_cache=path)
+    a2, b2 = ctx2.load_graph(g1), ctx2.load_graph(g2)
+    sample2 = [(a2, up) for up in W.mixed_stream(g1, 4, 30, 85, 0.35, 0.35, 8)]
+    sample2 += [(b2, up) for up in W.mixed_stream(g2, 4, 30, 86, 0.35, 0.35, 8)]
+    t0 = time.perf_counter()
+    again = ctx2.autotune(sample2)
+    reuse_s = time.perf_counter() - t0
+    say(f"tuning {tune_s:.2f}s, cached {reuse_s:.3f}s, schedules {cache['schedules']}")
+    assert again == first
+    assert reuse_s < tune_s / 5, "the cached schedules were tuned again"
+    for gr, g, seed in ((a2, g1, 87), (b2, g2, 88)):
+        cur = g
+        for up in W.mixed_stream(g, 8, 30, seed, 0.35, 0.35, 8):
+            gr.update(up)
+            cur = W.apply_update(cur, up)
+        check_full(gr, cur, f"n={g.n} under its bucket's schedule")
+    ctx2.close()

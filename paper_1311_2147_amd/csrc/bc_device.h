@@ -66,7 +66,8 @@ struct GraphCtl {
     alignas(256) int32_t work_next;    // next item of the persistent per-source kernel
     alignas(256) int32_t dag_count;    // listed sources with many changed targets: dlist[0 .. dag_count)
     alignas(256) int32_t dag_back;     // listed sources with few: dlist[n - dag_back .. n)
-    alignas(256) int32_t dag_next;     // next listed source of the DAG kernel
+    alignas(256) int32_t dag_next;     // next listed source with many changed targets (DAG kernel)
+    alignas(256) int32_t dag_next_light;  // next listed source with few
     alignas(256) int32_t big_count;    // deferred (large) sources of the update in flight
     alignas(256) int32_t big_next;     // next deferred source to process
     alignas(256) unsigned long long changed_pairs;  // statistic of the last update

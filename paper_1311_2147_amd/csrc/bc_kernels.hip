@@ -2575,22 +2575,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     const int tid = threadIdx.x, bs = blockDim.x;
     const int njobs = *njobs_p;
     const USlot u = uslot_at(scratch + (size_t)blockIdx.x * slot_bytes, n_layout);
+    // the heavy sources of every job first (the front of each job's list),
+    // then the light ones (the back): a step's long sub-DAG passes start
+    // early whatever job they belong to, and the light sources fill the tail
+    for (int phase = 0; phase < 2; ++phase)
     for (int j = 0; j < njobs; ++j) {
         const UpdateJob &J = jobs[j];
         if (job_halted(J)) continue;
         GraphCtl *ctl = J.g.ctl;
         const int32_t n = J.g.n;
         const bool lds = n <= lds_cap;
-        // heavy sources (front of the list) first, then the others (back)
-        const int32_t front = *(volatile int32_t *)&ctl->dag_count;
-        const int32_t count = front + *(volatile int32_t *)&ctl->dag_back;
+        const int32_t count = phase == 0 ? *(volatile int32_t *)&ctl->dag_count : *(volatile int32_t *)&ctl->dag_back;
+        int32_t *const next = phase == 0 ? &ctl->dag_next : &ctl->dag_next_light;
         for (;;) {
             __syncthreads();
-            if (tid == 0) sh.item = atomicAdd(&ctl->dag_next, 1);
+            if (tid == 0) sh.item = atomicAdd(next, 1);
             __syncthreads();
             const int32_t item = sh.item;
             if (item >= count) break;
-            const DItem it = J.g.dlist[item < front ? item : n - 1 - (item - front)];
+            const DItem it = J.g.dlist[phase == 0 ? item : n - 1 - item];
             if (lds) {
                 const int32_t *Dg = J.g.D + (size_t)it.s * n;
                 for (int32_t t = tid; t < n; t += bs) lds_row[t] = Dg[t];
@@ -2858,6 +2861,7 @@ __global__ void __launch_bounds__(256) k_commit(const UpdateJob *__restrict__ jo
             c->big_next = 0;
             c->dag_count = 0;
             c->dag_next = 0;
+            c->dag_next_light = 0;
             c->dag_back = 0;
         }
     }
@@ -2877,6 +2881,7 @@ __global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__res
         c->big_next = 0;
         c->dag_count = 0;
         c->dag_next = 0;
+        c->dag_next_light = 0;
         c->dag_back = 0;
     }
 }

@@ -2042,13 +2042,20 @@ bc_status bc_sync(bc_ctx *ctx) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     bc_status fs = flush_queues(ctx);
     if (fs) return fs;
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (auto *g : ctx->graphs) {
-        if (!g || !g->live) continue;
-        int32_t st = 0;
-        bc_status s = read_status(ctx, g, &st);
-        if (s) return s;
-        if (st) return sticky_to_status(st);
+    // every live graph's status word, copied behind the work into pinned
+    // memory, then one wait
+    for (size_t b = 0; b < ctx->graphs.size(); b += STATUS_BATCH) {
+        const size_t e = std::min(ctx->graphs.size(), b + STATUS_BATCH);
+        int used = 0;
+        for (size_t k = b; k < e; ++k) {
+            GraphRec *g = ctx->graphs[k];
+            if (!g || !g->live) continue;
+            HIPCHK(hipMemcpyAsync(ctx->h_status + used, &g->P.ctl->status, 4, hipMemcpyDeviceToHost, ctx->stream));
+            ++used;
+        }
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        for (int k = 0; k < used; ++k)
+            if (ctx->h_status[k]) return sticky_to_status(ctx->h_status[k]);
     }
     return BC_OK;
 }

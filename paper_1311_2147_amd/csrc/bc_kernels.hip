@@ -2504,7 +2504,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
                                               const int32_t *__restrict__ Bd, const uint64_t *__restrict__ Bs,
                                               const int32_t nb, const bool lds, int32_t *lds_row, const USlot &u,
                                               BlockShared &sh, const ExpandShared &es, const SmallDag &sd,
-                                              const DualDag &dd, const bool try_small) {
+                                              const DualDag &dd) {
     const int tid = threadIdx.x, bs = blockDim.x;
     const int32_t n = J.g.n;
     int32_t *const Dg = J.g.D + (size_t)s * n;
@@ -2516,19 +2516,16 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     // half that many or more almost never fits (on the Chung-Lu headline
     // window, 120 of 20 600 such sources fit with the 128-slot table), so
     // those skip the union walk; the new sub-DAG alone often fits
-    const bool fits = try_small && nb < TS * 3 / 4;
-    const bool dual_fits = try_small && nb < TS * 3 / 8;
+    const bool fits = nb < TS * 3 / 4;
+    const bool dual_fits = nb < TS * 3 / 8;
     int32_t *const pred_row = J.g.pred + (size_t)s * n;
     const bool dual = dual_fits && dual_pass<TS>(s, Drow, Sg, J.g.xc_ptr, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, Bd, Bs,
                                             pred_row, nb, bc_delta, sh, es, dd);
-    // a large B (here 1/16 of the row or more) makes the sub-DAG most of
-    // DAG(s): take every vertex's DAG in-arcs instead of walking back from B
-    const bool full = !try_small && (int64_t)nb * 16 >= (int64_t)n;
     // when the union outgrew the table it is mostly the old sub-DAG that did:
     // the old pass goes straight to the slot (it follows stored
     // predecessors), the new one tries the LDS table first
     if (!dual)
-        restricted_pass<false, XU>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, full, u,
+        restricted_pass<false, XU>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, false, u,
                                    -1.0, bc_delta, pred_row, nullptr, true, sh, es);
     for (int32_t i = tid; i < nb; i += bs) {
         const int32_t t = Bt[i];
@@ -2550,7 +2547,7 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     if (!fits ||
         !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, pred_row, sh, es, sd))
         preds_done = restricted_pass<false, XU>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb,
-                                                full, u, 1.0, bc_delta, pred_row, pred_row, false, sh, es);
+                                                false, u, 1.0, bc_delta, pred_row, pred_row, false, sh, es);
     if (!preds_done) refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, pred_row, sh, es);
 }
 
@@ -2600,7 +2597,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                 __syncthreads();
             }
             update_source<TS>(J, it.s, pool.t + it.off, pool.d + it.off, pool.s + it.off, it.nb, lds, lds_row, u, sh, es,
-                          sd, dd, true);
+                          sd, dd);
         }
     }
 }
@@ -2698,7 +2695,13 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
             }
             if (nb == 0) continue;
             if (role != 1 && tid == 0) sh.counter += (unsigned long long)nb;
-            const bool full = (int64_t)nb * 16 >= (int64_t)n;
+            // a B of half the row or more makes the sub-DAG most of DAG(s):
+            // take every vertex's DAG in-arcs instead of walking back from B.
+            // Below that the walk is cheaper: a hub update's changed targets
+            // hang mostly below the hub, so their new ancestors are little
+            // more than B itself (a hub update with 19 000 deferred sources
+            // took 80 ms this way, 127 ms with whole-DAG passes from 1/16)
+            const bool full = (int64_t)nb * 2 >= (int64_t)n;
             bool preds_done = false;
             // phase 0: old pass (roles 0 and 2); phase 1: new pass (roles 1 and 2)
             for (int ph = role == 1 ? 1 : 0; ph <= (role == 0 ? 0 : 1); ++ph) {
@@ -2731,15 +2734,18 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                     }
                     __syncthreads();
                 }
-                // B vertices are always tested, so the old pass of a source never
-                // uses a stored predecessor that its new pass (another
-                // workgroup, at the same time) rewrites: its walk may load one
-                // ahead, but stops at the B vertex, which is in the sub-DAG from
-                // the start
+                // The old pass of a paired source tests its B vertices' E*
+                // in-arcs, so it never uses a stored predecessor that its new
+                // pass (another workgroup, at the same time) rewrites: its walk
+                // may load one ahead, but stops at the B vertex, which is in the
+                // sub-DAG from the start.  A source updated by one workgroup
+                // rewrites its predecessors only in the new pass, so its old
+                // pass takes the B vertices' stored (old) predecessors
                 preds_done = restricted_pass<false, 2, 4>(
                     s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
                     ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u, ph ? 1.0 : -1.0,
-                    J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr, false, sh, es);
+                    J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr,
+                    role == 2 && ph == 0, sh, es);
             }
             // the new row of the new pass: in LDS, in the slot (role 1 without
             // staging) or written back to D (role 2)

@@ -1046,7 +1046,7 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
                 if (x < n) {
                     const int32_t dx = Drow[x], o = u.outdeg[x], pr = pred[x];
                     live[k] = x != s && dx != INF32;
-                    pv[k] = (o & W_B) ? PRED_MULTI : pr;
+                    pv[k] = ((o & W_B) && !b_pred) ? PRED_MULTI : pr;
                 }
             }
 #pragma unroll
@@ -1182,7 +1182,7 @@ __device__ bool restricted_pass(const int32_t s, const int32_t n, const int32_t 
             // idle until the walk ends)
             for (int32_t idx = lo + tid; idx < hi; idx += bs) {
                 const int32_t x = u.sub[idx];
-                const int32_t p = (pred && !(u.outdeg[x] & W_B)) ? pred[x] : PRED_MULTI;
+                const int32_t p = (pred && (b_pred || !(u.outdeg[x] & W_B))) ? pred[x] : PRED_MULTI;
                 if (p < 0) {
                     u.q1[atomicAdd(&sh.head, 1)] = x;
                     continue;
@@ -1588,8 +1588,8 @@ template <int TS>
 __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, const uint64_t *__restrict__ Srow,
                            const int32_t *__restrict__ cptr, const int32_t *__restrict__ csrc,
                            const int32_t *__restrict__ cw, const int32_t *__restrict__ Bt, const int32_t nB,
-                           const double sign, double *out, const int32_t *__restrict__ pred, BlockShared &sh,
-                           const ExpandShared &es, const SmallDag &d) {
+                           const double sign, double *out, const int32_t *__restrict__ pred, const bool b_pred,
+                           BlockShared &sh, const ExpandShared &es, const SmallDag &d) {
     SD_CONSTS
     const int tid = threadIdx.x, bs = blockDim.x;
     for (int32_t i = tid; i < SD_SLOTS; i += bs) {
@@ -1628,13 +1628,13 @@ __device__ bool small_pass(const int32_t s, const int32_t *__restrict__ Drow, co
     while (lo < hi) {
         if (tid == 0) sh.head = 0;
         __syncthreads();
-        // a vertex outside B with one stored predecessor: that arc, at once;
-        // the others (their E* in-arcs tested) listed in d.round, idle
-        // until the accumulation
+        // a vertex with one stored predecessor (outside B, or any with
+        // b_pred): that arc, at once; the others (their E* in-arcs tested)
+        // listed in d.round, idle until the accumulation
         for (int32_t idx = lo + tid; idx < hi; idx += bs) {
             const int32_t sx = d.sub[idx];
             const int32_t x = d.key[sx];
-            const int32_t p = (pred && !(d.flags[sx] & F_B)) ? pred[x] : PRED_MULTI;
+            const int32_t p = (pred && (b_pred || !(d.flags[sx] & F_B))) ? pred[x] : PRED_MULTI;
             if (p < 0) {
                 d.round[atomicAdd(&sh.head, 1)] = sx;
                 continue;
@@ -2491,6 +2491,23 @@ __global__ void __launch_bounds__(256) k_rows(const UpdateJob *__restrict__ jobs
     }
 }
 
+// Alg 2 (Update-DAG) on the stored predecessors, for a one-arc update (u, v)
+// and a changed target t of source s.  A target whose distance fell
+// (WT-changed) has exactly its DAG(v) in-arcs as DAG'(s) in-arcs, or the arc
+// (u, v) alone when t = v; one whose distance stayed (NUM-changed) keeps its
+// old in-arcs and gains those (at v: gains (u, v), so it has two or more).
+// DAG(v) itself does not change (no shortest path from v enters v again), so
+// row v of the predecessors is read as it stands while other rows change.
+__device__ __forceinline__ bool one_arc_job(const UpdateJob &J) { return J.n_in == 1 && J.n_out == 0; }
+
+__device__ __forceinline__ int32_t edge_pred(const UpdateJob &J, const int32_t t, const int32_t old_pred,
+                                             const bool fell) {
+    if (t == J.v) return fell ? J.in_tail[0] : PRED_MULTI;
+    const int32_t pv = J.g.pred[(size_t)J.v * J.g.n + t];
+    if (fell) return pv;
+    return old_pred >= 0 && old_pred == pv ? pv : PRED_MULTI;
+}
+
 // One listed source with its changed targets B (Bt, Bd, Bs; nb of them):
 // both partial dependencies in one traversal in LDS (dual_pass) and then the
 // changed pairs written to D and sigma; or, when the two sub-DAGs do not fit
@@ -2527,9 +2544,14 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     if (!dual)
         restricted_pass<false, XU>(s, n, Drow, Sg, J.g.xc_ptr, J.g.xc_src, J.g.xc_dst, J.g.xc_w, Bt, nb, false, u,
                                    -1.0, bc_delta, pred_row, nullptr, true, sh, es);
+    // a one-arc update gives the changed targets' new predecessors by Alg 2
+    // (before the old distances are overwritten); the new pass then follows
+    // them like any stored predecessor and tests no E* in-arcs of B
+    const bool edge = one_arc_job(J);
     for (int32_t i = tid; i < nb; i += bs) {
         const int32_t t = Bt[i];
         const int32_t d = Bd[i];
+        if (edge && !dual) pred_row[t] = edge_pred(J, t, pred_row[t], d < Drow[t]);
         Sg[t] = Bs[i];
         Dg[t] = d;
         if (lds) lds_row[t] = d;
@@ -2541,14 +2563,16 @@ __device__ __forceinline__ void update_source(const UpdateJob &J, const int32_t 
     }
     __syncthreads();
     if (dual) return;
-    // the new pass reads the stored predecessors of unchanged pairs only, so
-    // it may write the changed targets' new ones from its arc record
+    // the new pass reads the stored predecessors of unchanged pairs only (and
+    // of a one-arc update's changed targets, written above), so it may write
+    // the changed targets' new ones from its arc record
     bool preds_done = false;
-    if (!fits ||
-        !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, pred_row, sh, es, sd))
+    if (!fits || !small_pass<TS>(s, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, 1.0, bc_delta, pred_row,
+                                 edge, sh, es, sd))
         preds_done = restricted_pass<false, XU>(s, n, Drow, Sg, J.g.yc_ptr, J.g.yc_src, J.g.yc_dst, J.g.yc_w, Bt, nb,
-                                                false, u, 1.0, bc_delta, pred_row, pred_row, false, sh, es);
-    if (!preds_done) refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, pred_row, sh, es);
+                                                false, u, 1.0, bc_delta, pred_row, edge ? nullptr : pred_row, edge, sh,
+                                                es);
+    if (!preds_done && !edge) refresh_preds<4>(Drow, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, Bt, nb, pred_row, sh, es);
 }
 
 // DAG kernel (persistent): workgroups pull the sources the row kernel listed
@@ -2657,6 +2681,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
         const int32_t t_count = *(volatile int32_t *)&ctl->t_count;
         const bool use_tlist = (int64_t)t_count * 8 <= (int64_t)n;
         const BList L{u.bl_t, u.bl_d, u.bl_s, n};
+        const bool edge = one_arc_job(J);
         if (tid == 0) sh.counter = 0;
         bool ovf_s = false, ovf_d = false;
         for (;;) {
@@ -2674,6 +2699,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
             const int role = unit < 2 * paired ? (unit & 1) : 2;
             const int32_t s = J.g.biglist[item];
             const SrcScal sc = J.g.scal[s];
+            int32_t *const pred_row = J.g.pred + (size_t)s * n;
             const int32_t *Dg = J.g.D + (size_t)s * n;
             const uint64_t *Sg = J.g.S + (size_t)s * n;
             if (lds) {
@@ -2716,8 +2742,10 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                         for (int32_t t = tid; t < n; t += bs) u.snew[t] = Sg[t];
                         __syncthreads();
                         for (int32_t i = tid; i < nb; i += bs) {
-                            Dn[u.bl_t[i]] = u.bl_d[i];
-                            u.snew[u.bl_t[i]] = u.bl_s[i];
+                            const int32_t t = u.bl_t[i];
+                            if (edge) pred_row[t] = edge_pred(J, t, pred_row[t], u.bl_d[i] < Dn[t]);
+                            Dn[t] = u.bl_d[i];
+                            u.snew[t] = u.bl_s[i];
                         }
                         Dr = Dn;
                         Sr = u.snew;
@@ -2727,6 +2755,7 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                         for (int32_t i = tid; i < nb; i += bs) {
                             const int32_t t = u.bl_t[i];
                             const int32_t d = u.bl_d[i];
+                            if (edge) pred_row[t] = edge_pred(J, t, pred_row[t], d < (lds ? lds_row[t] : Dw[t]));
                             Sw[t] = u.bl_s[i];
                             Dw[t] = d;
                             if (lds) lds_row[t] = d;
@@ -2739,19 +2768,21 @@ __global__ void __launch_bounds__(1024) k_source_wide(const UpdateJob *__restric
                 // pass (another workgroup, at the same time) rewrites: its walk
                 // may load one ahead, but stops at the B vertex, which is in the
                 // sub-DAG from the start.  A source updated by one workgroup
-                // rewrites its predecessors only in the new pass, so its old
-                // pass takes the B vertices' stored (old) predecessors
+                // rewrites its predecessors only after the old pass, so that
+                // pass takes the B vertices' stored (old) predecessors.  The new
+                // pass of a one-arc update takes theirs from Alg 2 (written
+                // above); other updates test the B vertices' E* in-arcs and
+                // write the predecessors from the arc record
                 preds_done = restricted_pass<false, 2, 4>(
                     s, n, Dr, Sr, ph ? J.g.yc_ptr : J.g.xc_ptr, ph ? J.g.yc_src : J.g.xc_src,
                     ph ? J.g.yc_dst : J.g.xc_dst, ph ? J.g.yc_w : J.g.xc_w, u.bl_t, nb, full, u, ph ? 1.0 : -1.0,
-                    J.g.bc_delta, J.g.pred + (size_t)s * n, ph ? J.g.pred + (size_t)s * n : nullptr,
-                    role == 2 && ph == 0, sh, es);
+                    J.g.bc_delta, pred_row, ph && !edge ? pred_row : nullptr, ph ? edge : role == 2, sh, es);
             }
             // the new row of the new pass: in LDS, in the slot (role 1 without
             // staging) or written back to D (role 2)
-            if (role != 0 && !preds_done)
+            if (role != 0 && !preds_done && !edge)
                 refresh_preds<1>(lds ? lds_row : role == 1 ? u.dnew : Dg, J.g.yc_ptr, J.g.yc_src, J.g.yc_w, u.bl_t, nb,
-                                 J.g.pred + (size_t)s * n, sh, es);
+                                 pred_row, sh, es);
         }
         if (ovf_s) atomicOr(&ctl->status, ST_SIGMA_OVF);
         if (ovf_d) atomicOr(&ctl->status, ST_DIST_OVF);

@@ -33,3 +33,35 @@ def test_stored_predecessors_of_every_source(case):
         check_preds(gr, cur, range(g.n), f"{case} #{i}")
     say(f"[{case}] {len(ups)} updates, predecessors of all {g.n} sources checked after each")
     ctx.close()
+
+
+@pytest.mark.parametrize("sch", [{"big_b": 1, "wide_stage": 1, "wide_block": 1024, "block": 128, "table": 128},
+                                 {"big_b": 4, "wide_stage": 2, "wide_block": 256, "block": 64, "table": 256}])
+@pytest.mark.parametrize("case", ["ties", "spread"])
+def test_stored_predecessors_through_the_wide_kernel(case, sch):
+    """Arc updates only (Alg 2 gives the changed targets' new predecessors),
+    with deferral thresholds that send most affected sources through the wide
+    kernel: the first 16 as paired old and new passes on two workgroups, the
+    rest as one workgroup each.  Ties (weights 1 and 2) make many changed
+    targets keep their distance and gain paths, whose new in-arcs are the old
+    ones and row v's."""
+    if case == "ties":
+        g = W.random_small(140, 0.05, 2, seed=11, directed=True)
+        ups = W.mixed_stream(g, 14, 2, 12, 0.5, 0.5, 1)
+    else:
+        g = W.random_small(160, 0.04, 1000, seed=13, directed=True)
+        ups = W.mixed_stream(g, 14, 1000, 14, 0.5, 0.5, 1)
+    assert all(up.kind == "edge" for up in ups)
+    ctx = make_ctx(g.n, slots=16)
+    ctx.set_schedule(**sch)
+    gr = ctx.load_graph(g)
+    cur = g
+    deferred = 0
+    for i, up in enumerate(ups):
+        gr.update(up)
+        deferred += gr.stats()["deferred_sources"]
+        cur = W.apply_update(cur, up)
+        check_preds(gr, cur, range(g.n), f"{case} {sch} #{i}")
+    assert deferred > 16 * 2, "the stream should defer sources past the paired ones"
+    say(f"[{case} {sch}] {len(ups)} arc updates, {deferred} deferred sources, all predecessors checked after each")
+    ctx.close()

@@ -2199,6 +2199,15 @@ struct BList {
     int32_t cap;
 };
 
+// A streamed row quad.  Each affected row is read once per update, so its
+// loads are nontemporal: they do not displace the filter row, which every
+// row of the update reads again, from the caches.
+__device__ __forceinline__ int4 load_stream(const int4 *p) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i t = __builtin_nontemporal_load((const v4i *)p);
+    return make_int4(t.x, t.y, t.z, t.w);
+}
+
 // Bit mask of the pairs of one quad that may change (dv finite).
 __device__ __forceinline__ uint32_t quad_mask(const int4 d, const int4 f, const int32_t dv) {
     return (may_change1(d.x, dv, f.x) ? 1u : 0u) | (may_change1(d.y, dv, f.y) ? 2u : 0u) |
@@ -2248,7 +2257,7 @@ __device__ __forceinline__ void scan_row(const UpdateJob &J, const RowV &R, cons
 #pragma unroll
             for (int k = 0; k < QU; ++k) {
                 const int32_t q = q0 + k * bs;
-                dq[k] = (q < nq) ? D4[q] : make_int4(0, 0, 0, 0);
+                dq[k] = (q < nq) ? load_stream(D4 + q) : make_int4(0, 0, 0, 0);
                 fq[k] = (q < nq) ? F4[q] : make_int4(INF32, INF32, INF32, INF32);
             }
             uint32_t m = 0;

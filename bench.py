@@ -447,9 +447,35 @@ def main():
             res["by_n"] = by_n
             return res
 
-        sat = run(part(n_sat), None, 0)
+        # the plain path on the closed loop's requests: device clones of the 8
+        # graphs taken before it get the same requests one at a time (in the
+        # order they were queued, which keeps each graph's order), default
+        # schedule, bc_update_* and bc_sync after each; both must end in the
+        # same state
+        c5_twins = [gr.clone() for gr in sg]
+        ctx.sync()
+        sat_reqs = part(n_sat)
+        sat = run(sat_reqs, None, 0)
         sat_rate = sat["served_updates_per_s"]
         log(f"served closed loop: {sat_rate:.1f} updates/s, {sat['mean_requests_per_step']:.2f} requests per step")
+        ctx.set_schedule(**default_sched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for gi, up in sat_reqs:
+            c5_twins[gi].update(up)
+            ctx.sync()
+        c5_plain_s = time.perf_counter() - t0
+        ctx.set_schedule(**tuned)
+        c5_same = all(c5_twins[i].state_hash() == sg[i].state_hash() for i in range(len(sg)))
+        sat["plain_updates_per_s"] = len(sat_reqs) / c5_plain_s
+        sat["served_over_plain"] = sat_rate / sat["plain_updates_per_s"]
+        sat["plain_same_state"] = c5_same
+        log(f"plain path on the closed loop's {len(sat_reqs)} requests (clones): {sat['plain_updates_per_s']:.1f} "
+            f"updates/s; served/plain {sat['served_over_plain']:.2f}, same state {c5_same}")
+        for tw in c5_twins:
+            tw.free()
+        del c5_twins
+        torch.cuda.empty_cache()
         sweep = []
         for frac, cnt, seed in ((0.5, n_lo, 5101), (0.8, args.served_updates, 5102), (0.95, n_hi, 5103)):
             res = run(part(cnt), frac * sat_rate, W.derive_seed(5, seed))
@@ -460,6 +486,7 @@ def main():
                 f"{res['served_updates_per_s']:.0f}/s served, p50 {res['p50']:.2f} ms, p99 {res['p99']:.2f} ms; "
                 + ", ".join(f"n={k} p50 {v['p50']:.2f} p99 {v['p99']:.2f}" for k, v in res["by_n"].items()))
         served = {"graphs": [g.n for g in c5], "load_s": c5_load_s, "saturation": sat, "sweep": sweep}
+        comparators["served_over_plain"] = sat["served_over_plain"]
 
         # admission under a memory budget: the 8 graphs' arenas less half an
         # n=4096 arena, so one graph stays off the device at any time;

@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark: incremental betweenness-centrality updates per second at n = 32768.
 
-Workload (synthetic, seeded): two resident directed Chung-Lu graphs with
-n = 32768, degree exponent 2.5, mean out-degree 16 (m = 16n arcs), integer
+Workload (synthetic, seeded): six resident directed Chung-Lu graphs with
+n = 32768 (17.2 GB of state each), degree exponent 2.5, mean out-degree 16 (m = 16n arcs), integer
 weights uniform in {1..1000}; each graph gets its own stream of updates drawn
 35% insertions, 35% decreases to a uniform lower weight, 30% vertex updates
 touching 16 incident arcs.  Inputs are resident in HBM before timing starts.
@@ -14,7 +14,7 @@ captured HIP graphs.  value = updates completed per second over the timed
 steps.
 
 Besides the headline the run measures:
-  * the plain path on the same updates: device clones of both graphs taken
+  * the plain path on the same updates: device clones of the graphs taken
     before the timed window get the same requests one at a time, with the
     library's default schedule, synchronised after each, launched directly
     (no HIP graph, no batching); both legs must reach the same state;
@@ -24,7 +24,9 @@ Besides the headline the run measures:
     search over a subset containing E*, against the search over every arc;
   * a dedicated 1000-update stream on one freshly loaded graph;
   * the served workload at full shape: 8 resident Chung-Lu graphs (n = 4096,
-    8192, 16384, 32768, two of each) and Poisson streams over them, served by
+    8192, 16384, 32768, two of each), a closed loop for the saturation rate
+    (and the plain path on its requests, on clones), and Poisson streams over
+    them, served by
     continuous batching at 0.5, 0.8 (10,000 updates) and 0.95 times the
     closed-loop saturation rate, p50/p99 per graph size; then admission
     under a memory budget that holds only some graphs at once;
@@ -60,15 +62,20 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def committed_traffic():
+def committed_traffic(graphs: int, n: int):
     """HBM bytes per row-kernel launch from the committed counter summary,
-    or None when there is none or the kernel sources changed since."""
+    or None when there is none, the kernel sources changed since, or it was
+    taken on another workload (graphs per launch, n)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
     sha = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", text)
     val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not sha or not val or sha.group(1) != kernel_sources_sha256():
+    g = re.search(r"graphs_per_launch:\s*(\d+)", text)
+    nn = re.search(r"vertices:\s*(\d+)", text)
+    if not sha or not val or not g or not nn or sha.group(1) != kernel_sources_sha256():
+        return None
+    if int(g.group(1)) != graphs or int(nn.group(1)) != n:
         return None
     return float(val.group(1))
 
@@ -93,7 +100,7 @@ def main():
     ap.add_argument("--steps", type=int, default=150)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=32768)
-    ap.add_argument("--graphs", type=int, default=2)
+    ap.add_argument("--graphs", type=int, default=6)
     ap.add_argument("--legs", default="batched,plain,recompute,loader,single,served,budget,cpuinc,cpu,copy")
     ap.add_argument("--served-updates", type=int, default=10000, help="updates of the 0.8x served run")
     ap.add_argument("--cpu-updates", type=int, default=12, help="updates of the CPU incremental comparator's sample")
@@ -121,7 +128,7 @@ def main():
     # ---------------------------------------------------------------- inputs
     t = time.perf_counter()
     sizes = list(W.C5_SIZES)
-    gidx = [i for i in range(8) if sizes[i % 4] == n][:G] if n in sizes else list(range(G))
+    gidx = [i for i in range(4 * G) if sizes[i % 4] == n][:G] if n in sizes else list(range(G))
     graphs = [W.config5_graph(n, gi) for gi in gidx]
     per_graph = Wm + K + 8
     streams = [W.mixed_stream(g, per_graph, 1000, W.derive_seed(5, 2000 + gi), 0.35, 0.35, 16)
@@ -622,7 +629,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": committed_traffic(),
+            "traffic": committed_traffic(G, n),
             "copy_gbs": copy_gbs,
             "window": "the timed batched steps",
             "avg_launch_ms": rows_ms / launches,

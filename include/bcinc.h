@@ -203,15 +203,18 @@ typedef struct {
     int64_t t_finish_ns;   /* when done */
 } bc_result;
 
-/* bc_poll fills *out without waiting.  Once it reports done the ticket is
- * collected: polling it again reports done with status BC_OK and zero times.
- * bc_wait launches the ticket's queued requests if any, waits for its last
- * step and collects it. */
+/* bc_poll fills *out without waiting; out->status is the sticky error of
+ * any of the ticket's graphs once it is done (sigma overflow first, then
+ * distance overflow, then E* capacity), else BC_OK.  Once it reports done the
+ * ticket is collected: polling it again reports done with status BC_OK and
+ * zero times.  bc_wait launches the ticket's queued requests if any, waits
+ * for its last step, collects it and returns that same status. */
 bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, bc_result *out);
 bc_status bc_wait(bc_ctx *ctx, uint64_t ticket);
 
 /* Launches every queued request, waits for all work of the context, and
- * returns the first sticky error of any graph, or BC_OK. */
+ * returns the sticky error of any graph (sigma overflow first, then distance
+ * overflow, then E* capacity), or BC_OK. */
 bc_status bc_sync(bc_ctx *ctx);
 
 /* BC(v) for all v (Eq.3 over ordered pairs) into host memory out[0..n).

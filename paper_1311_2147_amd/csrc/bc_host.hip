@@ -287,6 +287,10 @@ char *misc_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes(); }
 int64_t pool_entries(int32_t n_max) { return std::max<int64_t>(int64_t(1) << 20, 256 * (int64_t)n_max); }
 size_t pool_bytes(int32_t n_max) { return align256(16 * (size_t)pool_entries(n_max)); }
 char *pool_dev(bc_ctx *ctx) { return ctx->scratch + ring_bytes() + MISC_BYTES; }
+// Device staging of the status gather, one area per stream that reads status
+// back (the main stream and the clock stream); each holds STATUS_BATCH words.
+int32_t *status_dev(bc_ctx *ctx, bool clock) { return (int32_t *)(misc_dev(ctx) + (clock ? 3072 : 1024)); }
+static_assert(1024 + 4 * STATUS_BATCH <= 2048 && 3072 + 4 * STATUS_BATCH <= MISC_BYTES, "status staging areas");
 StepPool step_pool(bc_ctx *ctx) {
     StepPool p;
     p.cap = pool_entries(ctx->n_layout);
@@ -955,6 +959,31 @@ bc_status sticky_to_status(int32_t st) {
     if (st & ST_SIGMA_OVF) return BC_ERR_SIGMA_OVERFLOW;
     if (st & ST_DIST_OVF) return BC_ERR_DIST_OVERFLOW;
     if (st & ST_ESTAR_CAP) return BC_ERR_ESTAR_CAPACITY;
+    return BC_OK;
+}
+
+// Bitwise or of the sticky status words at the given device addresses:
+// gathered by k_gather_status into the stream's staging area and copied into
+// pinned host memory, one wait per STATUS_BATCH words.  clock: on the clock
+// stream (polling results beside the work), else on the library stream
+// (behind the work).
+bc_status read_status(bc_ctx *ctx, const std::vector<const int32_t *> &words, bool clock, int32_t *acc) {
+    hipStream_t st = clock ? ctx->clock_stream : ctx->stream;
+    int32_t *dev = status_dev(ctx, clock);
+    *acc = 0;
+    for (size_t b = 0; b < words.size(); b += STATUS_BATCH) {
+        const size_t e = std::min(words.size(), b + (size_t)STATUS_BATCH);
+        for (size_t c = b; c < e; c += STATUS_GATHER) {
+            StatusPtrs a{};
+            const int cnt = (int)std::min<size_t>(STATUS_GATHER, e - c);
+            for (int k = 0; k < cnt; ++k) a.p[k] = words[c + k];
+            hipLaunchKernelGGL(k_gather_status, dim3(1), dim3(STATUS_GATHER), 0, st, a, cnt, dev + (c - b));
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(ctx->h_status, dev, 4 * (e - b), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t k = 0; k < e - b; ++k) *acc |= ctx->h_status[k];
+    }
     return BC_OK;
 }
 
@@ -2001,19 +2030,14 @@ bc_status bc_poll(bc_ctx *ctx, uint64_t ticket, bc_result *out) {
     if (!st) st = event_time_ns(ctx, t.last->end, &out->t_finish_ns);
     if (st) return st;
     // the sticky status of the ticket's graphs, read on the clock stream
-    int32_t acc = 0;
-    for (size_t b = 0; b < t.graphs.size(); b += STATUS_BATCH) {
-        const size_t e2 = std::min(t.graphs.size(), b + STATUS_BATCH);
-        int used = 0;
-        for (size_t k = b; k < e2; ++k) {
-            GraphRec *g = get_graph(ctx, t.graphs[k]);
-            if (!g) continue;
-            HIPCHK(hipMemcpyAsync(ctx->h_status + used, &g->P.ctl->status, 4, hipMemcpyDeviceToHost, ctx->clock_stream));
-            ++used;
-        }
-        HIPCHK(hipStreamSynchronize(ctx->clock_stream));
-        for (int k = 0; k < used; ++k) acc |= ctx->h_status[k];
+    std::vector<const int32_t *> words;
+    for (int32_t gid : t.graphs) {
+        GraphRec *g = get_graph(ctx, gid);
+        if (g) words.push_back(&g->P.ctl->status);
     }
+    int32_t acc = 0;
+    bc_status rs = read_status(ctx, words, true, &acc);
+    if (rs) return rs;
     out->status = sticky_to_status(acc);
     out->done = 1;
     release_ticket(ctx, t);
@@ -2033,31 +2057,34 @@ bc_status bc_wait(bc_ctx *ctx, uint64_t ticket) {
         if (!launched) return fail(ctx, BC_ERR_INVALID_ARG, "ticket has queued jobs but no queue holds them");
     }
     if (it->second.last) HIPCHK(hipEventSynchronize(it->second.last->end));
+    // the sticky status of the ticket's graphs, read on the clock stream (the
+    // library stream may hold later steps)
+    std::vector<const int32_t *> words;
+    for (int32_t gid : it->second.graphs) {
+        GraphRec *g = get_graph(ctx, gid);
+        if (g) words.push_back(&g->P.ctl->status);
+    }
+    int32_t acc = 0;
+    bc_status rs = read_status(ctx, words, true, &acc);
     release_ticket(ctx, it->second);
     ctx->tickets.erase(it);
-    return BC_OK;
+    if (rs) return rs;
+    return sticky_to_status(acc);
 }
 
 bc_status bc_sync(bc_ctx *ctx) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     bc_status fs = flush_queues(ctx);
     if (fs) return fs;
-    // every live graph's status word, copied behind the work into pinned
-    // memory, then one wait
-    for (size_t b = 0; b < ctx->graphs.size(); b += STATUS_BATCH) {
-        const size_t e = std::min(ctx->graphs.size(), b + STATUS_BATCH);
-        int used = 0;
-        for (size_t k = b; k < e; ++k) {
-            GraphRec *g = ctx->graphs[k];
-            if (!g || !g->live) continue;
-            HIPCHK(hipMemcpyAsync(ctx->h_status + used, &g->P.ctl->status, 4, hipMemcpyDeviceToHost, ctx->stream));
-            ++used;
-        }
-        HIPCHK(hipStreamSynchronize(ctx->stream));
-        for (int k = 0; k < used; ++k)
-            if (ctx->h_status[k]) return sticky_to_status(ctx->h_status[k]);
-    }
-    return BC_OK;
+    // every live graph's status word, gathered behind the work and copied
+    // into pinned memory, then one wait
+    std::vector<const int32_t *> words;
+    for (GraphRec *g : ctx->graphs)
+        if (g && g->live) words.push_back(&g->P.ctl->status);
+    int32_t acc = 0;
+    bc_status rs = read_status(ctx, words, false, &acc);
+    if (rs) return rs;
+    return sticky_to_status(acc);
 }
 
 bc_status bc_scores(bc_ctx *ctx, bc_graph_id gid, double *out) {

@@ -3161,6 +3161,19 @@ __global__ void __launch_bounds__(256) k_zero_fill(char *__restrict__ p, size_t 
         q[i] = 0;
 }
 
+// Sticky status words of up to STATUS_GATHER graphs gathered into one device
+// array by one launch, so that reading back many graphs' errors costs one
+// launch and one copy instead of a copy per graph.
+constexpr int STATUS_GATHER = 64;
+struct StatusPtrs {
+    const int32_t *p[STATUS_GATHER];
+};
+__global__ void __launch_bounds__(STATUS_GATHER) k_gather_status(const StatusPtrs a, int32_t count,
+                                                                 int32_t *__restrict__ out) {
+    const int i = threadIdx.x;
+    if (i < count) out[i] = *(const volatile int32_t *)a.p[i];
+}
+
 // Arcs of DAG(s): the predicate of Eq.1 over E*.
 __global__ void k_dag_arcs(const UpdateJob *__restrict__ jobs, int32_t s, int32_t *out_a, int32_t *out_b, int64_t cap,
                            unsigned long long *cnt) {

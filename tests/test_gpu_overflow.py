@@ -235,3 +235,48 @@ def test_heavy_arcs_around_a_light_hub(directed):
     gr.recompute()
     check_full(gr, cur, "recompute")
     ctx.close()
+
+
+def test_sticky_status_of_many_graphs_read_back_together():
+    """bc_sync and bc_poll gather the sticky status words of up to 64 graphs
+    per launch: an error on the 67th of 70 resident graphs is reported by
+    bc_sync and by the result of a ticket that holds it, and a ticket without
+    it is clean."""
+    bcinc = _bc()
+    base = arcs_graph(4, [(0, 1, W_MAX), (2, 3, 10)])
+    ctx = make_ctx(4, slots=4)
+    grs = [ctx.load_graph(base) for _ in range(70)]
+    ctx.sync()
+    t1 = ctx.submit([(grs[i], W.Update("edge", u=2, v=3, w=7)) for i in range(70) if i != 66])
+    ctx.wait(t1)
+    assert ctx.poll(t1)["status"] == "BC_OK"
+    ctx.sync()
+    say("[ovf-many] graph 66 of 70: bridge 1->2 puts d(0,2) past 31 bits")
+    grs[66].update(W.Update("edge", u=1, v=2, w=5))
+    with pytest.raises(bcinc.BcError) as e:
+        ctx.sync()
+    assert e.value.name == "BC_ERR_DIST_OVERFLOW"
+    t2 = ctx.submit([(grs[i], W.Update("edge", u=0, v=3, w=9)) for i in (0, 63, 64, 65, 67, 69)])
+    ctx.wait(t2)  # its graphs are clean: no error
+    t3 = ctx.submit([(grs[i], W.Update("edge", u=0, v=2, w=3)) for i in (1, 66, 68)])
+    with pytest.raises(bcinc.BcError) as e:
+        ctx.wait(t3)
+    assert e.value.name == "BC_ERR_DIST_OVERFLOW"
+    # an arc among vertices 2 and 3 only (a path through vertex 1, reached by
+    # the 2^31 - 2 arc, would overflow)
+    t4 = ctx.submit([(grs[i], W.Update("edge", u=3, v=2, w=4)) for i in (2, 66)])
+    t5 = ctx.submit([(grs[i], W.Update("edge", u=3, v=2, w=4)) for i in (3, 62)])
+    res = {}
+    while len(res) < 2:
+        for t in (t4, t5):
+            if t not in res:
+                r = ctx.poll(t)
+                if r is not None:
+                    res[t] = r["status"]
+    assert res == {t4: "BC_ERR_DIST_OVERFLOW", t5: "BC_OK"}
+    # the clean graphs reached the oracle's state
+    cur = W.apply_update(W.apply_update(base, W.Update("edge", u=2, v=3, w=7)), W.Update("edge", u=0, v=3, w=9))
+    check_full(grs[65], cur, "graph 65")
+    check_full(grs[62], W.apply_update(W.apply_update(base, W.Update("edge", u=2, v=3, w=7)),
+                                       W.Update("edge", u=3, v=2, w=4)), "graph 62")
+    ctx.close()

@@ -55,10 +55,16 @@ KERNEL_SOURCES = ("paper_1311_2147_amd/csrc/bc_kernels.hip", "paper_1311_2147_am
 
 
 def kernel_sources_sha256():
+    """SHA-256 of the kernel sources' code: comments and whitespace are
+    dropped first, so that only a change of the code itself invalidates the
+    committed counter figures."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -654,8 +654,9 @@ __device__ __forceinline__ SSlot sslot_at(char *base, int32_t n) {
     return s;
 }
 
-// A workgroup's slot.  Slots of the DAG kernel have no B list and no arc
-// record (null pointers, kcap 0).
+// A workgroup's slot.  Slots of the DAG kernel have no B list and no new
+// row (null pointers) and an arc record of n arcs; wide-kernel slots have
+// all of them, with a record of KARC_PER_VERTEX * n arcs.
 struct USlot {
     int32_t *outdeg, *sub, *q1, *q2, *bl_t, *bl_d;
     double *acc;

@@ -206,6 +206,7 @@ struct bc_ctx {
     int wide_slots = 0;  // 0: one workgroup per CU when staging, else two
     int table = 256;     // LDS sub-DAG table slots of the DAG kernel
     size_t wide_lds_limit = 0;  // dynamic LDS the wide kernel may use
+    size_t sssp_lds_limit = 0;  // and the static search
     int rows_grid = 1024;       // workgroups of the row kernel (all resident)
     int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
     bool full_search = false;  // BC_FLAG_FULL_SEARCH: the static pass relaxes every arc
@@ -1168,6 +1169,9 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
     HIPCHK(hipMemsetAsync(sp.src_base, 0, slot_region, ctx->stream));
     const int g_wave = (int)std::min<int64_t>(((int64_t)n * 64 + 255) / 256, 4096);
     hipStream_t s = ctx->stream;
+    // the search stages the row in LDS when it fits beside its expansion
+    // arrays (for n up to about 34 800), else works on the row in place
+    const int32_t sssp_cap = source_lds_bytes(L.lds_cap, 1024, 0) <= ctx->sssp_lds_limit ? L.lds_cap : 0;
     ArcCsr search;  // the arcs the distance search relaxes
     bool have_dist = false;
     int32_t rounds = 0;
@@ -1182,8 +1186,9 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
             ++rounds;
             if ((st = upload_csr(ctx, n, search, g->P.arcin_ptr, g->P.arcin_src, g->P.arcin_w))) return st;
             hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
-            hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, L.src_base,
-                               L.slot_bytes, L.lds_cap, L.n_layout, g->P.arcin_ptr, g->P.arcin_src, g->P.arcin_w);
+            hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), source_lds_bytes(sssp_cap, 1024, 0), s, dj,
+                               L.src_base, L.slot_bytes, sssp_cap, L.n_layout, g->P.arcin_ptr, g->P.arcin_src,
+                               g->P.arcin_w);
             HIPCHK(hipMemsetAsync(cnt, 0, 8, s));
             hipLaunchKernelGGL(k_search_check, dim3(std::max(1, std::min(g_wave, 4096))), dim3(256), 0, s, dj,
                                g->P.yc_src, g->P.yc_dst, g->P.yc_w, g->es_cap, cnt);
@@ -1229,8 +1234,8 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
     g->P.arc_m = search.size();
     if (!have_dist) {
         hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(1), 0, s, g->P.ctl);
-        hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), (size_t)L.lds_cap * 4, s, dj, L.src_base, L.slot_bytes,
-                           L.lds_cap, L.n_layout, g->P.arc_ptr, g->P.arc_dst, g->P.arc_w);
+        hipLaunchKernelGGL(k_sssp, dim3(slots), dim3(1024), source_lds_bytes(sssp_cap, 1024, 0), s, dj, L.src_base,
+                           L.slot_bytes, sssp_cap, L.n_layout, g->P.arc_ptr, g->P.arc_dst, g->P.arc_w);
     }
     hipLaunchKernelGGL(k_es_count<ES_BUILD>, dim3(g_wave), dim3(256), 0, s, dj, nj);
     hipLaunchKernelGGL(k_es_scan<ES_BUILD>, dim3(1), dim3(1024), 0, s, dj, nj);
@@ -1290,7 +1295,7 @@ bc_status set_lds_limits(bc_ctx *ctx) {
     if ((st = set_lds_limit(ctx, (const void *)k_source<256>))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_source<128>))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_source_wide, &ctx->wide_lds_limit))) return st;
-    if ((st = set_lds_limit(ctx, (const void *)k_sssp))) return st;
+    if ((st = set_lds_limit(ctx, (const void *)k_sssp, &ctx->sssp_lds_limit))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_static))) return st;
     if ((st = set_lds_limit(ctx, (const void *)k_delta_row_byval))) return st;
     return set_lds_limit(ctx, (const void *)k_delta_row);

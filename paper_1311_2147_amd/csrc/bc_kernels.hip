@@ -2941,11 +2941,16 @@ __global__ void k_begin(const UpdateJob *__restrict__ jobs, const int32_t *__res
 // relaxes the arcs of the set given by tail (sptr, sdst, sw): every arc of
 // the graph, or a set known or checked to contain E* (Section 6: any arc set
 // containing E* gives the same distances).
+// Arcs per lane in flight in the static search's frontier expansion.
+constexpr int SU = 4;
+
 __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ jobs, char *__restrict__ scratch,
                                                size_t slot_bytes, int32_t lds_cap, int32_t n_layout,
                                                const int32_t *__restrict__ sptr, const int32_t *__restrict__ sdst,
                                                const int32_t *__restrict__ sw) {
-    extern __shared__ int32_t lds_row[];
+    extern __shared__ __align__(16) char dyn_lds[];
+    int32_t *const lds_row = (int32_t *)dyn_lds;
+    const ExpandShared es = expand_at(dyn_lds, lds_cap);
     __shared__ BlockShared sh;
     const UpdateJob &J = jobs[0];
     const int32_t n = J.g.n;
@@ -2981,24 +2986,52 @@ __global__ void __launch_bounds__(1024) k_sssp(const UpdateJob *__restrict__ job
         for (;;) {
             const int32_t qlen = sh.tail;
             if (qlen == 0) break;
-            for (int32_t idx = tid; idx < qlen; idx += bs) {
-                const int32_t a = cur[idx];
-                const int32_t da = __atomic_load_n(&row[a], __ATOMIC_RELAXED);
-                const int32_t e1 = sptr[a + 1];
-                for (int32_t e = sptr[a]; e < e1; ++e) {
-                    const int32_t b = sdst[e];
-                    const int64_t nd = (int64_t)da + sw[e];
-                    if (nd >= INF32) { long_cand = true; continue; }
-                    if ((int32_t)nd < __atomic_load_n(&row[b], __ATOMIC_RELAXED)) {
-                        const int32_t old = atomicMin(&row[b], (int32_t)nd);
-                        if ((int32_t)nd < old && atomicExch(&flag[b], 1) == 0) {
-                            const int32_t pos = atomicAdd(&sh.next, 1);
-                            nxt[pos] = b;
+            // the frontier's out-arcs, arc-parallel: a block scan of the
+            // frontier vertices' out-degrees, then SU consecutive arcs per
+            // lane, so that a hub's arcs (thousands on a power-law graph)
+            // spread over the workgroup instead of one lane walking them
+            for (int32_t c = 0; c < qlen; c += bs) {
+                const int32_t idx = c + tid;
+                int32_t b0 = 0, deg = 0, da = INF32;
+                if (idx < qlen) {
+                    const int32_t a = cur[idx];
+                    b0 = sptr[a];
+                    deg = sptr[a + 1] - b0;
+                    da = __atomic_load_n(&row[a], __ATOMIC_RELAXED);
+                }
+                int32_t total;
+                const int32_t off = block_excl_scan(deg, sh.scan, total);
+                es.off[tid] = off;
+                es.beg[tid] = b0;
+                es.dx[tid] = da;
+                __syncthreads();
+                const int32_t nv = min(bs, qlen - c);
+                for (int32_t jb = tid * SU; jb < total; jb += bs * SU) {
+                    int32_t iv[SU], ev[SU], bv[SU], wv[SU];
+                    bool ok[SU];
+                    chunk_arcs(es, nv, total, jb, iv, ev, ok);
+#pragma unroll
+                    for (int k = 0; k < SU; ++k) {
+                        bv[k] = ok[k] ? sdst[ev[k]] : 0;
+                        wv[k] = ok[k] ? sw[ev[k]] : 0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < SU; ++k) {
+                        if (!ok[k]) continue;
+                        const int64_t nd = (int64_t)es.dx[iv[k]] + wv[k];
+                        if (nd >= INF32) {
+                            long_cand = true;
+                            continue;
+                        }
+                        const int32_t b = bv[k];
+                        if ((int32_t)nd < __atomic_load_n(&row[b], __ATOMIC_RELAXED)) {
+                            const int32_t old = atomicMin(&row[b], (int32_t)nd);
+                            if ((int32_t)nd < old && atomicExch(&flag[b], 1) == 0) nxt[atomicAdd(&sh.next, 1)] = b;
                         }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
             const int32_t nl = sh.next;
             for (int32_t idx = tid; idx < nl; idx += bs) flag[nxt[idx]] = 0;
             __syncthreads();

@@ -721,6 +721,9 @@ __device__ __forceinline__ USlot wslot_at(char *base, int32_t n) {
 //   3. levels in reverse: each vertex pulls Eq.4 over its successors,
 //      delta(a) = sigma_sa * sum_b (1 + delta(b)) / sigma_sb, and BC(a) gets
 //      delta(a) for a != s (Alg 1).
+// Out-degree above which the static pass gives a vertex a whole wave.
+constexpr int32_t HEAVY_DEG = 32;
+
 __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t *Drow, uint64_t *Srow,
                                 int32_t *pred, const int32_t *ptr, const int32_t *src, const int32_t *dst,
                                 const int32_t *wt, const int32_t m, const SSlot &sl, double *bc_delta, GraphCtl *ctl,
@@ -754,27 +757,50 @@ __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t 
     }
     __syncthreads();
     bool ovf = false;
+    // A vertex with more than HEAVY_DEG E* out-arcs (a hub of a power-law
+    // graph has thousands) is handled by a whole wave, its lanes striding over
+    // the arcs; the others by one lane each.  The heavy vertices of a level
+    // are listed in queue2 (unused by this pass) as the lanes meet them.
+    const int lane = lane_id(), wid = tid >> 6, nw = bs >> 6;
+    int32_t *const heavy = sl.queue2;
+    // one DAG-arc test of the forward pass: sigma_sb += sigma_sa, and b joins
+    // the next level once its last DAG predecessor has pushed
+    auto push = [&](const int32_t da, const uint64_t sa, const int32_t e) {
+        const int32_t b = dst[e];
+        const int32_t db = Drow[b];
+        if (db != INF32 && (int64_t)da + wt[e] == (int64_t)db) {
+            const uint64_t old = atomicAdd((unsigned long long *)&Srow[b], (unsigned long long)sa);
+            if (old + sa < old) ovf = true;
+            if (atomicSub(&sl.indeg[b], 1) == 1) sl.order[atomicAdd(&sh.next, 1)] = b;
+        }
+    };
     for (;;) {
         const int32_t lo = sh.head, hi = sh.tail;
         if (lo >= hi) break;
-        if (tid == 0) sl.lvl[sh.nlev] = lo;
+        if (tid == 0) {
+            sl.lvl[sh.nlev] = lo;
+            sh.kpos = 0;
+        }
+        __syncthreads();
         for (int32_t idx = lo + tid; idx < hi; idx += bs) {
             const int32_t a = sl.order[idx];
+            const int32_t e0 = ptr[a], e1 = ptr[a + 1];
+            if (e1 - e0 > HEAVY_DEG) {
+                heavy[atomicAdd(&sh.kpos, 1)] = a;
+                continue;
+            }
+            const int32_t da = Drow[a];
+            const uint64_t sa = Srow[a];
+            for (int32_t e = e0; e < e1; ++e) push(da, sa, e);
+        }
+        __syncthreads();
+        const int32_t nh = sh.kpos;
+        for (int32_t h = wid; h < nh; h += nw) {
+            const int32_t a = heavy[h];
             const int32_t da = Drow[a];
             const uint64_t sa = Srow[a];
             const int32_t e1 = ptr[a + 1];
-            for (int32_t e = ptr[a]; e < e1; ++e) {
-                const int32_t b = dst[e];
-                const int32_t db = Drow[b];
-                if (db != INF32 && (int64_t)da + wt[e] == (int64_t)db) {
-                    const uint64_t old = atomicAdd((unsigned long long *)&Srow[b], (unsigned long long)sa);
-                    if (old + sa < old) ovf = true;
-                    if (atomicSub(&sl.indeg[b], 1) == 1) {
-                        const int32_t pos = atomicAdd(&sh.next, 1);
-                        sl.order[pos] = b;
-                    }
-                }
-            }
+            for (int32_t e = ptr[a] + lane; e < e1; e += 64) push(da, sa, e);
         }
         __syncthreads();
         if (tid == 0) {
@@ -791,22 +817,48 @@ __device__ void static_dag_pass(const int32_t s, const int32_t n, const int32_t 
         atomicMax(&ctl->max_levels, nlev);
     }
     __syncthreads();
+    // delta(a) from its DAG successors' coefficients (all of a later level)
+    auto finish = [&](const int32_t a, const double acc) {
+        const double sa = (double)Srow[a];
+        const double dl = sa * acc;
+        sl.coef[a] = (1.0 + dl) / sa;
+        if (a != s && dl != 0.0) atomicAdd(&bc_delta[a], dl);
+    };
     for (int32_t L = nlev - 1; L >= 0; --L) {
         const int32_t lo = sl.lvl[L], hi = sl.lvl[L + 1];
+        if (tid == 0) sh.kpos = 0;
+        __syncthreads();
         for (int32_t idx = lo + tid; idx < hi; idx += bs) {
             const int32_t a = sl.order[idx];
+            const int32_t e0 = ptr[a], e1 = ptr[a + 1];
+            if (e1 - e0 > HEAVY_DEG) {
+                heavy[atomicAdd(&sh.kpos, 1)] = a;
+                continue;
+            }
             const int32_t da = Drow[a];
             double acc = 0.0;
-            const int32_t e1 = ptr[a + 1];
-            for (int32_t e = ptr[a]; e < e1; ++e) {
+            for (int32_t e = e0; e < e1; ++e) {
                 const int32_t b = dst[e];
                 const int32_t db = Drow[b];
                 if (db != INF32 && (int64_t)da + wt[e] == (int64_t)db) acc += sl.coef[b];
             }
-            const double sa = (double)Srow[a];
-            const double dl = sa * acc;
-            sl.coef[a] = (1.0 + dl) / sa;
-            if (a != s && dl != 0.0) atomicAdd(&bc_delta[a], dl);
+            finish(a, acc);
+        }
+        __syncthreads();
+        const int32_t nh = sh.kpos;
+        for (int32_t h = wid; h < nh; h += nw) {
+            const int32_t a = heavy[h];
+            const int32_t da = Drow[a];
+            double acc = 0.0;
+            const int32_t e1 = ptr[a + 1];
+            for (int32_t e = ptr[a] + lane; e < e1; e += 64) {
+                const int32_t b = dst[e];
+                const int32_t db = Drow[b];
+                if (db != INF32 && (int64_t)da + wt[e] == (int64_t)db) acc += sl.coef[b];
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (lane == 0) finish(a, acc);
         }
         __syncthreads();
     }

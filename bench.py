@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--graphs", type=int, default=6)
-    ap.add_argument("--legs", default="batched,plain,recompute,loader,single,c4,served,budget,cpuinc,cpu,copy")
+    ap.add_argument("--legs", default="batched,plain,recompute,loader,single,served,budget,c4,cpuinc,cpu,copy")
     ap.add_argument("--served-updates", type=int, default=10000, help="updates of the 0.8x served run")
     ap.add_argument("--cpu-updates", type=int, default=12, help="updates of the CPU incremental comparator's sample")
     ap.add_argument("--cpu-one-core-sources", type=int, default=512, help="sources of the one-core oracle sample")
@@ -419,64 +419,6 @@ def main():
     del grs
     torch.cuda.empty_cache()
 
-    # ---------------------------------------------------------------- many graphs
-    # The 64-graph batched workload (n log-uniform in [256, 4096], half
-    # directed with out-degree 8, half complete with weights up to n^2, 32
-    # updates each): every step's 64 updates in one batched launch sequence
-    # under the autotuner's choice per size bucket (tuned on a separately
-    # drawn sample of eight graphs, on clones), then the same updates one at a
-    # time on clones of the graphs (default schedule, bc_sync after each);
-    # both must end in the same states.
-    if "c4" in legs:
-        t = time.perf_counter()
-        work = W.config4()
-        c4g = [ctx.load_graph(g) for g, _ in work]
-        ctx.sync()
-        c4_load_s = time.perf_counter() - t
-        sample = []
-        for i in range(0, len(work), 8):
-            g = work[i][0]
-            if g.directed:
-                ups4 = W.mixed_stream(g, 4, 100, W.derive_seed(4, 9000 + i), 0.35, 0.35, 16)
-            else:
-                ups4 = W.mixed_stream(g, 4, g.n * g.n, W.derive_seed(4, 9000 + i), 0.0, 0.70, 16)
-            sample += [(c4g[i], up) for up in ups4]
-        t = time.perf_counter()
-        ctx.autotune(sample)
-        c4_tune_s = time.perf_counter() - t
-        c4_twins = [gr.clone() for gr in c4g]
-        ctx.sync()
-        n_steps = len(work[0][1])
-        reqs4 = [(c4g[i], ups4[k]) for k in range(n_steps) for i, (_, ups4) in enumerate(work)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.wait(ctx.submit(reqs4))
-        torch.cuda.synchronize()
-        c4_b = len(reqs4) / (time.perf_counter() - t0)
-        ctx.set_schedule(**default_sched)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(n_steps):
-            for i, (_, ups4) in enumerate(work):
-                c4_twins[i].update(ups4[k])
-                ctx.sync()
-        c4_p = len(reqs4) / (time.perf_counter() - t0)
-        ctx.set_schedule(**tuned)
-        c4_same = all(c4_twins[i].state_hash() == c4g[i].state_hash() for i in range(len(work)))
-        comparators["many_graphs"] = {
-            "workload": "64 graphs, n log-uniform in [256, 4096], half directed out-degree 8 (weights 1..100), "
-                        "half complete undirected (weights 1..n^2), 32 updates each, one update per graph per step",
-            "updates": len(reqs4), "load_s": c4_load_s, "autotune_s": c4_tune_s,
-            "batched_updates_per_s": c4_b, "plain_updates_per_s": c4_p, "batched_over_plain": c4_b / c4_p,
-            "same_state": c4_same}
-        log(f"64-graph batched workload ({len(reqs4)} updates, loaded in {c4_load_s:.1f}s, tuned in {c4_tune_s:.1f}s): "
-            f"batched {c4_b:.0f} updates/s, plain {c4_p:.0f} updates/s, batched/plain {c4_b / c4_p:.2f}, "
-            f"same state {c4_same}")
-        for gr in c4_twins + c4g:
-            gr.free()
-        del c4_twins, c4g
-        torch.cuda.empty_cache()
-
     # ---------------------------------------------------------------- served
     # The served workload at full shape: 8 resident Chung-Lu graphs and one
     # seeded stream over them, cut into consecutive parts (each part is valid
@@ -610,6 +552,64 @@ def main():
         else:
             for gr in sg:
                 gr.free()
+        torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- many graphs
+    # The 64-graph batched workload (n log-uniform in [256, 4096], half
+    # directed with out-degree 8, half complete with weights up to n^2, 32
+    # updates each): every step's 64 updates in one batched launch sequence
+    # under the autotuner's choice per size bucket (tuned on a separately
+    # drawn sample of eight graphs, on clones), then the same updates one at a
+    # time on clones of the graphs (default schedule, bc_sync after each);
+    # both must end in the same states.
+    if "c4" in legs:
+        t = time.perf_counter()
+        work = W.config4()
+        c4g = [ctx.load_graph(g) for g, _ in work]
+        ctx.sync()
+        c4_load_s = time.perf_counter() - t
+        sample = []
+        for i in range(0, len(work), 8):
+            g = work[i][0]
+            if g.directed:
+                ups4 = W.mixed_stream(g, 4, 100, W.derive_seed(4, 9000 + i), 0.35, 0.35, 16)
+            else:
+                ups4 = W.mixed_stream(g, 4, g.n * g.n, W.derive_seed(4, 9000 + i), 0.0, 0.70, 16)
+            sample += [(c4g[i], up) for up in ups4]
+        t = time.perf_counter()
+        ctx.autotune(sample)
+        c4_tune_s = time.perf_counter() - t
+        c4_twins = [gr.clone() for gr in c4g]
+        ctx.sync()
+        n_steps = len(work[0][1])
+        reqs4 = [(c4g[i], ups4[k]) for k in range(n_steps) for i, (_, ups4) in enumerate(work)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.wait(ctx.submit(reqs4))
+        torch.cuda.synchronize()
+        c4_b = len(reqs4) / (time.perf_counter() - t0)
+        ctx.set_schedule(**default_sched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_steps):
+            for i, (_, ups4) in enumerate(work):
+                c4_twins[i].update(ups4[k])
+                ctx.sync()
+        c4_p = len(reqs4) / (time.perf_counter() - t0)
+        ctx.set_schedule(**tuned)
+        c4_same = all(c4_twins[i].state_hash() == c4g[i].state_hash() for i in range(len(work)))
+        comparators["many_graphs"] = {
+            "workload": "64 graphs, n log-uniform in [256, 4096], half directed out-degree 8 (weights 1..100), "
+                        "half complete undirected (weights 1..n^2), 32 updates each, one update per graph per step",
+            "updates": len(reqs4), "load_s": c4_load_s, "autotune_s": c4_tune_s,
+            "batched_updates_per_s": c4_b, "plain_updates_per_s": c4_p, "batched_over_plain": c4_b / c4_p,
+            "same_state": c4_same}
+        log(f"64-graph batched workload ({len(reqs4)} updates, loaded in {c4_load_s:.1f}s, tuned in {c4_tune_s:.1f}s): "
+            f"batched {c4_b:.0f} updates/s, plain {c4_p:.0f} updates/s, batched/plain {c4_b / c4_p:.2f}, "
+            f"same state {c4_same}")
+        for gr in c4_twins + c4g:
+            gr.free()
+        del c4_twins, c4g
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------------ copy

@@ -290,3 +290,41 @@ def test_lemma1_row_v_column_u_and_undirected_symmetry():
         D, S = gh.rows()
         assert np.array_equal(D, D.T) and np.array_equal(S, S.T), "undirected state lost its symmetry"
     ctx.close()
+
+
+def test_hub_fan_graph_static_pass_and_updates():
+    """A unit-weight fan: vertex 0 has 1500 out-arcs to a middle layer, every
+    middle vertex has arcs to the same 40 bottom vertices, and each bottom
+    vertex one arc on.  The static search's frontier holds 1500 vertices in
+    one round (more than one chunk of a workgroup), vertex 0 and every middle
+    vertex have more out-arcs than a lane takes alone (a wave each in the sigma
+    and delta passes), and the bottom vertices gather 1500 tied paths each.
+    Load and a few updates against the oracle, with the DAGs of sources 0, a
+    middle vertex and a bottom vertex."""
+    mid, bot = 1500, 40
+    n = 1 + mid + 2 * bot
+    src, dst = [], []
+    for m in range(1, mid + 1):
+        src.append(0)
+        dst.append(m)
+        for b in range(bot):
+            src.append(m)
+            dst.append(1 + mid + b)
+    for b in range(bot):
+        src.append(1 + mid + b)
+        dst.append(1 + mid + bot + b)
+    g = W.Graph(n, True, np.asarray(src, np.int32), np.asarray(dst, np.int32), np.ones(len(src), np.int64))
+    ctx = make_ctx(n, slots=16)
+    gr = ctx.load_graph(g)
+    check_full(gr, g, "fan load", dags=(0, 7, 1 + mid + 3), estar=True)
+    say(f"[fan] n={n}, {len(src)} arcs: load matches the oracle")
+    ups = [W.Update("edge", u=0, v=1 + mid + 5, w=1),        # a shortcut past the fan to one bottom vertex
+           W.Update("edge", u=2, v=1 + mid + bot + 7, w=1),  # a middle vertex straight to a last-layer vertex
+           W.Update("vertex", v=1 + mid, edges=[(0, 1 + mid, 2), (1 + mid, 1 + mid + bot + 1, 1)])]
+    cur = g
+    for k, up in enumerate(ups):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        check_full(gr, cur, f"fan update {k}", dags=(0, 7), estar=True)
+    say("[fan] three updates match the oracle")
+    ctx.close()

@@ -61,7 +61,8 @@ enum {
     BC_ERR_DIST_OVERFLOW = -10,  /* sticky: a finite distance reached 2^31-1 */
     BC_ERR_HIP = -11,            /* HIP runtime error; text in bc_last_error */
     BC_ERR_NO_DEVICE = -12,      /* no usable gfx950 device */
-    BC_ERR_ESTAR_CAPACITY = -13  /* sticky: E* outgrew its capacity */
+    BC_ERR_ESTAR_CAPACITY = -13, /* sticky: E* outgrew its capacity */
+    BC_ERR_CHECK_FAILED = -14    /* sticky: a state check found the state wrong (BC_FLAG_CHECK, bc_check) */
 };
 
 typedef struct bc_ctx bc_ctx;
@@ -71,6 +72,8 @@ typedef int32_t bc_graph_id;
 #define BC_FLAG_TIMING 1      /* time every update step and its per-source kernels with HIP events */
 #define BC_FLAG_FULL_SEARCH 2 /* the static pass (load, bc_recompute) relaxes every arc, never a
                                  checked subset (see bc_load_graph) */
+#define BC_FLAG_CHECK 4       /* debugging: check the state after every load, recompute and update
+                                 step (see bc_check); slow, and every such call synchronises */
 
 typedef struct {
     int32_t device;         /* HIP device ordinal */
@@ -292,6 +295,48 @@ bc_status bc_get_preds(bc_ctx *ctx, bc_graph_id g, int32_t s, int32_t *out);
 bc_status bc_get_affected(bc_ctx *ctx, bc_graph_id g, int32_t *out, int64_t cap, int64_t *cnt);
 bc_status bc_state_hash(bc_ctx *ctx, bc_graph_id g, uint64_t out[2]);
 
+/* State check, a debugging aid: tests the graph's state against the
+ * definitions on the device, over its current arcs (a thread per pair).  For
+ * every source s and target t, with the arcs (a,t) of weight w whose tail
+ * a is reachable from s:
+ *   - d(s,s) = 0, sigma_ss = 1, no stored predecessor at s (BC_CHECK_SOURCE);
+ *   - no arc gives d(s,a) + w < d(s,t), and none leads from a reachable a to
+ *     an unreachable t (BC_CHECK_RELAX);
+ *   - a reachable t has an arc with d(s,a) + w = d(s,t), an arc of DAG(s)
+ *     by Eq.1 (BC_CHECK_NO_PATH); sigma_st is the sum of sigma_sa over those
+ *     arcs (BC_CHECK_SIGMA); its stored predecessor (bc_get_preds) is the
+ *     tail of the only one, or -2 for several (BC_CHECK_PRED);
+ *   - an unreachable t has sigma_st = 0 and no stored predecessor
+ *     (BC_CHECK_UNREACHED);
+ *   - an undirected graph has equal d and sigma at (s,t) and (t,s)
+ *     (BC_CHECK_SYMMETRY);
+ * and E* holds exactly the arcs (a,b) with w(a,b) = d(a,b), once each, with
+ * their current weights (BC_CHECK_ESTAR).  With positive weights the first
+ * three fix d and sigma uniquely, so a state that passes has the exact
+ * distances, path counts, stored predecessors and E* of its arcs.  BC itself
+ * is not checked.
+ * bc_check runs it on every source and synchronises.  A context created with
+ * BC_FLAG_CHECK runs it after every load and recompute, and after every
+ * update step on the step's affected sources (sources outside A keep their
+ * rows by Lemma 2 and Lemma 4) and all of E*; a failing step makes its call
+ * return BC_ERR_CHECK_FAILED.
+ * A failure is sticky (BC_ERR_CHECK_FAILED, ranked after the overflow and E*
+ * capacity errors, until bc_recompute) and its first instance is in
+ * bc_last_error and bc_update_stats.  A graph that already carries a sticky
+ * error is not checked and returns that error.
+ * Errors: BC_ERR_INVALID_ARG (no such graph), the sticky errors. */
+bc_status bc_check(bc_ctx *ctx, bc_graph_id g);
+
+/* Kinds of a failed check (bc_update_stats.check_kind). */
+#define BC_CHECK_SOURCE 1
+#define BC_CHECK_RELAX 2
+#define BC_CHECK_NO_PATH 3
+#define BC_CHECK_SIGMA 4
+#define BC_CHECK_PRED 5
+#define BC_CHECK_UNREACHED 6
+#define BC_CHECK_SYMMETRY 7
+#define BC_CHECK_ESTAR 8
+
 typedef struct {
     int64_t affected_sources; /* |A| of the last update (sum over its phases) */
     int64_t changed_pairs;    /* pairs (s,t) whose d or sigma changed */
@@ -307,6 +352,11 @@ typedef struct {
     int64_t total_scan_bytes; /* the same summed over all updates since load */
     int64_t search_arcs;      /* arcs the distance search of the last static pass relaxed */
     int64_t search_rounds;    /* its searches when the arc set was checked (0: one search) */
+    int64_t check_rows;       /* source rows verified by state checks since load (bc_check) */
+    int64_t check_failures;   /* conditions those checks found false */
+    int64_t check_source;     /* the first of them: source s (tail for BC_CHECK_ESTAR), -1 if none */
+    int64_t check_target;     /* its target t (head for BC_CHECK_ESTAR), -1 if none */
+    int64_t check_kind;       /* its BC_CHECK_* kind, 0 if none */
 } bc_update_stats;
 bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id g, bc_update_stats *out);
 

@@ -33,7 +33,7 @@ STATUS_NAMES = {
     0: "BC_OK", -1: "BC_ERR_INVALID_ARG", -2: "BC_ERR_SELF_LOOP", -3: "BC_ERR_BAD_WEIGHT",
     -4: "BC_ERR_DUPLICATE_EDGE", -5: "BC_ERR_NOT_INCIDENT", -6: "BC_ERR_NOT_INCREMENTAL",
     -7: "BC_ERR_ADMISSION", -8: "BC_ERR_CAPACITY", -9: "BC_ERR_SIGMA_OVERFLOW", -10: "BC_ERR_DIST_OVERFLOW",
-    -11: "BC_ERR_HIP", -12: "BC_ERR_NO_DEVICE", -13: "BC_ERR_ESTAR_CAPACITY",
+    -11: "BC_ERR_HIP", -12: "BC_ERR_NO_DEVICE", -13: "BC_ERR_ESTAR_CAPACITY", -14: "BC_ERR_CHECK_FAILED",
 }
 INF = np.iinfo(np.int64).max
 
@@ -67,7 +67,9 @@ class bc_update_stats(ctypes.Structure):
                 ("total_affected", ctypes.c_int64), ("total_changed", ctypes.c_int64),
                 ("deferred_sources", ctypes.c_int64), ("scan_bytes", ctypes.c_int64),
                 ("total_scan_bytes", ctypes.c_int64), ("search_arcs", ctypes.c_int64),
-                ("search_rounds", ctypes.c_int64)]
+                ("search_rounds", ctypes.c_int64), ("check_rows", ctypes.c_int64),
+                ("check_failures", ctypes.c_int64), ("check_source", ctypes.c_int64),
+                ("check_target", ctypes.c_int64), ("check_kind", ctypes.c_int64)]
 
 
 class bc_result(ctypes.Structure):
@@ -90,6 +92,11 @@ SCHEDULE_FIELDS = tuple(f for f, _ in bc_schedule._fields_)
 
 BC_FLAG_TIMING = 1
 BC_FLAG_FULL_SEARCH = 2
+BC_FLAG_CHECK = 4
+
+# kinds of a failed state check (bc_update_stats.check_kind)
+CHECK_KINDS = {1: "source", 2: "relax", 3: "no_path", 4: "sigma", 5: "pred", 6: "unreached", 7: "symmetry",
+               8: "estar"}
 
 
 _P = ctypes.c_void_p
@@ -122,6 +129,7 @@ _SIGS = {
     "bc_get_preds": (_i32, [_P, _i32, _i32, _P]),
     "bc_get_affected": (_i32, [_P, _i32, _P, _i64, ctypes.POINTER(_i64)]),
     "bc_state_hash": (_i32, [_P, _i32, _P]),
+    "bc_check": (_i32, [_P, _i32]),
     "bc_get_stats": (_i32, [_P, _i32, ctypes.POINTER(bc_update_stats)]),
     "bc_get_timing": (_i32, [_P, ctypes.POINTER(bc_timing)]),
     "bc_reset_timing": (_i32, [_P]),
@@ -174,14 +182,16 @@ class Context:
     """A bcinc context on one GPU (bc_create / bc_destroy)."""
 
     def __init__(self, device: int = 0, n_max: int = 4096, slots: int = 0, block: int = 0, memory_budget: int = 0,
-                 stream=None, timing: bool = False, full_search: bool = False, tune_cache: str | None = None):
+                 stream=None, timing: bool = False, full_search: bool = False, tune_cache: str | None = None,
+                 check: bool = False):
         import torch
 
         self.device = device
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.scratch_bytes = bc_scratch_bytes(n_max, slots)
         self._scratch, addr = _device_buffer(self.scratch_bytes, device)
-        flags = (BC_FLAG_TIMING if timing else 0) | (BC_FLAG_FULL_SEARCH if full_search else 0)
+        flags = ((BC_FLAG_TIMING if timing else 0) | (BC_FLAG_FULL_SEARCH if full_search else 0)
+                 | (BC_FLAG_CHECK if check else 0))
         self._tune_cache = tune_cache.encode() if tune_cache else None
         cfg = bc_config(device, flags, self.stream.cuda_stream, addr, self.scratch_bytes, memory_budget, slots, block,
                         self._tune_cache)
@@ -453,6 +463,11 @@ class Graph:
         self.ctx._check(_lib.bc_get_affected(self.ctx.h, self.gid, _np_ptr(out), k, ctypes.byref(cnt)),
                         "bc_get_affected")
         return np.sort(out[:k])
+
+    def check(self):
+        """bc_check: the whole state against its definitions on the device
+        (raises BcError BC_ERR_CHECK_FAILED, naming the first failure)."""
+        self.ctx._check(_lib.bc_check(self.ctx.h, self.gid), "bc_check")
 
     def state_hash(self) -> tuple[int, int]:
         out = np.zeros(2, dtype=np.uint64)

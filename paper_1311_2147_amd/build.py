@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libbcinc.so")
 SOURCES = [os.path.join(CSRC, "bcinc.hip")]
-DEPENDS = [os.path.join(CSRC, f) for f in ("bc_device.h", "bc_kernels.hip", "bc_host.hip", "bcinc.hip")] + [
+DEPENDS = [os.path.join(CSRC, f) for f in ("bc_device.h", "bc_kernels.hip", "bc_check.hip", "bc_host.hip", "bcinc.hip")] + [
     os.path.join(os.path.dirname(HERE), "include", "bcinc.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -139,7 +139,9 @@ struct GraphPtrs {
                       // phase with d''(v,t)
     int32_t *f_out;
     GraphCtl *ctl;
-    // Full arc set by tail and by head (static recompute and E* build).
+    // Full arc set by tail and by head (static recompute and E* build).  No
+    // update reads them; a state check puts the current arcs by head in
+    // arcin_* before it runs.
     int32_t *arc_ptr, *arc_dst, *arc_w;
     int32_t *arcin_ptr, *arcin_src, *arcin_w;
     int64_t arc_m;

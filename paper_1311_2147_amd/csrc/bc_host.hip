@@ -143,6 +143,10 @@ struct GraphRec {
     uint64_t updates = 0;
     int64_t search_arcs = 0;   // arcs the last static pass's distance search relaxed
     int32_t search_rounds = 0; // searches of its checked search (0: one search over a given set)
+    CheckRec *chk = nullptr;   // the state checks' record (in the arena)
+    // BC_FLAG_CHECK: the arcs as of the last step launched on the device (the
+    // mirror runs ahead by every request validated but not launched yet)
+    Mirror dev;
 };
 
 struct StepGraph {
@@ -210,6 +214,7 @@ struct bc_ctx {
     int rows_grid = 1024;       // workgroups of the row kernel (all resident)
     int32_t n_layout = 1;  // slot layout size: the largest graph ever loaded
     bool full_search = false;  // BC_FLAG_FULL_SEARCH: the static pass relaxes every arc
+    bool check = false;        // BC_FLAG_CHECK: state check after every load, recompute and step
     // schedules chosen by the autotuner per size bucket (ceil(log2 n) of a
     // step's largest graph), used while use_tuned is set; the cache file
     // keeps them across contexts of the same device kind
@@ -361,7 +366,7 @@ struct Carve {
     }
 };
 
-GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *total) {
+GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *total, CheckRec **chk = nullptr) {
     Carve c;
     const size_t nn = (size_t)n * (size_t)n;
     size_t oD = c.take(4 * nn), oS = c.take(8 * nn), oPr = c.take(4 * nn);
@@ -382,9 +387,11 @@ GraphPtrs carve(char *base, int32_t n, int64_t arc_cap, int64_t es_cap, size_t *
     size_t octl = c.take(sizeof(GraphCtl));
     size_t oap = c.take(4 * ((size_t)n + 1)), oad = c.take(4 * (size_t)arc_cap), oaw = c.take(4 * (size_t)arc_cap);
     size_t oip = c.take(4 * ((size_t)n + 1)), ois = c.take(4 * (size_t)arc_cap), oiw = c.take(4 * (size_t)arc_cap);
+    size_t ochk = c.take(sizeof(CheckRec));
     *total = c.off;
     GraphPtrs P{};
     if (!base) return P;
+    if (chk) *chk = (CheckRec *)(base + ochk);
     P.n = n;
     P.es_cap = es_cap;
     P.D = (int32_t *)(base + oD);
@@ -669,6 +676,8 @@ struct ScheduleScope {
     }
 };
 
+bc_status check_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs);
+
 bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_graph, StepEvents *se = nullptr) {
     int32_t n_max = 1;
     for (auto &j : jobs) n_max = std::max(n_max, j.g.n);
@@ -695,7 +704,8 @@ bc_status run_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs, bool use_gra
     if (timed) HIPCHK(hipEventRecord(ctx->tev[r][4], ctx->stream));
     if (timed) ctx->tev_pending[r] = true;
     if (se) HIPCHK(hipEventRecord(se->end, ctx->stream));
-    return ring_release(ctx, r);
+    if ((st = ring_release(ctx, r))) return st;
+    return ctx->check ? check_step(ctx, jobs) : BC_OK;
 }
 
 // Step events from the pool (timing-enabled events; created on first use).
@@ -960,6 +970,7 @@ bc_status sticky_to_status(int32_t st) {
     if (st & ST_SIGMA_OVF) return BC_ERR_SIGMA_OVERFLOW;
     if (st & ST_DIST_OVF) return BC_ERR_DIST_OVERFLOW;
     if (st & ST_ESTAR_CAP) return BC_ERR_ESTAR_CAPACITY;
+    if (st & ST_CHECK) return BC_ERR_CHECK_FAILED;
     return BC_OK;
 }
 
@@ -988,8 +999,6 @@ bc_status read_status(bc_ctx *ctx, const std::vector<const int32_t *> &words, bo
     return BC_OK;
 }
 
-// Static pass on the GPU from the mirror's arcs: distances, E*, counts,
-// dependencies and BC (Alg 7 with the DAG taken from E*, Alg 6 steps 2-8).
 // The maintained E* as an arc list grouped by tail (heads ascending within a
 // tail), read from its by-head copy XC.  Refuses a graph with a sticky error:
 // its E* may be incomplete then.
@@ -1123,6 +1132,77 @@ bool use_checked_search(int32_t n, int64_t m) { return m >= 4 * (int64_t)search_
 // Static pass: all-pairs distances, path counts, E* and BC from scratch
 // (Alg 7 with the DAG taken from E*, Alg 6 steps 2-8).
 //
+const char *check_kind_name(int32_t k) {
+    switch (k) {
+        case CK_SOURCE: return "source entry";
+        case CK_RELAX: return "shorter in-arc";
+        case CK_NO_PATH: return "no tight in-arc";
+        case CK_SIGMA: return "path count";
+        case CK_PRED: return "stored predecessor";
+        case CK_UNREACHED: return "unreachable pair";
+        case CK_SYMMETRY: return "symmetry";
+        case CK_ESTAR: return "E*";
+        default: return "unknown";
+    }
+}
+
+// State check (bc_check, BC_FLAG_CHECK) over the given arcs, which must be
+// the arcs of the state on the device: they go by head into arcin_* (no
+// update reads those), then the check kernels run on every source (all) or
+// on the last update's affected ones, and on E*.  Synchronises.  Returns
+// BC_ERR_CHECK_FAILED, with the first failure in the message, when a check
+// fails; *status gets the graph's sticky bits (a graph that had some before
+// is not checked).
+bc_status run_check(bc_ctx *ctx, GraphRec *g, const Mirror &arcs, bool all, int32_t *status) {
+    const int32_t n = g->n;
+    Mirror m = arcs;
+    m.compact();
+    ArcCsr tail, head;
+    tail.ptr.resize((size_t)n + 1);
+    for (int32_t i = 0; i <= n; ++i) tail.ptr[i] = (int32_t)m.ptr[i];
+    tail.dst = std::move(m.dst);
+    tail.w = std::move(m.w);
+    if (tail.size() > g->arc_cap) return fail(ctx, BC_ERR_CAPACITY, "arc capacity exceeded");
+    by_head(n, tail, head);
+    bc_status st = upload_csr(ctx, n, head, g->P.arcin_ptr, g->P.arcin_src, g->P.arcin_w);
+    if (st) return st;
+    hipLaunchKernelGGL(k_check_rows, dim3(2048), dim3(256), 0, ctx->stream, g->P, g->chk, all ? 1 : 0);
+    hipLaunchKernelGGL(k_check_estar, dim3((int)std::min<int64_t>(((int64_t)n + 255) / 256, 1024)), dim3(256), 0,
+                       ctx->stream, g->P, g->chk);
+    HIPCHK(hipGetLastError());
+    CheckRec rec{};
+    *status = 0;
+    HIPCHK(hipMemcpyAsync(&rec, g->chk, sizeof rec, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(status, &g->P.ctl->status, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    // the host arrays above are read by the copies: finish before they go
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (*status & ST_CHECK) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "state check failed: %s at (%d, %d), %llu condition(s) false", check_kind_name(rec.kind),
+                 rec.s, rec.t, rec.fails);
+        return fail(ctx, BC_ERR_CHECK_FAILED, msg);
+    }
+    return BC_OK;
+}
+
+// Applies a step's arc changes to the check copies of its graphs' arcs, then
+// checks each graph (BC_FLAG_CHECK).
+bc_status check_step(bc_ctx *ctx, const std::vector<UpdateJob> &jobs) {
+    for (const UpdateJob &j : jobs) {
+        GraphRec *g = nullptr;
+        for (GraphRec *r : ctx->graphs)
+            if (r && r->live && r->P.ctl == j.g.ctl) g = r;
+        if (!g) continue;
+        for (int32_t k = 0; k < j.n_u; ++k) g->dev.set(j.u_tail[k], j.u_head[k], j.u_w[k]);
+        int32_t status = 0;
+        const bc_status st = run_check(ctx, g, g->dev, false, &status);
+        if (st) return st;
+    }
+    return BC_OK;
+}
+
+// Static pass on the GPU from the mirror's arcs: distances, E*, counts,
+// dependencies and BC (Alg 7 with the DAG taken from E*, Alg 6 steps 2-8).
 // The distance search relaxes a set of arcs that contains E*; every
 // shortest path lies in E* and any such set gives the same distances, DAGs,
 // counts and BC (Section 6):
@@ -1152,6 +1232,7 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
     if (m > g->arc_cap) return fail(ctx, BC_ERR_CAPACITY, "arc capacity exceeded");
     const bool checked = !over_estar && !ctx->full_search && use_checked_search(n, m);
     HIPCHK(hipMemsetAsync(g->P.ctl, 0, sizeof(GraphCtl), ctx->stream));
+    HIPCHK(hipMemsetAsync(g->chk, 0, sizeof(CheckRec), ctx->stream));
     HIPCHK(hipMemsetAsync(g->P.bc_delta, 0, 8 * (size_t)n, ctx->stream));
     std::vector<UpdateJob> jobs(1, job_template(g));
     LaunchShape L;
@@ -1257,6 +1338,10 @@ bc_status static_pass(bc_ctx *ctx, GraphRec *g, bool over_estar = false) {
     int32_t status = 0;
     if ((st = read_status(ctx, g, &status))) return st;
     if (status) return fail(ctx, sticky_to_status(status), "static pass failed");
+    if (ctx->check) {
+        g->dev = g->mirror;
+        return run_check(ctx, g, g->dev, true, &status);
+    }
     return BC_OK;
 }
 
@@ -1414,6 +1499,7 @@ const char *bc_status_string(bc_status s) {
         case BC_ERR_HIP: return "HIP runtime error";
         case BC_ERR_NO_DEVICE: return "no gfx950 device";
         case BC_ERR_ESTAR_CAPACITY: return "E* capacity exceeded";
+        case BC_ERR_CHECK_FAILED: return "state check failed";
         default: return "unknown status";
     }
 }
@@ -1498,6 +1584,7 @@ bc_status bc_create(bc_ctx **out, const bc_config *cfg) {
     read_tune_cache(ctx);
     ctx->timing = (cfg->flags & BC_FLAG_TIMING) != 0;
     ctx->full_search = (cfg->flags & BC_FLAG_FULL_SEARCH) != 0;
+    ctx->check = (cfg->flags & BC_FLAG_CHECK) != 0;
     {
         // the row kernel is persistent: as many workgroups as stay resident
         int per_cu = 0;
@@ -1792,7 +1879,7 @@ bc_status bc_load_graph(bc_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
     for (int32_t a = 0; a < n; ++a) mr.ptr[a + 1] += mr.ptr[a];
     mr.arcs = (int64_t)keyed.size();
     size_t total = 0;
-    g->P = carve((char *)arena, n, arc_capacity, estar_capacity, &total);
+    g->P = carve((char *)arena, n, arc_capacity, estar_capacity, &total, &g->chk);
     g->P.directed = g->directed;
     g->live = true;
     ctx->n_layout = std::max(ctx->n_layout, n);  // the static pass below re-zeroes every slot
@@ -1829,7 +1916,7 @@ bc_status bc_clone_graph(bc_ctx *ctx, bc_graph_id gid, void *arena, uint64_t are
     g->arena = (char *)arena;
     g->arena_bytes = arena_bytes;
     size_t total = 0;
-    g->P = carve((char *)arena, g->n, g->arc_cap, g->es_cap, &total);
+    g->P = carve((char *)arena, g->n, g->arc_cap, g->es_cap, &total, &g->chk);
     g->P.directed = g->directed;
     ctx->graphs.push_back(g);
     ctx->in_use += arena_bytes;
@@ -1848,6 +1935,7 @@ bc_status bc_free_graph(bc_ctx *ctx, bc_graph_id gid) {
     g->live = false;
     ctx->in_use -= g->arena_bytes;
     g->mirror = Mirror();
+    g->dev = Mirror();
     return BC_OK;
 }
 
@@ -2126,6 +2214,20 @@ bc_status bc_recompute_estar(bc_ctx *ctx, bc_graph_id gid) {
     return static_pass(ctx, g, true);
 }
 
+bc_status bc_check(bc_ctx *ctx, bc_graph_id gid) {
+    GraphRec *g = get_graph(ctx, gid);
+    if (!g) return fail(ctx, BC_ERR_INVALID_ARG, "no such graph");
+    {
+        const bc_status fq = flush_queues(ctx);
+        if (fq) return fq;
+    }
+    // every request validated so far is launched: the mirror is the device's arc set
+    int32_t status = 0;
+    const bc_status st = run_check(ctx, g, g->mirror, true, &status);
+    if (st) return st;
+    return status ? fail(ctx, sticky_to_status(status), "graph carries a sticky error") : BC_OK;
+}
+
 bc_status bc_get_rows(bc_ctx *ctx, bc_graph_id gid, int32_t s0, int32_t cnt, int64_t *D, uint64_t *sigma) {
     GraphRec *g = get_graph(ctx, gid);
     if (!g || s0 < 0 || cnt < 0 || s0 + (int64_t)cnt > g->n) return fail(ctx, BC_ERR_INVALID_ARG, "bad row range");
@@ -2311,6 +2413,14 @@ bc_status bc_get_stats(bc_ctx *ctx, bc_graph_id gid, bc_update_stats *out) {
     out->total_scan_bytes = (int64_t)c.scan_bytes_total;
     out->search_arcs = g->search_arcs;
     out->search_rounds = g->search_rounds;
+    CheckRec r{};
+    HIPCHK(hipMemcpyAsync(&r, g->chk, sizeof r, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    out->check_rows = (int64_t)r.rows;
+    out->check_failures = (int64_t)r.fails;
+    out->check_source = r.fails ? r.s : -1;
+    out->check_target = r.fails ? r.t : -1;
+    out->check_kind = r.fails ? r.kind : 0;
     return BC_OK;
 }
 

@@ -113,3 +113,27 @@ def test_checkpoint_file_holds_plain_arrays(lib_built, tmp_path):
     g = ld.g
     assert g.n == 6 and g.directed is False and g.m == 3
     assert np.array_equal(g.src, arcs.src) and np.array_equal(g.dst, arcs.dst) and np.array_equal(g.w, arcs.w)
+
+
+def _header_defines(prefix):
+    text = open(HEADER).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(rf"#define ({prefix}\w+)\s+(-?\d+)", text)}
+
+
+def test_binding_constants_match_the_header(lib_built):
+    """Status codes, config flags, check kinds and the stats struct's fields
+    of the binding are the header's."""
+    from paper_1311_2147_amd import bcinc
+
+    text = open(HEADER).read()
+    codes = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(BC_(?:OK|ERR_\w+))\s*=\s*(-?\d+)", text)}
+    assert codes == {name: code for code, name in bcinc.STATUS_NAMES.items()}
+    flags = _header_defines("BC_FLAG_")
+    assert flags == {"BC_FLAG_TIMING": bcinc.BC_FLAG_TIMING, "BC_FLAG_FULL_SEARCH": bcinc.BC_FLAG_FULL_SEARCH,
+                     "BC_FLAG_CHECK": bcinc.BC_FLAG_CHECK}
+    kinds = _header_defines("BC_CHECK_")
+    assert {v: k[len("BC_CHECK_"):].lower() for k, v in kinds.items()} == bcinc.CHECK_KINDS
+    body = text[:text.index("} bc_update_stats;")].rsplit("typedef struct {", 1)[1]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"int64_t\s+(\w+);", body)
+    assert fields == [f for f, _ in bcinc.bc_update_stats._fields_]

@@ -14,6 +14,8 @@ an index: nothing reads a path count or a predecessor as an address here.
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -221,4 +223,77 @@ def test_check_mode_stops_the_update_that_meets_a_broken_row():
     g2 = W.Graph(g.n, True, np.append(g.src, np.int32(u)), np.append(g.dst, np.int32(v)),
                  np.append(g.w, np.int64(1)))
     check_full(gr, g2, "recovered with the arc")
+    ctx.close()
+
+
+def test_check_mode_through_full_size_streams():
+    """Every step of three workloads checked on the device, which covers every
+    affected source's row, stored predecessors and E* at each step (the oracle
+    comparisons elsewhere sample them): the out-degree-8 stream at n = 4096
+    (256 edge updates), vertex updates of 32 edges on a complete graph, and
+    eight graphs of both kinds advanced together, one batched submit per
+    step.  BC, which the check leaves out, is compared with the oracle at the
+    end of each."""
+    ctx = make_ctx(4096, check=True)
+    g, ups = W.config2()
+    say(f"check: {g.name} m={g.m}, {len(ups)} updates")
+    gr = ctx.load_graph(g)
+    cur = g
+    for i, up in enumerate(ups):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        if i % 64 == 63:
+            say(f"check: {g.name} update {i} |A|={gr.stats()['affected_sources']}")
+    st = assert_clean(gr, g.name)
+    assert st["check_rows"] == g.n + st["total_affected"]
+    check_full(gr, cur, f"{g.name} under the check")
+    gr.free()
+
+    g3, ups3 = W.config3(n=512, n_updates=24, k=32)
+    say(f"check: {g3.name}, {len(ups3)} vertex updates")
+    gr3 = ctx.load_graph(g3)
+    cur3 = g3
+    for up in ups3:
+        gr3.update(up)
+        cur3 = W.apply_update(cur3, up)
+    st = assert_clean(gr3, g3.name)
+    assert st["check_rows"] == g3.n + st["total_affected"]
+    check_full(gr3, cur3, f"{g3.name} under the check", dags=(ups3[-1].v,))
+
+    work = W.config4(count=8, n_updates=8, lo=256, hi=1024)
+    say(f"check: eight graphs {[g4.n for g4, _ in work]}, 8 updates each, one submit per step")
+    grs = [ctx.load_graph(g4) for g4, _ in work]
+    curs = [g4 for g4, _ in work]
+    for k in range(8):
+        reqs = [(grs[i], work[i][1][k]) for i in range(len(work)) if k < len(work[i][1])]
+        ctx.wait(ctx.submit(reqs))
+        for i in range(len(work)):
+            if k < len(work[i][1]):
+                curs[i] = W.apply_update(curs[i], work[i][1][k])
+    for i, (g4, _) in enumerate(work):
+        st = assert_clean(grs[i], g4.name)
+        assert st["check_rows"] == g4.n + st["total_affected"]
+        check_full(grs[i], curs[i], f"{g4.name} under the check")
+    ctx.close()
+
+
+@pytest.mark.slow
+def test_check_mode_complete_graph_full_size():
+    """The complete-graph workload at n = 2048 under the check: vertex
+    updates of 32 edges, every step's affected sources checked over all n^2
+    arcs, then BC and the whole state against the oracle."""
+    g, ups = W.config3()
+    ctx = make_ctx(g.n, check=True)
+    t0 = time.time()
+    gr = ctx.load_graph(g)
+    say(f"check: {g.name} loaded and checked in {time.time() - t0:.1f} s")
+    cur = g
+    for i, up in enumerate(ups):
+        t0 = time.time()
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        say(f"check: {g.name} vertex update {i} |A|={gr.stats()['affected_sources']} in {time.time() - t0:.1f} s")
+    st = assert_clean(gr, g.name)
+    assert st["check_rows"] == g.n + st["total_affected"]
+    check_full(gr, cur, f"{g.name} under the check", dags=(ups[-1].v,))
     ctx.close()

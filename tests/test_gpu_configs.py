@@ -6,6 +6,8 @@ seconds).  Sizes are chosen to span several workgroup tiles with ragged tails.
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 import pytest
 
@@ -204,4 +206,10 @@ def test_chunglu_sampled(n):
         fa, fb, fw = fresh.estar()
         assert set(zip(a.tolist(), b.tolist(), w.tolist())) == set(zip(fa.tolist(), fb.tolist(), fw.tolist()))
         fresh.free()
+    # every pair of the final state against the definitions (bc_check: no
+    # arc shortens a distance, counts are sums over the Eq.1 in-arcs, stored
+    # predecessors, E* the tight arcs)
+    t0 = time.time()
+    gr.check()
+    say(f"[c5 n={n}] state check of all {n} sources passed in {time.time() - t0:.1f} s")
     ctx.close()

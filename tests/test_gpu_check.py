@@ -297,3 +297,31 @@ def test_check_mode_complete_graph_full_size():
     assert st["check_rows"] == g.n + st["total_affected"]
     check_full(gr, cur, f"{g.name} under the check", dags=(ups[-1].v,))
     ctx.close()
+
+
+def test_check_degenerate_graphs_and_bad_ids():
+    """One vertex, no arcs (every pair but (s,s) unreachable), a graph that
+    becomes connected by insertions, and a freed graph's id."""
+    bcinc = _bc()
+    ctx = make_ctx(64, slots=8, check=True)
+    empty = lambda n, directed: W.Graph(n, directed, np.zeros(0, np.int32), np.zeros(0, np.int32),  # noqa: E731
+                                        np.zeros(0, np.int64))
+    one = ctx.load_graph(empty(1, True))
+    one.check()
+    assert_clean(one, "one vertex")
+    g = empty(9, False)
+    gr = ctx.load_graph(g)
+    gr.check()
+    cur = g
+    for i in range(8):
+        up = W.Update("edge", u=i, v=i + 1, w=1 + i % 3, insert=True)
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+    st = assert_clean(gr, "path by insertions")
+    assert st["check_rows"] == g.n + st["total_affected"]
+    check_full(gr, cur, "path by insertions")
+    gr.free()
+    with pytest.raises(bcinc.BcError) as e:
+        gr.check()
+    assert e.value.code == -1
+    ctx.close()

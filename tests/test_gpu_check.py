@@ -318,7 +318,7 @@ def test_check_degenerate_graphs_and_bad_ids():
         gr.update(up)
         cur = W.apply_update(cur, up)
     st = assert_clean(gr, "path by insertions")
-    assert st["check_rows"] == g.n + st["total_affected"]
+    assert st["check_rows"] == 2 * g.n + st["total_affected"]  # the load, bc_check, then each update
     check_full(gr, cur, "path by insertions")
     gr.free()
     with pytest.raises(bcinc.BcError) as e:

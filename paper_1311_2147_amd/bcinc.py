@@ -241,7 +241,10 @@ class Context:
     @staticmethod
     def _requests(requests):
         """bc_request array of [(graph, update)]; the edge arrays it points to
-        are returned alongside and must outlive the call."""
+        are returned alongside and must outlive the call.  A Batch is passed
+        through as it was marshalled."""
+        if isinstance(requests, Batch):
+            return requests.reqs, requests.keep
         reqs = (bc_request * len(requests))()
         keep = []
         for i, (gr, up) in enumerate(requests):
@@ -267,8 +270,15 @@ class Context:
         del ws, keep
         return {f: getattr(out, f) for f in SCHEDULE_FIELDS}
 
+    def batch(self, requests) -> "Batch":
+        """[(graph, update)] marshalled once into the request array that
+        submit and enqueue take (reusable; the graphs must stay resident)."""
+        reqs, keep = self._requests(requests)
+        return Batch(reqs, keep, len(requests))
+
     def submit(self, requests) -> int:
-        """bc_submit of [(graph, update)] where update has kind/u/v/w/edges."""
+        """bc_submit of [(graph, update)] where update has kind/u/v/w/edges,
+        or of a Batch."""
         reqs, keep = self._requests(requests)
         ticket = ctypes.c_uint64()
         bad = ctypes.c_int32(-1)
@@ -338,6 +348,16 @@ class Context:
         self._check(_lib.bc_set_schedule(self.h, ctypes.byref(s)), "bc_set_schedule")
 
 
+class Batch:
+    """Requests already marshalled for bc_submit / bc_enqueue (Context.batch)."""
+
+    def __init__(self, reqs, keep, count: int):
+        self.reqs, self.keep, self.count = reqs, keep, count
+
+    def __len__(self) -> int:
+        return self.count
+
+
 class Arcs:
     """A graph's arcs as load_graph takes them (n, directed, src, dst, w)."""
 
@@ -383,6 +403,17 @@ class Graph:
             self.update_edge(up.u, up.v, up.w)
         else:
             self.update_vertex(up.v, up.edges)
+
+    def prepare(self, up):
+        """The update's bc_update_edge / bc_update_vertex call with its
+        arguments marshalled once: returns a function of no arguments."""
+        h, gid, chk = self.ctx.h, self.gid, self.ctx._check
+        if up.kind == "edge":
+            u, v, w = up.u, up.v, up.w
+            return lambda: chk(_lib.bc_update_edge(h, gid, u, v, w), "bc_update_edge")
+        arr = (bc_edge * len(up.edges))(*[bc_edge(a, b, w) for a, b, w in up.edges])
+        v, k = up.v, len(up.edges)
+        return lambda: chk(_lib.bc_update_vertex(h, gid, v, k, arr), "bc_update_vertex")
 
     def scores(self) -> np.ndarray:
         out = np.empty(self.n, dtype=np.float64)

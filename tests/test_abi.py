@@ -137,3 +137,23 @@ def test_binding_constants_match_the_header(lib_built):
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"int64_t\s+(\w+);", body)
     assert fields == [f for f, _ in bcinc.bc_update_stats._fields_]
+
+
+def test_requests_marshal_once_into_a_batch(lib_built):
+    """Context._requests fills bc_request entries (edge: kind 0 with u, v, w;
+    vertex: kind 1 with v and its edge array) and passes a Batch through
+    untouched, so a batch marshalled before a timed region is not redone."""
+    from paper_1311_2147_amd import bcinc
+    from paper_1311_2147_amd import workloads as W
+
+    class G:
+        gid = 3
+
+    ups = [W.Update("edge", u=1, v=2, w=7), W.Update("vertex", v=4, edges=[(4, 5, 2), (6, 4, 9)])]
+    reqs, keep = bcinc.Context._requests([(G(), up) for up in ups])
+    assert (reqs[0].graph, reqs[0].kind, reqs[0].u, reqs[0].v, reqs[0].w) == (3, 0, 1, 2, 7)
+    assert (reqs[1].graph, reqs[1].kind, reqs[1].v, reqs[1].k) == (3, 1, 4, 2)
+    assert [(reqs[1].edges[i].a, reqs[1].edges[i].b, reqs[1].edges[i].w) for i in range(2)] == [(4, 5, 2), (6, 4, 9)]
+    batch = bcinc.Batch(reqs, keep, len(ups))
+    again, kept = bcinc.Context._requests(batch)
+    assert again is reqs and kept is keep and len(batch) == 2

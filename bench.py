@@ -37,7 +37,8 @@ Besides the headline the run measures:
   * the multi-core CPU incremental comparator on a short sample;
   * the CPU oracle (from-scratch Brandes): one complete BC recompute of the
     n = 32768 graph on all host cores, and a one-core figure on a sample.
-Prints one JSON line.
+Prints one JSON line, which also names the system (GPU, ROCm and HIP
+versions, host CPU and threads, the GPU clocks rocm-smi reports).
 """
 from __future__ import annotations
 
@@ -49,6 +50,7 @@ import json
 import os
 import platform
 import re
+import subprocess
 import sys
 import time
 
@@ -117,6 +119,31 @@ def cpu_model():
     except OSError:
         pass
     return platform.processor() or "unknown"
+
+
+def system_info():
+    """Where the run happened: the GPU, the runtime versions, the host CPU and
+    the clocks rocm-smi reports (read after the timed work; None where a
+    figure is not available)."""
+    import torch
+
+    p = torch.cuda.get_device_properties(0)
+    info = {"gpu": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "hbm_gib": round(p.total_memory / 2**30, 1), "hip": torch.version.hip, "torch": torch.__version__,
+            "rocm": None, "cpu": cpu_model(), "host_threads": len(os.sched_getaffinity(0)), "clocks": None}
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            info["rocm"] = f.read().strip()
+    except OSError:
+        pass
+    try:
+        res = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
+        cards = json.loads(res.stdout)
+        info["clocks"] = {k.rstrip(":"): v for card in cards.values() if isinstance(card, dict)
+                          for k, v in card.items() if "clk" in k.lower()}
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
 
 
 def main():
@@ -740,6 +767,7 @@ def main():
             "step_avg_ms": window_timing["step_ms"] / launches,
         },
         "cpu_baseline": cpu,
+        "system": system_info(),
     }
     print(json.dumps(line), flush=True)
     ctx.close()

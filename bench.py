@@ -38,7 +38,7 @@ Besides the headline the run measures:
   * the CPU oracle (from-scratch Brandes): one complete BC recompute of the
     n = 32768 graph on all host cores, and a one-core figure on a sample.
 Prints one JSON line, which also names the system (GPU, ROCm and HIP
-versions, host CPU and threads, the GPU clocks rocm-smi reports).
+versions, host CPU and threads, the GPU clocks rocm-smi reports once idle).
 """
 from __future__ import annotations
 
@@ -123,14 +123,15 @@ def cpu_model():
 
 def system_info():
     """Where the run happened: the GPU, the runtime versions, the host CPU and
-    the clocks rocm-smi reports (read after the timed work; None where a
-    figure is not available)."""
+    the clocks rocm-smi reports once the work is done (the idle power state,
+    not the clocks under load; None where a figure is not available)."""
     import torch
 
     p = torch.cuda.get_device_properties(0)
     info = {"gpu": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
             "hbm_gib": round(p.total_memory / 2**30, 1), "hip": torch.version.hip, "torch": torch.__version__,
-            "rocm": None, "cpu": cpu_model(), "host_threads": len(os.sched_getaffinity(0)), "clocks": None}
+            "rocm": None, "cpu": cpu_model(), "host_threads": len(os.sched_getaffinity(0)),
+            "clocks_idle_after_run": None}
     try:
         with open("/opt/rocm/.info/version") as f:
             info["rocm"] = f.read().strip()
@@ -139,7 +140,7 @@ def system_info():
     try:
         res = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
         cards = json.loads(res.stdout)
-        info["clocks"] = {k.rstrip(":"): v for card in cards.values() if isinstance(card, dict)
+        info["clocks_idle_after_run"] = {k.rstrip(":"): v for card in cards.values() if isinstance(card, dict)
                           for k, v in card.items() if "clk" in k.lower()}
     except (OSError, ValueError, subprocess.SubprocessError):
         pass

@@ -408,12 +408,14 @@ bc_status bc_get_schedule(bc_ctx *ctx, bc_schedule *out);
 
 /* Autotuner of the launch schedule.  reqs[0..cnt) is a sample of requests
  * in bc_submit form on resident graphs (typically updates like the expected
- * stream, drawn for tuning).  The sample is split by size bucket of its
- * graphs (ceil(log2 n)); a bucket that already has a schedule, from an
- * earlier tuning or from the cache file, keeps it and runs nothing.  For the
- * others, each candidate schedule (table 128 or 256; block 256, 128 or 64,
- * the last one wave per source; wide_block 512 or 1024; big_b 512 or 1024;
- * the other fields as set) runs the bucket's sample on fresh device clones
+ * stream, drawn for tuning).  Schedules are kept per size bucket
+ * (ceil(log2 n)) and a step takes the one of its largest graph's bucket, so
+ * bucket B is tuned on the sample's requests on graphs of bucket B and below
+ * (steps like the ones it will serve); a bucket that already has a schedule,
+ * from an earlier tuning or from the cache file, keeps it and runs nothing.
+ * For the others, each candidate schedule (table 128 or 256; block 256, 128
+ * or 64, the last one wave per source; wide_block 512 or 1024; big_b 512 or
+ * 1024; the other fields as set) runs that sample on fresh device clones
  * of its graphs, twice (the first run also captures the step graphs), and
  * the summed device time of the second run's steps ranks it.  Afterwards
  * every step takes the schedule of its bucket (the size of its largest

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <mutex>
 #include <tuple>
 #include <string>
@@ -1666,10 +1667,16 @@ bc_status bc_autotune(bc_ctx *ctx, int32_t cnt, const bc_request *reqs, void *wo
     if (workspace_bytes < need) return fail(ctx, BC_ERR_CAPACITY, "autotune workspace below the sampled graphs' bytes");
     bc_schedule start;
     bc_get_schedule(ctx, &start);
-    // the sample's requests by size bucket of their graph; a bucket with a
-    // schedule from the cache or an earlier tuning is not tuned again
+    // a step takes the schedule of its largest graph's size bucket, so
+    // bucket B is tuned on steps like the ones it serves: the sample's
+    // requests on graphs of bucket B and below, in sample order (a bucket
+    // with a schedule from the cache or an earlier tuning is not tuned again)
+    std::set<int> sampled;
+    for (int32_t i = 0; i < cnt; ++i) sampled.insert(n_bucket(ctx->graphs[reqs[i].graph]->n));
     std::map<int, std::vector<bc_request>> by_bucket;
-    for (int32_t i = 0; i < cnt; ++i) by_bucket[n_bucket(ctx->graphs[reqs[i].graph]->n)].push_back(reqs[i]);
+    for (const int b : sampled)
+        for (int32_t i = 0; i < cnt; ++i)
+            if (n_bucket(ctx->graphs[reqs[i].graph]->n) <= b) by_bucket[b].push_back(reqs[i]);
     const bool timing0 = ctx->timing;
     bc_status st = BC_OK;
     HIPCHK(hipStreamSynchronize(ctx->stream));

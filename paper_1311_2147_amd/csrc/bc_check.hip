@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) k_check_rows(const GraphPtrs G, CheckRec 
     GraphCtl *const ctl = G.ctl;
     if (*(volatile int32_t *)&ctl->status != 0) return;  // no valid state to check
     const int32_t n = G.n;
-    const int64_t ns = all ? (int64_t)n : (int64_t)ctl->affected_last;
+    const int64_t ns = all ? (int64_t)n : min((int64_t)ctl->affected_last, (int64_t)n);  // alist holds n
     const int64_t chunks = ((int64_t)n + blockDim.x - 1) / blockDim.x;
     for (int64_t it = blockIdx.x; it < ns * chunks; it += gridDim.x) {
         const int64_t si = it / chunks;

@@ -157,3 +157,11 @@ def test_requests_marshal_once_into_a_batch(lib_built):
     batch = bcinc.Batch(reqs, keep, len(ups))
     again, kept = bcinc.Context._requests(batch)
     assert again is reqs and kept is keep and len(batch) == 2
+
+
+def test_check_kinds_of_the_kernels_are_the_headers():
+    """The device's CK_* kinds (bc_check.hip) carry the public BC_CHECK_* values."""
+    src = open(os.path.join(ROOT, "paper_1311_2147_amd", "csrc", "bc_check.hip")).read()
+    device = {m.group(1): int(m.group(2)) for m in re.finditer(r"\bCK_(\w+)\s*=\s*(\d+)", src)}
+    public = {k[len("BC_CHECK_"):]: v for k, v in _header_defines("BC_CHECK_").items()}
+    assert device == public

@@ -325,3 +325,26 @@ def test_check_degenerate_graphs_and_bad_ids():
         gr.check()
     assert e.value.code == -1
     ctx.close()
+
+
+def test_check_mode_autotuner_clones():
+    """The autotuner's runs on device clones take the same checked steps (its
+    clones carry the arc copy the checks advance); the resident graph is
+    left as it was and then updates under the tuned schedule, checked."""
+    ctx = make_ctx(1024, slots=16, check=True)
+    g = W.random_small(300, 0.02, 20, seed=91, directed=True)
+    gr = ctx.load_graph(g)
+    h0 = gr.state_hash()
+    sample = [(gr, up) for up in W.mixed_stream(g, 6, 20, 92, 0.35, 0.35, 6)]
+    say(f"check: autotune over {len(sample)} sample updates on clones of n={g.n}")
+    ctx.autotune(sample)
+    assert gr.state_hash() == h0, "the autotuner changed the resident graph"
+    assert_clean(gr, "after tuning")
+    cur = g
+    for up in W.mixed_stream(g, 8, 20, 93, 0.35, 0.35, 6):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+    st = assert_clean(gr, "tuned updates")
+    assert st["check_rows"] == g.n + st["total_affected"]
+    check_full(gr, cur, "tuned updates under the check")
+    ctx.close()

@@ -20,6 +20,9 @@ Besides the headline the run measures:
     before the timed window get the same requests one at a time, with the
     library's default schedule, synchronised after each, launched directly
     (no HIP graph, no batching); both legs must reach the same state;
+  * the same with two graphs per step (the two n = 32768 graphs of the
+    served workload), batched and plain, on 300 more updates of graphs 0
+    and 1;
   * the row kernel's achieved HBM bandwidth over the timed window;
   * a full GPU recompute (the static pass) and the recompute over E*;
   * loads of dense graphs (complete, weights up to n^2) by the checked
@@ -154,7 +157,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--graphs", type=int, default=6)
-    ap.add_argument("--legs", default="batched,plain,recompute,loader,single,served,budget,c4,cpuinc,cpu,copy")
+    ap.add_argument("--legs", default="batched,plain,two,recompute,loader,single,served,budget,c4,cpuinc,cpu,copy")
     ap.add_argument("--served-updates", type=int, default=10000, help="updates of the 0.8x served run")
     ap.add_argument("--cpu-updates", type=int, default=12, help="updates of the CPU incremental comparator's sample")
     ap.add_argument("--cpu-one-core-sources", type=int, default=512, help="sources of the one-core oracle sample")
@@ -184,8 +187,11 @@ def main():
     gidx = [i for i in range(4 * G) if sizes[i % 4] == n][:G] if n in sizes else list(range(G))
     graphs = [W.config5_graph(n, gi) for gi in gidx]
     per_graph = Wm + K + 8
-    streams = [W.mixed_stream(g, per_graph, 1000, W.derive_seed(5, 2000 + gi), 0.35, 0.35, 16)
-               for g, gi in zip(graphs, gidx)]
+    # the two-graph leg continues the streams of graphs 0 and 1 (a longer
+    # stream starts with the same updates)
+    two = "two" in legs and G >= 2
+    streams = [W.mixed_stream(g, per_graph + (K if two and i < 2 else 0), 1000, W.derive_seed(5, 2000 + gi),
+                              0.35, 0.35, 16) for i, (g, gi) in enumerate(zip(graphs, gidx))]
     log(f"generated {G} graphs n={n} m={graphs[0].m} and {per_graph} updates each in {time.perf_counter() - t:.1f}s")
     cursor = [0] * G
 
@@ -300,6 +306,44 @@ def main():
         for tw in twins:
             tw.free()
         del twins
+        torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- two graphs
+    # The same measurement with two graphs per step (the two n = 32768 graphs
+    # of the served workload): graphs 0 and 1 continue their streams for K
+    # more steps, batched, and device clones taken before get the same
+    # updates one at a time (default schedule, synchronised after each).
+    if two:
+        pair = grs[:2]
+        twins2 = [gr.clone() for gr in pair]
+        reqs2 = [(pair[i], take(i)) for _ in range(K) for i in range(2)]
+        batch2 = ctx.batch(reqs2)
+        calls2 = [twins2[pair.index(gr)].prepare(up) for gr, up in reqs2]
+        ctx.sync()
+        torch.cuda.synchronize()
+        with quiet_gc():
+            t0 = time.perf_counter()
+            ctx.wait(ctx.submit(batch2))
+            torch.cuda.synchronize()
+            two_b = len(reqs2) / (time.perf_counter() - t0)
+        ctx.set_schedule(**default_sched)
+        torch.cuda.synchronize()
+        with quiet_gc():
+            t0 = time.perf_counter()
+            for call in calls2:
+                call()
+                ctx.sync()
+            two_p = len(reqs2) / (time.perf_counter() - t0)
+        ctx.set_schedule(**tuned)
+        two_same = all(twins2[i].state_hash() == pair[i].state_hash() for i in range(2))
+        comparators["two_graphs"] = {"updates": len(reqs2), "batched_updates_per_s": two_b,
+                                     "plain_updates_per_s": two_p, "batched_over_plain": two_b / two_p,
+                                     "same_state": two_same}
+        log(f"two graphs per step ({len(reqs2)} more updates on graphs 0 and 1): batched {two_b:.1f} updates/s, "
+            f"plain {two_p:.1f} updates/s, batched/plain {two_b / two_p:.3f}, same state {two_same}")
+        for tw in twins2:
+            tw.free()
+        del twins2
         torch.cuda.empty_cache()
 
     # ---------------------------------------------------------------- recompute

@@ -348,3 +348,24 @@ def test_check_mode_autotuner_clones():
     assert st["check_rows"] == g.n + st["total_affected"]
     check_full(gr, cur, "tuned updates under the check")
     ctx.close()
+
+
+@pytest.mark.slow
+def test_check_mode_unit_weights():
+    """The tie regime: a unit-weight power-law graph (every arc in E*, most
+    vertices with several DAG in-arcs, the per-source passes in their slots)
+    under the check after every step, then against the oracle."""
+    g = W.chung_lu_directed(4096, 2.5, 16.0, 1, W.derive_seed(5, 0, 77), "cl-unit-4096")
+    ups = W.mixed_stream(g, 16, 1, 78, 0.5, 0.0, 16)
+    ctx = make_ctx(g.n, check=True)
+    gr = ctx.load_graph(g)
+    cur = g
+    for i, up in enumerate(ups):
+        gr.update(up)
+        cur = W.apply_update(cur, up)
+        if i % 4 == 3:
+            say(f"check: unit weights, update {i} |A|={gr.stats()['affected_sources']}")
+    st = assert_clean(gr, "unit weights")
+    assert st["check_rows"] == g.n + st["total_affected"]
+    check_full(gr, cur, "unit weights under the check")
+    ctx.close()

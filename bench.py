@@ -30,6 +30,9 @@ Besides the headline the run measures:
   * a dedicated 1000-update stream on one freshly loaded graph;
   * the 64-graph batched workload (n from 256 to 4096), batched against the
     plain path on clones;
+  * the out-degree-8 stream at n = 4096 and the complete graph's vertex
+    updates at n = 2048, one update per step and one at a time, beside the
+    oracle's time per update;
   * the served workload at full shape: 8 resident Chung-Lu graphs (n = 4096,
     8192, 16384, 32768, two of each), a closed loop for the saturation rate
     (and the plain path on its requests, on clones), and Poisson streams over
@@ -157,7 +160,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--graphs", type=int, default=6)
-    ap.add_argument("--legs", default="batched,plain,two,recompute,loader,single,served,budget,c4,cpuinc,cpu,copy")
+    ap.add_argument("--legs",
+                    default="batched,plain,two,recompute,loader,single,served,budget,c4,c2c3,cpuinc,cpu,copy")
     ap.add_argument("--served-updates", type=int, default=10000, help="updates of the 0.8x served run")
     ap.add_argument("--cpu-updates", type=int, default=12, help="updates of the CPU incremental comparator's sample")
     ap.add_argument("--cpu-one-core-sources", type=int, default=512, help="sources of the one-core oracle sample")
@@ -719,6 +723,62 @@ def main():
         del c4_twins, c4g
         torch.cuda.empty_cache()
 
+    # ------------------------------------------------------------ C2 and C3
+    # The out-degree-8 stream at n = 4096 (256 arc updates) and the complete
+    # graph at n = 2048 (64 vertex updates of 32 edges each): one graph each,
+    # so its stream runs one update per step (bc_submit of the whole stream,
+    # under the autotuner's schedule for the graph's size bucket, tuned on a
+    # separately drawn sample unless a bucket has one) and, on a device clone,
+    # one update at a time (default schedule, synchronised after each); both
+    # must end in the same state.  The CPU leg times the oracle on the final
+    # graphs.
+    small_finals = []
+    if "c2c3" in legs:
+        small = {}
+        for name, (g, ups) in (("out-degree-8 n=4096, 256 arc updates", W.config2()),
+                               ("complete n=2048, 64 vertex updates of 32 edges", W.config3())):
+            gr = ctx.load_graph(g)
+            if g.directed:
+                tsample = W.edge_stream(g, 4, 4, 100, W.derive_seed(2, 9000))
+            else:
+                tsample = W.vertex_stream(g, 4, 32, g.n * g.n, W.derive_seed(3, 9000))
+            ctx.autotune([(gr, up) for up in tsample])
+            tw = gr.clone()
+            sb = ctx.batch([(gr, up) for up in ups])
+            calls = [tw.prepare(up) for up in ups]
+            ctx.sync()
+            torch.cuda.synchronize()
+            with quiet_gc():
+                t0 = time.perf_counter()
+                ctx.wait(ctx.submit(sb))
+                torch.cuda.synchronize()
+                b_rate = len(ups) / (time.perf_counter() - t0)
+            b_sched = ctx.schedule()
+            ctx.set_schedule(**default_sched)
+            torch.cuda.synchronize()
+            with quiet_gc():
+                t0 = time.perf_counter()
+                for call in calls:
+                    call()
+                    ctx.sync()
+                p_rate = len(ups) / (time.perf_counter() - t0)
+            ctx.set_schedule(**tuned)
+            st = gr.stats()
+            same = gr.state_hash() == tw.state_hash()
+            cur = g
+            for up in ups:
+                cur = W.apply_update(cur, up)
+            small_finals.append((name, cur))
+            small[name] = {"updates": len(ups), "batched_updates_per_s": b_rate, "plain_updates_per_s": p_rate,
+                           "schedule": b_sched, "same_state": same, "affected_per_update": st["total_affected"] / len(ups),
+                           "changed_pairs_per_update": st["total_changed"] / len(ups)}
+            log(f"{name}: batched {b_rate:.0f} updates/s, plain {p_rate:.0f} updates/s, same state {same}, "
+                f"|A| {st['total_affected'] / len(ups):.0f}, schedule {b_sched}")
+            tw.free()
+            gr.free()
+            torch.cuda.empty_cache()
+        comparators["small_configs"] = small
+
     # ------------------------------------------------------------------ copy
     # A plain device-to-device copy of 1 GiB: the achievable HBM bandwidth on
     # this box (read + write bytes over time), and the calibration kernel of
@@ -770,6 +830,27 @@ def main():
                                       f"{one_full:.0f}s per recompute (extrapolated)"}}
         log(f"cpu oracle: complete recompute {full_s:.1f}s on {threads} threads -> {1 / full_s:.4f} updates/s; "
             f"one core {S1} sources in {one_s:.2f}s -> {one_full:.0f}s per recompute (extrapolated)")
+        # the oracle's time per update on the two single-graph workloads: a
+        # from-scratch BC recompute of the final graph on all host cores (every
+        # source for n = 4096; for the complete graph, whose Dijkstra relaxes
+        # n^2 arcs per source, a 128-source sample scaled to n)
+        per_cfg = {}
+        for name, cur in small_finals:
+            if cur.m <= 64 * cur.n:
+                t0 = time.perf_counter()
+                oracle.brandes(cur, rows=False, threads=threads)
+                o_s = time.perf_counter() - t0
+                note = f"complete recompute of all {cur.n} sources"
+            else:
+                S2 = 128
+                t0 = time.perf_counter()
+                oracle.rows(cur, np.linspace(0, cur.n - 1, S2).astype(np.int32), threads=threads)
+                o_s = (time.perf_counter() - t0) * cur.n / S2
+                note = f"{S2} of {cur.n} sources scaled by n/{S2} (extrapolated)"
+            per_cfg[name] = {"s_per_update": o_s, "updates_per_s": 1.0 / o_s, "cores": threads, "sample": note}
+            log(f"cpu oracle, {name}: {o_s:.2f}s per update on {threads} threads ({note})")
+        if per_cfg:
+            cpu["small_configs"] = per_cfg
 
     line = {
         "metric": "BC updates/sec at n=32768 (batched incremental path)",
